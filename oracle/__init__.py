@@ -1,0 +1,220 @@
+"""FP64 CPU oracle for the batched regularised contact solve (test infrastructure).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It never imports the GPU package and the
+GPU package never imports it; the two meet only through the seeded input
+generator.
+
+``oracle.c`` (compiled to ``liboracle.so`` by :func:`build`) holds the
+method: Newton steps with QR solves and an exact sort-and-scan line search
+(Sec. III-B, eqs. 6, 9, 10), the IFT adjoint VJP (Sec. III-C, eq. 17) and
+the unrolled-trace VJP.  ``brute.py`` pins the forward result by active-set
+enumeration; ``fd.py`` pins the gradients by central finite differences.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD = 1, 2, 4, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc (plain -O2, OpenMP across instances)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_i32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+class _Opt:
+    """ndpointer argtype that also accepts None (NULL)."""
+
+    def __init__(self, base):
+        self.base = base
+
+    def from_param(self, obj):
+        if obj is None:
+            return None
+        return self.base.from_param(obj)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        i, d = C.c_int, C.c_double
+        L.oracle_forward.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _Opt(_dp), i, d, _dp, _u8,
+                                     C.POINTER(i), C.POINTER(i), _Opt(_dp), _Opt(_u8), _Opt(_u8)]
+        L.oracle_ift_vjp.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _Opt(_u8), _dp,
+                                     _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
+                                     _Opt(_dp)]
+        L.oracle_unrolled_vjp.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp,
+                                          _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
+                                          C.POINTER(i), C.POINTER(i)]
+        L.oracle_line_search.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u8]
+        L.oracle_line_search.restype = C.c_double
+        L.oracle_max_threads.restype = C.c_int
+        pk = [i, _i32, _i32, _i64, _i64, _i64, _i64]
+        L.oracle_forward_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8, _i32,
+                                                _i32, i]
+        L.oracle_ift_vjp_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, _dp, _Opt(_u8), _dp,
+                                                _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
+                                                _Opt(_dp), i]
+        L.oracle_unrolled_vjp_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp,
+                                                     _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
+                                                     _Opt(_dp), _i32, _i32, i]
+        _lib = L
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+# ---------------------------------------------------------------- one instance
+
+def forward(M, J, a0, aref, D, a_init=None, max_iter=10, tol=1e-10, trace=False):
+    """Solve one instance.  Returns dict(a, active, iters, status[, alphas, A, Ap])."""
+    M, J, a0, aref, D = map(_f64, (M, J, a0, aref, D))
+    n = a0.shape[0]
+    m = aref.shape[0]
+    J = J.reshape(m, n)
+    a = np.empty(n)
+    act = np.empty(m, dtype=np.uint8)
+    it, st = C.c_int(0), C.c_int(0)
+    K = max(max_iter, 0)
+    al = np.zeros(max(K, 1)) if trace else None
+    tA = np.zeros((max(K, 1), max(m, 1)), dtype=np.uint8) if trace else None
+    tAp = np.zeros((max(K, 1), max(m, 1)), dtype=np.uint8) if trace else None
+    lib().oracle_forward(n, m, M, J, a0, aref, D, None if a_init is None else _f64(a_init),
+                         max_iter, tol, a, act, C.byref(it), C.byref(st), al, tA, tAp)
+    out = dict(a=a, active=act.astype(bool), iters=it.value, status=st.value)
+    if trace:
+        k = it.value
+        out.update(alphas=al[:k], A=tA[:k, :m].astype(bool), Ap=tAp[:k, :m].astype(bool))
+    return out
+
+
+def ift_vjp(M, J, a0, aref, D, a, abar, active=None):
+    """IFT VJP at solution ``a`` (eq. 17).  Returns dict of the five cotangents + lambda."""
+    M, J, a0, aref, D, a, abar = map(_f64, (M, J, a0, aref, D, a, abar))
+    n, m = a0.shape[0], aref.shape[0]
+    J = J.reshape(m, n)
+    out = dict(a0=np.empty(n), aref=np.empty(m), J=np.empty((m, n)), D=np.empty(m),
+               M=np.empty((n, n)), lam=np.empty(n))
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    lib().oracle_ift_vjp(n, m, M, J, a0, aref, D, a, act, abar, out["a0"], out["aref"],
+                         out["J"], out["D"], out["M"], out["lam"])
+    return out
+
+
+def unrolled_vjp(M, J, a0, aref, D, abar, K, tol=1e-10):
+    """Gradient of abar . a_K through the executed K-step trace."""
+    M, J, a0, aref, D, abar = map(_f64, (M, J, a0, aref, D, abar))
+    n, m = a0.shape[0], aref.shape[0]
+    J = J.reshape(m, n)
+    out = dict(a=np.empty(n), a0=np.empty(n), aref=np.empty(m), J=np.empty((m, n)),
+               D=np.empty(m), M=np.empty((n, n)))
+    it, st = C.c_int(0), C.c_int(0)
+    lib().oracle_unrolled_vjp(n, m, M, J, a0, aref, D, abar, K, tol, out["a"], out["a0"],
+                              out["aref"], out["J"], out["D"], out["M"], C.byref(it),
+                              C.byref(st))
+    out.update(iters=it.value, status=st.value)
+    return out
+
+
+def line_search(M, J, a0, aref, D, a, p):
+    """Exact line search alone.  Returns (alpha, Ap, q)."""
+    M, J, a0, aref, D, a, p = map(_f64, (M, J, a0, aref, D, a, p))
+    n, m = a0.shape[0], aref.shape[0]
+    J = J.reshape(m, n)
+    q = np.empty(max(m, 1))
+    Ap = np.empty(max(m, 1), dtype=np.uint8)
+    alpha = lib().oracle_line_search(n, m, M, J, a0, aref, D, a, p, q, Ap)
+    return alpha, Ap[:m].astype(bool), q[:m]
+
+
+# ---------------------------------------------------------------- batches
+
+class Packed:
+    """Packed batch description (flat FP64 arrays + element offsets)."""
+
+    def __init__(self, nv, nrows, M, J, a0, aref, D, abar=None):
+        self.nv = np.ascontiguousarray(nv, dtype=np.int32)
+        self.nrows = np.ascontiguousarray(nrows, dtype=np.int32)
+        nv64, nr64 = self.nv.astype(np.int64), self.nrows.astype(np.int64)
+        cs = lambda s: np.concatenate([[0], np.cumsum(s)]).astype(np.int64)
+        self.off_nn, self.off_mn = cs(nv64 * nv64), cs(nv64 * nr64)
+        self.off_n, self.off_m = cs(nv64), cs(nr64)
+        self.M, self.J, self.a0, self.aref, self.D = (_f64(x).ravel() for x in (M, J, a0, aref, D))
+        self.abar = None if abar is None else _f64(abar).ravel()
+        self.B = int(self.nv.shape[0])
+
+    @classmethod
+    def uniform(cls, M, J, a0, aref, D, abar=None):
+        B, m, n = J.shape
+        return cls(np.full(B, n), np.full(B, m), M, J, a0, aref, D, abar)
+
+    def _pk(self):
+        return (self.B, self.nv, self.nrows, self.off_nn, self.off_mn, self.off_n, self.off_m)
+
+    def _buf(self, key):
+        size = {"n": self.off_n[-1], "m": self.off_m[-1], "mn": self.off_mn[-1],
+                "nn": self.off_nn[-1]}[key]
+        return np.zeros(max(int(size), 1))
+
+    def forward(self, max_iter=10, tol=1e-10, threads=0):
+        a = self._buf("n")
+        act = np.zeros(max(int(self.off_m[-1]), 1), dtype=np.uint8)
+        it = np.zeros(self.B, dtype=np.int32)
+        st = np.zeros(self.B, dtype=np.int32)
+        lib().oracle_forward_batch(*self._pk(), self.M, self.J, self.a0, self.aref, self.D,
+                                   max_iter, tol, a, act, it, st, threads)
+        return dict(a=a, active=act, iters=it, status=st)
+
+    def ift_vjp(self, a, active, abar=None, threads=0, outputs=("a0", "aref", "J", "D", "M")):
+        abar = self.abar if abar is None else _f64(abar).ravel()
+        g = {k: (self._buf({"a0": "n", "aref": "m", "J": "mn", "D": "m", "M": "nn"}[k])
+                 if k in outputs else None) for k in ("a0", "aref", "J", "D", "M")}
+        lib().oracle_ift_vjp_batch(*self._pk(), self.M, self.J, self.a0, self.aref, self.D,
+                                   _f64(a).ravel(),
+                                   None if active is None else np.ascontiguousarray(active, np.uint8),
+                                   abar, g["a0"], g["aref"], g["J"], g["D"], g["M"], threads)
+        return g
+
+    def unrolled_vjp(self, K, tol=1e-10, abar=None, threads=0):
+        abar = self.abar if abar is None else _f64(abar).ravel()
+        a = self._buf("n")
+        g = dict(a0=self._buf("n"), aref=self._buf("m"), J=self._buf("mn"), D=self._buf("m"),
+                 M=self._buf("nn"))
+        it = np.zeros(self.B, dtype=np.int32)
+        st = np.zeros(self.B, dtype=np.int32)
+        lib().oracle_unrolled_vjp_batch(*self._pk(), self.M, self.J, self.a0, self.aref, self.D,
+                                        abar, K, tol, a, g["a0"], g["aref"], g["J"], g["D"],
+                                        g["M"], it, st, threads)
+        g.update(a=a, iters=it, status=st)
+        return g

@@ -1,0 +1,652 @@
+/*
+ * oracle.c -- plain FP64 reference for the batched regularised contact solve,
+ * its implicit-function-theorem VJP and the unrolled-trace VJP.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the two meet only through the
+ * seeded input generator.  Everything here is plain loops in double precision,
+ * one instance at a time (OpenMP only distributes whole instances).
+ *
+ * Problem (paper Sec. III-A, reduced objective eq. 5, with pyramidal rows so
+ * that the regulariser is s(u) = 1/2 sum_i D_i min(u_i, 0)^2):
+ *
+ *   L(a) = 1/2 (a - a0)^T M (a - a0) + 1/2 sum_i D_i min(r_i, 0)^2,
+ *   r    = J a - aref,   A = 1[r < 0],   w = D o A o r.
+ *
+ *   stationarity residual (eq. 6):   F(a) = M (a - a0) + J^T w
+ *   Newton matrix (eq. 9):           H    = M + J^T diag(D o A) J
+ *   Newton step + line search (eq. 10): p = -H^{-1} F, a <- a + alpha p,
+ *       alpha the exact minimiser of phi(alpha) = L(a + alpha p).
+ *   IFT adjoint (eq. 17):  H^T lambda = abar,  theta_bar = -F_theta^T lambda.
+ *
+ * Linear systems are solved with Householder QR (the dense QR the paper uses
+ * for the transposed adjoint solve), never with Cholesky.
+ *
+ * Stopping rule (reading of "tolerance-converged" with a max-iteration cap,
+ * Sec. III-C): iterate a_k is converged when
+ *   ||F(a_k)||_2 <= tol * tr(M)          (gradient scaled by mean inertia * n)
+ * or, for k >= 1, the step that produced it was negligible,
+ *   ||a_k - a_{k-1}||_inf <= tol * (1 + ||a_k||_inf).
+ * At most max_iter steps are taken; the returned active set and residual are
+ * those of the returned iterate.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ST_CONVERGED 1
+#define ST_MAXITER 2
+#define ST_NONFINITE 4
+#define ST_NOTSPD 8
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers (row-major)                                      */
+/* ------------------------------------------------------------------ */
+
+static double dot(int n, const double *x, const double *y) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+/* y = A x, A is rows x cols */
+static void matvec(int rows, int cols, const double *A, const double *x, double *y) {
+    for (int i = 0; i < rows; ++i) y[i] = dot(cols, A + (size_t)i * cols, x);
+}
+
+/* y = A^T x, A is rows x cols */
+static void matvec_t(int rows, int cols, const double *A, const double *x, double *y) {
+    for (int j = 0; j < cols; ++j) y[j] = 0.0;
+    for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < cols; ++j) y[j] += A[(size_t)i * cols + j] * x[i];
+}
+
+static int all_finite(size_t len, const double *x) {
+    for (size_t i = 0; i < len; ++i)
+        if (!isfinite(x[i])) return 0;
+    return 1;
+}
+
+/* Householder QR solve of A x = b (A n x n, row-major, not modified).
+ * Returns 0 on success, -1 if R has a zero pivot. */
+static int qr_solve(int n, const double *A, const double *b, double *x) {
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 0;
+    memcpy(R, A, sizeof(double) * (size_t)n * n);
+    memcpy(y, b, sizeof(double) * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+        /* reflector for column k, rows k..n-1 */
+        double norm = 0.0;
+        for (int i = k; i < n; ++i) norm += R[i * n + k] * R[i * n + k];
+        norm = sqrt(norm);
+        if (norm == 0.0) continue;
+        double alpha = R[k * n + k] > 0 ? -norm : norm;
+        for (int i = 0; i < n; ++i) v[i] = 0.0;
+        v[k] = R[k * n + k] - alpha;
+        for (int i = k + 1; i < n; ++i) v[i] = R[i * n + k];
+        double vv = 0.0;
+        for (int i = k; i < n; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        /* apply I - 2 v v^T / (v^T v) to R (columns k..n-1) and to y */
+        for (int j = k; j < n; ++j) {
+            double s = 0.0;
+            for (int i = k; i < n; ++i) s += v[i] * R[i * n + j];
+            s = 2.0 * s / vv;
+            for (int i = k; i < n; ++i) R[i * n + j] -= s * v[i];
+        }
+        double s = 0.0;
+        for (int i = k; i < n; ++i) s += v[i] * y[i];
+        s = 2.0 * s / vv;
+        for (int i = k; i < n; ++i) y[i] -= s * v[i];
+    }
+    /* back substitution R x = Q^T b */
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int j = i + 1; j < n; ++j) s -= R[i * n + j] * x[j];
+        if (R[i * n + i] == 0.0) { rc = -1; x[i] = NAN; continue; }
+        x[i] = s / R[i * n + i];
+    }
+    free(R); free(y); free(v);
+    return rc;
+}
+
+/* Plain Cholesky attempt, used only to classify M as SPD or not. */
+static int is_spd(int n, const double *M) {
+    double *L = (double *)calloc((size_t)n * n, sizeof(double));
+    int ok = 1;
+    for (int j = 0; j < n && ok; ++j) {
+        double s = M[j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0.0)) { ok = 0; break; }
+        L[j * n + j] = sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double t = M[i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = t / L[j * n + j];
+        }
+    }
+    free(L);
+    return ok;
+}
+
+/* ------------------------------------------------------------------ */
+/* the method's pieces                                                  */
+/* ------------------------------------------------------------------ */
+
+/* r = J a - aref, A = 1[r < 0], F = M (a - a0) + J^T (D o A o r)   (eq. 6) */
+static void eval_residual(int n, int m, const double *M, const double *J, const double *a0,
+                          const double *aref, const double *D, const double *a,
+                          double *r, unsigned char *A, double *F) {
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    matvec(n, n, M, d, F);
+    for (int i = 0; i < m; ++i) {
+        r[i] = dot(n, J + (size_t)i * n, a) - aref[i];
+        A[i] = r[i] < 0.0;
+        if (A[i]) {
+            double w = D[i] * r[i];
+            for (int j = 0; j < n; ++j) F[j] += J[(size_t)i * n + j] * w;
+        }
+    }
+    free(d);
+}
+
+/* H = M + J^T diag(D o A) J   (eq. 9) */
+static void assemble_H(int n, int m, const double *M, const double *J, const double *D,
+                       const unsigned char *A, double *H) {
+    memcpy(H, M, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < m; ++i) {
+        if (!A[i]) continue;
+        const double *Ji = J + (size_t)i * n;
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) H[j * n + k] += D[i] * Ji[j] * Ji[k];
+    }
+}
+
+typedef struct { double t; int i; } bp_t;
+
+static int bp_cmp(const void *x, const void *y) {
+    double a = ((const bp_t *)x)->t, b = ((const bp_t *)y)->t;
+    return (a > b) - (a < b);
+}
+
+/* Exact line search along p from a (eq. 10 with the exact minimiser of
+ * phi(alpha) = L(a + alpha p)).
+ *
+ * phi'(alpha) = alpha p^T M p + p^T M (a - a0) + sum_i D_i q_i min(r_i + alpha q_i, 0),
+ * q = J p, is continuous, piecewise linear and strictly increasing.  Its
+ * breakpoints t_i = -r_i / q_i (t_i > 0) are sorted and the pieces scanned
+ * from alpha = 0+; the first piece that contains its own root -b/c (closed
+ * endpoints) gives alpha.  On return Ap holds the active rows of that piece.
+ */
+static double exact_line_search(int n, int m, const double *M, const double *J,
+                                const double *a0, const double *D, const double *a,
+                                const double *p, const double *r, double *q,
+                                unsigned char *Ap, double *c_out) {
+    double *Mp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    bp_t *bps = (bp_t *)malloc(sizeof(bp_t) * (size_t)(m > 0 ? m : 1));
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    matvec(n, n, M, p, Mp);
+    double c = dot(n, p, Mp);            /* p^T M p */
+    double b = 0.0;                      /* p^T M (a - a0) */
+    {
+        double *Md = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        matvec(n, n, M, d, Md);
+        b = dot(n, p, Md);
+        free(Md);
+    }
+    int nb = 0;
+    for (int i = 0; i < m; ++i) {
+        q[i] = dot(n, J + (size_t)i * n, p);
+        /* piece at alpha = 0+ */
+        Ap[i] = (r[i] < 0.0) || (r[i] == 0.0 && q[i] < 0.0);
+        if (Ap[i]) { c += D[i] * q[i] * q[i]; b += D[i] * q[i] * r[i]; }
+        if (q[i] != 0.0) {
+            double t = -r[i] / q[i];
+            if (t > 0.0) { bps[nb].t = t; bps[nb].i = i; ++nb; }
+        }
+    }
+    qsort(bps, (size_t)nb, sizeof(bp_t), bp_cmp);
+    double alpha = -b / c;
+    int k = 0;
+    while (k < nb) {
+        double t = bps[k].t;
+        alpha = -b / c;
+        if (alpha <= t) break;           /* root lies in the current piece */
+        /* cross every breakpoint equal to t: those rows change activity */
+        while (k < nb && bps[k].t == t) {
+            int i = bps[k].i;
+            double s = Ap[i] ? -1.0 : 1.0;
+            Ap[i] = !Ap[i];
+            c += s * D[i] * q[i] * q[i];
+            b += s * D[i] * q[i] * r[i];
+            ++k;
+        }
+        alpha = -b / c;
+    }
+    if (c_out) *c_out = c;
+    free(Mp); free(d); free(bps);
+    return alpha;
+}
+
+static double inf_norm(int n, const double *x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = fmax(s, fabs(x[i]));
+    return s;
+}
+
+/* step_inf: ||a_k - a_{k-1}||_inf of the step that produced a, or < 0 at k = 0 */
+static int converged(int n, const double *M, const double *F, double step_inf,
+                     const double *a, double tol) {
+    double trM = 0.0;
+    for (int j = 0; j < n; ++j) trM += M[j * n + j];
+    double g = sqrt(dot(n, F, F));
+    if (g <= tol * trM) return 1;
+    if (step_inf >= 0.0 && step_inf <= tol * (1.0 + inf_norm(n, a))) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* one instance                                                         */
+/* ------------------------------------------------------------------ */
+
+/* Forward solve.  a_init may be NULL (start at a0).  Outputs: a (n),
+ * active (m, A at the returned iterate), *iters (steps taken), *status.
+ * Optional trace (may be NULL): alphas[max_iter], trA[max_iter*m] (A_k),
+ * trAp[max_iter*m] (line-search piece A'_k). */
+int oracle_forward(int n, int m, const double *M, const double *J, const double *a0,
+                   const double *aref, const double *D, const double *a_init,
+                   int max_iter, double tol,
+                   double *a, unsigned char *active, int *iters, int *status,
+                   double *alphas, unsigned char *trA, unsigned char *trAp) {
+    size_t nn = (size_t)n * n, mn = (size_t)m * n;
+    *iters = 0;
+    if (!all_finite(nn, M) || !all_finite(mn, J) || !all_finite(n, a0) ||
+        !all_finite(m, aref) || !all_finite(m, D) || (a_init && !all_finite(n, a_init))) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) active[i] = 0;
+        *status = ST_NONFINITE;
+        return 0;
+    }
+    if (!is_spd(n, M)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) active[i] = 0;
+        *status = ST_NOTSPD;
+        return 0;
+    }
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *r = (double *)malloc(sizeof(double) * mm);
+    double *q = (double *)malloc(sizeof(double) * mm);
+    double *F = (double *)malloc(sizeof(double) * n1);
+    double *negF = (double *)malloc(sizeof(double) * n1);
+    double *p = (double *)malloc(sizeof(double) * n1);
+    double *H = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    unsigned char *Ap = (unsigned char *)malloc(mm);
+    for (int j = 0; j < n; ++j) a[j] = a_init ? a_init[j] : a0[j];
+    int st = ST_MAXITER;
+    double step_inf = -1.0;
+    for (int k = 0;; ++k) {
+        eval_residual(n, m, M, J, a0, aref, D, a, r, active, F);
+        if (converged(n, M, F, step_inf, a, tol)) { st = ST_CONVERGED; break; }
+        if (k == max_iter) { st = ST_MAXITER; break; }
+        assemble_H(n, m, M, J, D, active, H);
+        for (int j = 0; j < n; ++j) negF[j] = -F[j];
+        qr_solve(n, H, negF, p);
+        double alpha = exact_line_search(n, m, M, J, a0, D, a, p, r, q, Ap, NULL);
+        if (alphas) alphas[k] = alpha;
+        if (trA) memcpy(trA + (size_t)k * m, active, m);
+        if (trAp) memcpy(trAp + (size_t)k * m, Ap, m);
+        step_inf = 0.0;
+        for (int j = 0; j < n; ++j) {
+            a[j] += alpha * p[j];
+            step_inf = fmax(step_inf, fabs(alpha * p[j]));
+        }
+        *iters = k + 1;
+    }
+    *status = st;
+    free(r); free(q); free(F); free(negF); free(p); free(H); free(Ap);
+    return 0;
+}
+
+/* IFT VJP at the returned solution (eq. 17, pyramidal rows):
+ *   H(A*)^T lambda = abar,  sigma = J lambda,
+ *   a0bar = M^T lambda,  arefbar = D o A* o sigma,  Dbar = -A* o r* o sigma,
+ *   Jbar = -(w* lambda^T + arefbar a*^T),  Mbar = -lambda (a* - a0)^T.
+ * active may be NULL (then A* = 1[r(a) < 0]).  Every output may be NULL.
+ * lambda_out (n) may be NULL. */
+int oracle_ift_vjp(int n, int m, const double *M, const double *J, const double *a0,
+                   const double *aref, const double *D, const double *a,
+                   const unsigned char *active, const double *abar,
+                   double *a0bar, double *arefbar, double *Jbar, double *Dbar, double *Mbar,
+                   double *lambda_out) {
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *r = (double *)malloc(sizeof(double) * mm);
+    double *sig = (double *)malloc(sizeof(double) * mm);
+    double *H = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *Ht = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *lam = (double *)malloc(sizeof(double) * n1);
+    unsigned char *A = (unsigned char *)malloc(mm);
+    for (int i = 0; i < m; ++i) {
+        r[i] = dot(n, J + (size_t)i * n, a) - aref[i];
+        A[i] = active ? active[i] : (r[i] < 0.0);
+    }
+    assemble_H(n, m, M, J, D, A, H);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) Ht[j * n + k] = H[k * n + j];
+    int rc = qr_solve(n, Ht, abar, lam);
+    for (int i = 0; i < m; ++i) sig[i] = dot(n, J + (size_t)i * n, lam);
+    if (a0bar) matvec_t(n, n, M, lam, a0bar);
+    for (int i = 0; i < m; ++i) {
+        double w = A[i] ? D[i] * r[i] : 0.0;
+        double ar = A[i] ? D[i] * sig[i] : 0.0;
+        if (arefbar) arefbar[i] = ar;
+        if (Dbar) Dbar[i] = A[i] ? -r[i] * sig[i] : 0.0;
+        if (Jbar)
+            for (int j = 0; j < n; ++j) Jbar[(size_t)i * n + j] = -(w * lam[j] + ar * a[j]);
+    }
+    if (Mbar)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) Mbar[j * n + k] = -lam[j] * (a[k] - a0[k]);
+    if (lambda_out) memcpy(lambda_out, lam, sizeof(double) * (size_t)n);
+    free(r); free(sig); free(H); free(Ht); free(lam); free(A);
+    return rc;
+}
+
+/* Unrolled VJP: the gradient of abar . a_K through the executed K-step trace.
+ * Steps after the stopping rule fires are the identity (not recorded).  The
+ * line-search step alpha = -b/c is differentiated on its accepted piece A'_k
+ * with A_k and A'_k held fixed (reverse-mode AD of the recorded trace). */
+int oracle_unrolled_vjp(int n, int m, const double *M, const double *J, const double *a0,
+                        const double *aref, const double *D, const double *abar,
+                        int K, double tol, double *a_out,
+                        double *a0bar, double *arefbar, double *Jbar, double *Dbar,
+                        double *Mbar, int *iters, int *status) {
+    size_t nn = (size_t)n * n, mn = (size_t)m * n;
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1, K1 = K > 0 ? K : 1;
+    /* zero every gradient: the sweep accumulates */
+    if (a0bar) memset(a0bar, 0, sizeof(double) * n);
+    if (arefbar) memset(arefbar, 0, sizeof(double) * m);
+    if (Jbar) memset(Jbar, 0, sizeof(double) * mn);
+    if (Dbar) memset(Dbar, 0, sizeof(double) * m);
+    if (Mbar) memset(Mbar, 0, sizeof(double) * nn);
+    *iters = 0;
+    if (!all_finite(nn, M) || !all_finite(mn, J) || !all_finite(n, a0) ||
+        !all_finite(m, aref) || !all_finite(m, D) || !all_finite(n, abar)) {
+        for (int j = 0; j < n; ++j) a_out[j] = NAN;
+        *status = ST_NONFINITE;
+        return 0;
+    }
+    if (!is_spd(n, M)) {
+        for (int j = 0; j < n; ++j) a_out[j] = NAN;
+        *status = ST_NOTSPD;
+        return 0;
+    }
+    /* tape */
+    double *tA = (double *)malloc(sizeof(double) * (size_t)K1 * n1);   /* a_k */
+    double *tP = (double *)malloc(sizeof(double) * (size_t)K1 * n1);   /* p_k */
+    double *tR = (double *)malloc(sizeof(double) * (size_t)K1 * mm);   /* r_k */
+    double *tQ = (double *)malloc(sizeof(double) * (size_t)K1 * mm);   /* q_k */
+    double *tH = (double *)malloc(sizeof(double) * (size_t)K1 * n1 * n1);
+    unsigned char *tAk = (unsigned char *)malloc((size_t)K1 * mm);
+    unsigned char *tAp = (unsigned char *)malloc((size_t)K1 * mm);
+    double *tAlpha = (double *)malloc(sizeof(double) * K1);
+    double *tC = (double *)malloc(sizeof(double) * K1);
+    double *a = (double *)malloc(sizeof(double) * n1);
+    double *F = (double *)malloc(sizeof(double) * n1);
+    double *negF = (double *)malloc(sizeof(double) * n1);
+    double *p = (double *)malloc(sizeof(double) * n1);
+    double *H = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *r = (double *)malloc(sizeof(double) * mm);
+    unsigned char *Ak = (unsigned char *)malloc(mm);
+    for (int j = 0; j < n; ++j) a[j] = a0[j];
+    int steps = 0, st = ST_MAXITER;
+    double step_inf = -1.0;
+    for (int k = 0; k < K; ++k) {
+        eval_residual(n, m, M, J, a0, aref, D, a, r, Ak, F);
+        if (converged(n, M, F, step_inf, a, tol)) { st = ST_CONVERGED; break; }
+        assemble_H(n, m, M, J, D, Ak, H);
+        for (int j = 0; j < n; ++j) negF[j] = -F[j];
+        qr_solve(n, H, negF, p);
+        memcpy(tA + (size_t)k * n, a, sizeof(double) * n);
+        memcpy(tP + (size_t)k * n, p, sizeof(double) * n);
+        memcpy(tR + (size_t)k * m, r, sizeof(double) * m);
+        memcpy(tH + (size_t)k * nn, H, sizeof(double) * nn);
+        memcpy(tAk + (size_t)k * m, Ak, m);
+        double c;
+        double alpha = exact_line_search(n, m, M, J, a0, D, a, p, r, tQ + (size_t)k * m,
+                                         tAp + (size_t)k * m, &c);
+        tAlpha[k] = alpha;
+        tC[k] = c;
+        step_inf = 0.0;
+        for (int j = 0; j < n; ++j) {
+            a[j] += alpha * p[j];
+            step_inf = fmax(step_inf, fabs(alpha * p[j]));
+        }
+        steps = k + 1;
+    }
+    if (st != ST_CONVERGED) {
+        /* the K-th iterate is returned; classify it like the forward does */
+        eval_residual(n, m, M, J, a0, aref, D, a, r, Ak, F);
+        st = converged(n, M, F, step_inf, a, tol) ? ST_CONVERGED : ST_MAXITER;
+    }
+    memcpy(a_out, a, sizeof(double) * n);
+    *iters = steps;
+    *status = st;
+
+    /* reverse sweep over the recorded steps */
+    double *ab = (double *)malloc(sizeof(double) * n1);      /* adjoint of a_{k+1} then a_k */
+    double *akb = (double *)malloc(sizeof(double) * n1);
+    double *pb = (double *)malloc(sizeof(double) * n1);
+    double *d = (double *)malloc(sizeof(double) * n1);
+    double *Mp = (double *)malloc(sizeof(double) * n1);
+    double *MTp = (double *)malloc(sizeof(double) * n1);
+    double *Md = (double *)malloc(sizeof(double) * n1);
+    double *u = (double *)malloc(sizeof(double) * n1);
+    double *gb = (double *)malloc(sizeof(double) * n1);
+    double *tmp = (double *)malloc(sizeof(double) * n1);
+    double *Ht = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *qb = (double *)malloc(sizeof(double) * mm);
+    double *rb = (double *)malloc(sizeof(double) * mm);
+    double *Ju = (double *)malloc(sizeof(double) * mm);
+    double *t = (double *)malloc(sizeof(double) * mm);
+    /* private accumulators so a NULL output still lets the sweep run */
+    double *g_a0 = (double *)calloc(n1, sizeof(double));
+    double *g_aref = (double *)calloc(mm, sizeof(double));
+    double *g_J = (double *)calloc(mn > 0 ? mn : 1, sizeof(double));
+    double *g_D = (double *)calloc(mm, sizeof(double));
+    double *g_M = (double *)calloc((size_t)n1 * n1, sizeof(double));
+    memcpy(ab, abar, sizeof(double) * n);
+    for (int k = steps - 1; k >= 0; --k) {
+        const double *ak = tA + (size_t)k * n, *pk = tP + (size_t)k * n;
+        const double *rk = tR + (size_t)k * m, *qk = tQ + (size_t)k * m;
+        const double *Hk = tH + (size_t)k * nn;
+        const unsigned char *Ak_ = tAk + (size_t)k * m, *Apk = tAp + (size_t)k * m;
+        double alpha = tAlpha[k], c = tC[k];
+        for (int j = 0; j < n; ++j) d[j] = ak[j] - a0[j];
+        /* a_{k+1} = a_k + alpha p */
+        double alphab = dot(n, ab, pk);
+        for (int j = 0; j < n; ++j) { pb[j] = alpha * ab[j]; akb[j] = ab[j]; }
+        /* alpha = -b / c */
+        double bb = -alphab / c;
+        double cb = -alphab * alpha / c;
+        matvec(n, n, M, pk, Mp);
+        matvec_t(n, n, M, pk, MTp);
+        matvec(n, n, M, d, Md);
+        /* c = p^T M p + sum_{A'} D q^2 */
+        for (int j = 0; j < n; ++j) pb[j] += cb * (Mp[j] + MTp[j]);
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) g_M[j * n + l] += cb * pk[j] * pk[l];
+        for (int i = 0; i < m; ++i) { qb[i] = 0.0; rb[i] = 0.0; }
+        for (int i = 0; i < m; ++i) {
+            if (!Apk[i]) continue;
+            g_D[i] += cb * qk[i] * qk[i];
+            qb[i] += 2.0 * cb * D[i] * qk[i];
+        }
+        /* b = p^T M (a_k - a0) + sum_{A'} D q r */
+        for (int j = 0; j < n; ++j) pb[j] += bb * Md[j];
+        for (int j = 0; j < n; ++j) { akb[j] += bb * MTp[j]; g_a0[j] -= bb * MTp[j]; }
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) g_M[j * n + l] += bb * pk[j] * d[l];
+        for (int i = 0; i < m; ++i) {
+            if (!Apk[i]) continue;
+            g_D[i] += bb * qk[i] * rk[i];
+            qb[i] += bb * D[i] * rk[i];
+            rb[i] += bb * D[i] * qk[i];
+        }
+        /* q = J p */
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) {
+                pb[j] += J[(size_t)i * n + j] * qb[i];
+                g_J[(size_t)i * n + j] += qb[i] * pk[j];
+            }
+        /* p = -H^{-1} g  ->  u = H^{-T} pbar, gbar = -u, Hbar = -u p^T */
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) Ht[j * n + l] = Hk[l * n + j];
+        qr_solve(n, Ht, pb, u);
+        for (int j = 0; j < n; ++j) gb[j] = -u[j];
+        /* H = M + J^T diag(D o A_k) J */
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) g_M[j * n + l] -= u[j] * pk[l];
+        for (int i = 0; i < m; ++i) {
+            Ju[i] = dot(n, J + (size_t)i * n, u);
+            if (!Ak_[i]) continue;
+            for (int j = 0; j < n; ++j)
+                g_J[(size_t)i * n + j] -= D[i] * Ju[i] * pk[j] + D[i] * qk[i] * u[j];
+            g_D[i] -= Ju[i] * qk[i];
+        }
+        /* g = M (a_k - a0) + J^T (D o A_k o r_k) */
+        matvec_t(n, n, M, gb, tmp);
+        for (int j = 0; j < n; ++j) { akb[j] += tmp[j]; g_a0[j] -= tmp[j]; }
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) g_M[j * n + l] += gb[j] * d[l];
+        for (int i = 0; i < m; ++i) {
+            t[i] = dot(n, J + (size_t)i * n, gb);
+            if (!Ak_[i]) continue;
+            double w = D[i] * rk[i];
+            for (int j = 0; j < n; ++j) g_J[(size_t)i * n + j] += w * gb[j];
+            rb[i] += D[i] * t[i];
+            g_D[i] += rk[i] * t[i];
+        }
+        /* r = J a_k - aref */
+        matvec_t(m, n, J, rb, tmp);
+        for (int j = 0; j < n; ++j) akb[j] += tmp[j];
+        for (int i = 0; i < m; ++i) {
+            for (int j = 0; j < n; ++j) g_J[(size_t)i * n + j] += rb[i] * ak[j];
+            g_aref[i] -= rb[i];
+        }
+        memcpy(ab, akb, sizeof(double) * n);
+    }
+    /* the first iterate is a0 itself */
+    for (int j = 0; j < n; ++j) g_a0[j] += ab[j];
+    if (a0bar) memcpy(a0bar, g_a0, sizeof(double) * n);
+    if (arefbar) memcpy(arefbar, g_aref, sizeof(double) * m);
+    if (Jbar) memcpy(Jbar, g_J, sizeof(double) * mn);
+    if (Dbar) memcpy(Dbar, g_D, sizeof(double) * m);
+    if (Mbar) memcpy(Mbar, g_M, sizeof(double) * nn);
+
+    free(tA); free(tP); free(tR); free(tQ); free(tH); free(tAk); free(tAp); free(tAlpha);
+    free(tC); free(a); free(F); free(negF); free(p); free(H); free(r); free(Ak);
+    free(ab); free(akb); free(pb); free(d); free(Mp); free(MTp); free(Md); free(u); free(gb);
+    free(tmp); free(Ht); free(qb); free(rb); free(Ju); free(t);
+    free(g_a0); free(g_aref); free(g_J); free(g_D); free(g_M);
+    return 0;
+}
+
+/* Line search alone (for its own tests): returns alpha; Ap (m) and q (m) out. */
+double oracle_line_search(int n, int m, const double *M, const double *J, const double *a0,
+                          const double *aref, const double *D, const double *a,
+                          const double *p, double *q, unsigned char *Ap) {
+    double *r = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    for (int i = 0; i < m; ++i) r[i] = dot(n, J + (size_t)i * n, a) - aref[i];
+    double alpha = exact_line_search(n, m, M, J, a0, D, a, p, r, q, Ap, NULL);
+    free(r);
+    return alpha;
+}
+
+/* ------------------------------------------------------------------ */
+/* packed batches: instance i uses off_*[i]; OpenMP over instances      */
+/* ------------------------------------------------------------------ */
+
+static void set_threads(int threads) {
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_forward_batch(int B, const int32_t *nv, const int32_t *nrows,
+                          const int64_t *off_nn, const int64_t *off_mn, const int64_t *off_n,
+                          const int64_t *off_m, const double *M, const double *J,
+                          const double *a0, const double *aref, const double *D,
+                          int max_iter, double tol, double *a, unsigned char *active,
+                          int32_t *iters, int32_t *status, int threads) {
+    set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b) {
+        int it = 0, st = 0;
+        oracle_forward(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], a0 + off_n[b],
+                       aref + off_m[b], D + off_m[b], NULL, max_iter, tol, a + off_n[b],
+                       active + off_m[b], &it, &st, NULL, NULL, NULL);
+        iters[b] = it;
+        status[b] = st;
+    }
+}
+
+void oracle_ift_vjp_batch(int B, const int32_t *nv, const int32_t *nrows,
+                          const int64_t *off_nn, const int64_t *off_mn, const int64_t *off_n,
+                          const int64_t *off_m, const double *M, const double *J,
+                          const double *a0, const double *aref, const double *D,
+                          const double *a, const unsigned char *active, const double *abar,
+                          double *a0bar, double *arefbar, double *Jbar, double *Dbar,
+                          double *Mbar, int threads) {
+    set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b) {
+        oracle_ift_vjp(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], a0 + off_n[b],
+                       aref + off_m[b], D + off_m[b], a + off_n[b],
+                       active ? active + off_m[b] : NULL, abar + off_n[b],
+                       a0bar ? a0bar + off_n[b] : NULL, arefbar ? arefbar + off_m[b] : NULL,
+                       Jbar ? Jbar + off_mn[b] : NULL, Dbar ? Dbar + off_m[b] : NULL,
+                       Mbar ? Mbar + off_nn[b] : NULL, NULL);
+    }
+}
+
+void oracle_unrolled_vjp_batch(int B, const int32_t *nv, const int32_t *nrows,
+                               const int64_t *off_nn, const int64_t *off_mn,
+                               const int64_t *off_n, const int64_t *off_m, const double *M,
+                               const double *J, const double *a0, const double *aref,
+                               const double *D, const double *abar, int K, double tol,
+                               double *a, double *a0bar, double *arefbar, double *Jbar,
+                               double *Dbar, double *Mbar, int32_t *iters, int32_t *status,
+                               int threads) {
+    set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b) {
+        int it = 0, st = 0;
+        oracle_unrolled_vjp(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], a0 + off_n[b],
+                            aref + off_m[b], D + off_m[b], abar + off_n[b], K, tol,
+                            a + off_n[b], a0bar ? a0bar + off_n[b] : NULL,
+                            arefbar ? arefbar + off_m[b] : NULL, Jbar ? Jbar + off_mn[b] : NULL,
+                            Dbar ? Dbar + off_m[b] : NULL, Mbar ? Mbar + off_nn[b] : NULL,
+                            &it, &st);
+        iters[b] = it;
+        status[b] = st;
+    }
+}
