@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: batched contact solve + IFT VJP on one MI355X.
+
+One step = cs_forward + cs_ift_vjp over one batch of B = 4096 instances with
+nv = 9 and 16 contacts (64 pyramid rows), FP32, Newton cap K = 10, tol 1e-5,
+inputs resident in HBM.  Steps rotate over enough distinct batches (seeded
+synthetic inputs) that their working set exceeds twice the 256 MB last-level
+(MALL) cache.  Prints one JSON line.
+
+Also measured (reported inside the same line): the unrolled-trace gradient
+at the same K on the same GPU, the state/tape memory, the dominant kernel's
+roofline position from HIP events bracketing every launch in the timed
+region, and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+B, NV, NC = 4096, 9, 16
+M_ROWS = 4 * NC
+K_CAP, TOL = 10, 1e-5
+MALL_BYTES = 256 * 2 ** 20
+HBM_PEAK = 8.0e12          # B/s
+FP32_VEC_PEAK = 157.3e12   # flop/s (256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz)
+
+
+def algorithmic_bytes(n, m, s=4):
+    """Compulsory HBM traffic per solve of cs_forward and cs_ift_vjp (all outputs)."""
+    fwd = s * (n * n + m * n + n + 2 * m) + s * n + math.ceil(m / 8)
+    vjp = s * (3 * n + n * n + m * n + 2 * m) + math.ceil(m / 8) + s * (n + 2 * m + m * n + n * n)
+    return fwd, vjp
+
+
+def forward_flops(n, m, active, iters):
+    """Algorithmic flops of one forward solve.
+
+    Per Newton step: r = J a - aref (2mn), F = M(a-a0) + J^T w (2n^2 + 2mn),
+    H = M + J^T D_A J on the lower triangle (|A| n (n+1)), Cholesky (n^3/3),
+    solve (2n^2), q = J p (2mn), line-search coefficients (4n^2), two
+    line-search passes over the rows (8m) and the update (2n).  The returned
+    iterate adds one residual/gradient/Hessian/Cholesky evaluation.
+    """
+    step = 8 * m * n + 8 * n * n + active * n * (n + 1) + n ** 3 / 3 + 8 * m + 2 * n
+    final = 4 * m * n + 2 * n * n + active * n * (n + 1) + n ** 3 / 3
+    return iters * step + final
+
+
+def make_batches(count, seed0):
+    from paper_2607_24959_amd import synth
+    return [synth.uniform_batch(B, NV, NC, seed0 + i).astype(np.float32) for i in range(count)]
+
+
+def cpu_baseline(b32, seconds=10.0):
+    """The FP64 oracle (unmodified) on the FP32-rounded inputs of one batch."""
+    import oracle
+    b64 = b32.astype(np.float64)
+    P = oracle.Packed.uniform(b64.M, b64.J, b64.a0, b64.aref, b64.D, b64.abar)
+    threads = oracle.max_threads()
+    done, t0 = 0, time.perf_counter()
+    reps = 0
+    while True:
+        fw = P.forward(max_iter=K_CAP, tol=1e-10, threads=threads)
+        P.ift_vjp(fw["a"], fw["active"], threads=threads)
+        done += P.B
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 400:
+            break
+    return dict(value=done / el, unit="solves/s", cores=threads, kind="oracle",
+                sample=f"{reps} passes of forward + IFT VJP over one B={B} batch (FP64 oracle on "
+                       f"the FP32-rounded inputs, {threads} OpenMP threads, {el:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-unrolled", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (instances are "
+              "independent, so a multi-GPU run would be B/G instances per GPU at the same "
+              "shape)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_24959_amd import solver
+    dev = torch.device("cuda:0")
+
+    fwd_b, vjp_b = algorithmic_bytes(NV, M_ROWS)
+    per_batch = (B * 4 * (NV * NV * 2 + M_ROWS * NV * 2 + NV * 4 + M_ROWS * 4)
+                 + solver.Batch.uniform(B, NV, M_ROWS, torch.float32, device="cpu").state_bytes())
+    R = max(8, math.ceil(2 * MALL_BYTES / per_batch) + 1)
+    host = make_batches(R, 20260725)
+    batch = solver.Batch.uniform(B, NV, M_ROWS, torch.float32, device=dev)
+    keys = ("M", "J", "a0", "aref", "D", "abar")
+    bufs = []
+    for hb in host:
+        t = {k: torch.from_numpy(np.ascontiguousarray(getattr(hb, k))).to(dev) for k in keys}
+        sol = solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CAP, tol=TOL)
+        grads = solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"])
+        bufs.append((t, sol, grads))
+    torch.cuda.synchronize()
+
+    def step(i, ev=None):
+        t, sol, grads = bufs[i % R]
+        if ev is not None:
+            ev[0].record()
+        solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CAP, tol=TOL,
+                       out=sol)
+        if ev is not None:
+            ev[1].record()
+        solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
+        if ev is not None:
+            ev[2].record()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # whole timed region on the GPU clock (first forward start -> last VJP end)
+    gpu_ms = evs[0][0].elapsed_time(evs[-1][2])
+    ms = max(wall * 1e3, gpu_ms)
+    t_fwd = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    t_vjp = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    value = B * args.steps / (ms / 1e3)
+
+    # convergence / active-set statistics of the benchmarked solves (one batch)
+    st = bufs[0][1].status.cpu().numpy()
+    it = bufs[0][1].iters.cpu().numpy()
+    sb = batch.state_bytes()
+    al = (4 * B * NV * NV + 255) // 256 * 256
+    act = bufs[0][1].state[al:al + B * M_ROWS].cpu().numpy().reshape(B, M_ROWS).sum(1)
+    flops_per_launch = float(np.sum(forward_flops(NV, M_ROWS, act, it)))
+    fwd_s = float(np.mean(t_fwd)) / 1e3
+    vjp_s = float(np.mean(t_vjp)) / 1e3
+    fwd_flops_rate = flops_per_launch / fwd_s
+    vjp_gbps = B * vjp_b / vjp_s
+
+    out = {
+        "metric": "fwd+IFT-VJP contact solves/sec and GB/s vs unrolled-AD; p50/p99 latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "uniform batch B=4096, nv=9, 16 contacts (64 pyramid rows), FP32, "
+                               "forward (Newton cap K=10, tol 1e-5) + IFT VJP",
+                   "B": B, "nv": NV, "contacts": NC, "rows": M_ROWS, "K": K_CAP, "tol": TOL,
+                   "rotating_batches": R, "working_set_MB": round(R * per_batch / 2 ** 20, 1)},
+        "gbps_algorithmic": value * (fwd_b + vjp_b) / 1e9,
+        "bytes_per_solve": {"forward": fwd_b, "ift_vjp": vjp_b},
+        "kernels": {
+            "forward_ms": fwd_s * 1e3, "ift_vjp_ms": vjp_s * 1e3,
+            "forward_tflops": fwd_flops_rate / 1e12,
+            "ift_vjp_gbps": vjp_gbps / 1e9, "ift_vjp_hbm_frac": vjp_gbps / HBM_PEAK,
+        },
+        "roofline": {"kernel": "k_forward_small<float,9,4>", "bound": "alu",
+                     "achieved": fwd_flops_rate / 1e12, "peak": FP32_VEC_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fwd_flops_rate / FP32_VEC_PEAK, "traffic": None,
+                     "flops_per_launch": flops_per_launch},
+        "solver": {"converged_frac": float(np.mean(st & 1)), "mean_iters": float(it.mean()),
+                   "mean_active_rows": float(act.mean())},
+        "memory": {"state_bytes": sb, "tape_bytes_K10": batch.tape_bytes(K_CAP),
+                   "tape_bytes_K1": batch.tape_bytes(1)},
+    }
+
+    if not args.no_unrolled:
+        t, sol, grads = bufs[0]
+        n_u = max(10, args.steps // 10)
+        tape = torch.empty(batch.tape_bytes(K_CAP), dtype=torch.uint8, device=dev)
+        for i in range(3):
+            tt = bufs[i % R][0]
+            solver.unrolled_vjp(batch, tt["M"], tt["J"], tt["a0"], tt["aref"], tt["D"], tt["abar"],
+                                K=K_CAP, tol=TOL, tape=tape)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(n_u):
+            tt = bufs[i % R][0]
+            solver.unrolled_vjp(batch, tt["M"], tt["J"], tt["a0"], tt["aref"], tt["D"], tt["abar"],
+                                K=K_CAP, tol=TOL, tape=tape)
+        e1.record()
+        torch.cuda.synchronize()
+        u_ms = e0.elapsed_time(e1) / n_u
+        u_val = B / (u_ms / 1e3)
+        out["unrolled"] = {"value": u_val, "unit": "solves/s", "K": K_CAP, "ms_per_step": u_ms,
+                           "ift_over_unrolled": value / u_val}
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(host[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * cs.h -- C ABI of the batched contact-solve library (libcs.so, gfx950).
+ *
+ * Each instance i of a batch is one regularised contact block with pyramidal
+ * friction rows (the reduced problem of Sec. III-A, eq. 5):
+ *
+ *   a*_i = argmin_a 1/2 (a - a0)^T M (a - a0) + 1/2 sum_r D_r min(r_r, 0)^2,
+ *          r = J a - aref,
+ *
+ * with M (n x n, symmetric positive definite), J (m x n, m = 4 x contacts,
+ * rows per contact ordered [J_n + mu J_t1, J_n - mu J_t1, J_n + mu J_t2,
+ * J_n - mu J_t2]), a0 (n), aref (m) and D = 1/R (m, D > 0).
+ *
+ * Conventions for every entry point:
+ *  - All arrays are device pointers, row-major, of the batch's dtype (float for
+ *    CS_F32, double for CS_F64), except where stated.  The caller allocates and
+ *    owns every buffer (including `state` and `tape`); the library never
+ *    allocates or frees device memory on a call.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *    stream).  The return code reports argument and launch errors only; the
+ *    per-instance `status` words are valid once the stream has synchronised.
+ *  - Outputs must not alias inputs.
+ *  - Uniform batches: `nv`, `nrows` and every `off_*` pointer are NULL and
+ *    instance i occupies elements [i n^2, (i+1) n^2) of M, [i m n, ...) of J,
+ *    [i n, ...) of n-vectors and [i m, ...) of m-vectors.
+ *  - Packed (uneven) batches: `nv`, `nrows` [B] and the four offset arrays
+ *    [B+1] (element offsets, off[B] = total) are device arrays, and the host
+ *    fields `nv_max`, `nrows_max`, `total_*` must describe them.
+ *
+ * Error codes: CS_OK, CS_EINVAL (bad argument: sizes, NULL required pointer,
+ * dtype, unsupported shape), CS_ENOSPC (caller buffer too small), CS_EHIP (HIP
+ * launch error), CS_EUNSUPPORTED.  cs_strerror() names them.
+ */
+#ifndef CS_H
+#define CS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CS_OK 0
+#define CS_EINVAL (-1)
+#define CS_ENOSPC (-2)
+#define CS_EHIP (-3)
+#define CS_EUNSUPPORTED (-4)
+
+#define CS_F32 0
+#define CS_F64 1
+
+/* per-instance status bits (status[i]) */
+#define CS_ST_CONVERGED 1   /* stopping rule met at the returned iterate */
+#define CS_ST_MAXITER 2     /* max_iter steps taken without meeting it */
+#define CS_ST_NONFINITE 4   /* an input was NaN/Inf; outputs are NaN */
+#define CS_ST_NOTSPD 8      /* M (or a Newton matrix) is not positive definite; outputs NaN */
+#define CS_ST_LSFAIL 16     /* the line search hit its safeguard cap (step still taken) */
+
+/* Kernel families (cs_batch.path).  AUTO picks SMALL when the batch is
+ * uniform and its shape fits a small-instance kernel (FP32 n <= 12, FP64
+ * n <= 6, m <= 64), TEAM otherwise.  TEAM: one workgroup per instance, any
+ * supported shape.  SMALL: 16 lanes per instance with the instance held in
+ * registers; CS_EUNSUPPORTED when the shape does not fit.  Every family
+ * writes the same state layout, so any cs_ift_vjp path can read any
+ * cs_forward state. */
+#define CS_PATH_AUTO 0
+#define CS_PATH_TEAM 1
+#define CS_PATH_SMALL 2
+
+/* Largest sizes the library supports per instance. */
+#define CS_NV_MAX 128
+#define CS_NROWS_MAX 4096
+
+typedef struct cs_batch {
+    int32_t B;              /* number of instances (>= 0) */
+    int32_t dtype;          /* CS_F32 or CS_F64 */
+    int32_t nv_uniform;     /* n when nv == NULL */
+    int32_t nrows_uniform;  /* m when nrows == NULL */
+    const int32_t *nv;      /* device [B] or NULL */
+    const int32_t *nrows;   /* device [B] or NULL */
+    const int64_t *off_nn;  /* device [B+1]: offsets into M, Mbar and the state factors */
+    const int64_t *off_mn;  /* device [B+1]: offsets into J, Jbar */
+    const int64_t *off_n;   /* device [B+1]: offsets into a0, a, abar, a0bar */
+    const int64_t *off_m;   /* device [B+1]: offsets into aref, D, arefbar, Dbar */
+    const int32_t *order;   /* device [B] processing order (a permutation), or NULL */
+    int32_t nv_max;         /* packed: max n over the batch */
+    int32_t nrows_max;      /* packed: max m over the batch */
+    int64_t total_nn;       /* packed: off_nn[B] */
+    int64_t total_mn;       /* packed: off_mn[B] */
+    int64_t total_n;        /* packed: off_n[B] */
+    int64_t total_m;        /* packed: off_m[B] */
+    int32_t path;           /* kernel family: CS_PATH_AUTO, CS_PATH_TEAM or CS_PATH_SMALL */
+    int32_t reserved;       /* must be 0 */
+} cs_batch;
+
+typedef struct cs_solver_params {
+    int32_t max_iter;  /* cap on Newton steps (>= 0); the unrolled VJP takes exactly this K */
+    int32_t flags;     /* reserved, must be 0 */
+    double tol;        /* stopping tolerance (>= 0), see cs_forward */
+} cs_solver_params;
+
+/* Bytes of the `state` buffer cs_forward writes and cs_ift_vjp reads: the
+ * Cholesky factor of H(A*) (n x n slot per instance, lower triangle used) and
+ * the active set A* (one byte per row).  0 on invalid arguments. */
+size_t cs_state_bytes(const cs_batch *batch);
+
+/* Bytes of the tape cs_unrolled_vjp needs for K recorded steps. */
+size_t cs_unrolled_tape_bytes(const cs_batch *batch, int32_t K);
+
+/* Forward solve (Sec. III-B): from a_init (a0 when NULL) take Newton steps
+ * p = -H^{-1} F with F = M (a - a0) + J^T (D o A o r) (eq. 6) and
+ * H = M + J^T diag(D o A) J (eq. 9), A = 1[r < 0], each scaled by the exact
+ * minimiser of L along p (eq. 10).  Iterate a_k is converged when
+ * ||F(a_k)||_2 <= tol tr(M), or (k >= 1) the step into it was small,
+ * ||a_k - a_{k-1}||_inf <= tol (1 + ||a_k||_inf), and left the active set
+ * unchanged, A(a_k) = A(a_{k-1}); at most max_iter steps are taken.  M is
+ * read as symmetric (the SMALL family reads its lower triangle only).
+ * Writes a_out [n per instance], state (factor of H at the returned iterate and
+ * its active set), status [B] (CS_ST_* bits) and, if non-NULL, iters [B]
+ * (steps taken).  a_init, iters may be NULL. */
+int cs_forward(const cs_batch *batch, const cs_solver_params *params,
+               const void *M, const void *J, const void *a0, const void *aref, const void *D,
+               const void *a_init, void *a_out, void *state, size_t state_bytes,
+               int32_t *status, int32_t *iters, void *stream);
+
+/* IFT vector-Jacobian product (Sec. III-C, eq. 17) at the solution `a` that
+ * cs_forward returned, using the saved factor of H(A*) and A* from `state`:
+ *   H lambda = abar,  sigma = J lambda,  w = D o A* o r*,
+ *   a0bar = M^T lambda,  arefbar = D o A* o sigma,  Dbar = -A* o r* o sigma,
+ *   Jbar = -(w lambda^T + arefbar a^T),  Mbar = -lambda (a - a0)^T.
+ * Each of the five outputs may be NULL (not computed).  Inputs must be the
+ * ones given to the cs_forward call that wrote `state`.  If that call stopped
+ * at max_iter the product linearises at the returned iterate. */
+int cs_ift_vjp(const cs_batch *batch, const void *state, size_t state_bytes,
+               const void *M, const void *J, const void *a0, const void *aref, const void *D,
+               const void *a, const void *abar,
+               void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar, void *stream);
+
+/* Unrolled-trace VJP (the baseline gradient): runs exactly K = params->max_iter
+ * steps of the same solver from a0 (steps after the stopping rule fires are the
+ * identity), records each step on `tape`, then differentiates abar . a_K
+ * through the recorded trace in reverse with the active sets and line-search
+ * pieces held fixed.  Writes a_out, the five gradients (each non-NULL),
+ * status [B] and, if non-NULL, iters [B].  tape_bytes must be at least
+ * cs_unrolled_tape_bytes(batch, K). */
+int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params,
+                    const void *M, const void *J, const void *a0, const void *aref, const void *D,
+                    const void *abar, void *a_out,
+                    void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar,
+                    void *tape, size_t tape_bytes, int32_t *status, int32_t *iters,
+                    void *stream);
+
+/* Name of an error code. */
+const char *cs_strerror(int code);
+
+/* Library ABI version (bumped on incompatible changes). */
+int cs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CS_H */

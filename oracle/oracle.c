@@ -26,8 +26,9 @@
  * Stopping rule (reading of "tolerance-converged" with a max-iteration cap,
  * Sec. III-C): iterate a_k is converged when
  *   ||F(a_k)||_2 <= tol * tr(M)          (gradient scaled by mean inertia * n)
- * or, for k >= 1, the step that produced it was negligible,
- *   ||a_k - a_{k-1}||_inf <= tol * (1 + ||a_k||_inf).
+ * or, for k >= 1, the step that produced it was negligible and did not change
+ * the active set,
+ *   ||a_k - a_{k-1}||_inf <= tol * (1 + ||a_k||_inf)  and  A(a_k) = A(a_{k-1}).
  * At most max_iter steps are taken; the returned active set and residual are
  * those of the returned iterate.
  */
@@ -243,14 +244,15 @@ static double inf_norm(int n, const double *x) {
     return s;
 }
 
-/* step_inf: ||a_k - a_{k-1}||_inf of the step that produced a, or < 0 at k = 0 */
-static int converged(int n, const double *M, const double *F, double step_inf,
+/* step_inf: ||a_k - a_{k-1}||_inf of the step that produced a, or < 0 at k = 0;
+ * same_set: A(a_k) equals A(a_{k-1}) */
+static int converged(int n, const double *M, const double *F, double step_inf, int same_set,
                      const double *a, double tol) {
     double trM = 0.0;
     for (int j = 0; j < n; ++j) trM += M[j * n + j];
     double g = sqrt(dot(n, F, F));
     if (g <= tol * trM) return 1;
-    if (step_inf >= 0.0 && step_inf <= tol * (1.0 + inf_norm(n, a))) return 1;
+    if (step_inf >= 0.0 && same_set && step_inf <= tol * (1.0 + inf_norm(n, a))) return 1;
     return 0;
 }
 
@@ -293,9 +295,12 @@ int oracle_forward(int n, int m, const double *M, const double *J, const double 
     for (int j = 0; j < n; ++j) a[j] = a_init ? a_init[j] : a0[j];
     int st = ST_MAXITER;
     double step_inf = -1.0;
+    unsigned char *Aprev = (unsigned char *)malloc(mm);
     for (int k = 0;; ++k) {
+        if (k > 0) memcpy(Aprev, active, m);
         eval_residual(n, m, M, J, a0, aref, D, a, r, active, F);
-        if (converged(n, M, F, step_inf, a, tol)) { st = ST_CONVERGED; break; }
+        int same = k > 0 && (m == 0 || memcmp(Aprev, active, m) == 0);
+        if (converged(n, M, F, step_inf, same, a, tol)) { st = ST_CONVERGED; break; }
         if (k == max_iter) { st = ST_MAXITER; break; }
         assemble_H(n, m, M, J, D, active, H);
         for (int j = 0; j < n; ++j) negF[j] = -F[j];
@@ -312,7 +317,7 @@ int oracle_forward(int n, int m, const double *M, const double *J, const double 
         *iters = k + 1;
     }
     *status = st;
-    free(r); free(q); free(F); free(negF); free(p); free(H); free(Ap);
+    free(r); free(q); free(F); free(negF); free(p); free(H); free(Ap); free(Aprev);
     return 0;
 }
 
@@ -333,7 +338,7 @@ int oracle_ift_vjp(int n, int m, const double *M, const double *J, const double 
     double *H = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
     double *Ht = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
     double *lam = (double *)malloc(sizeof(double) * n1);
-    unsigned char *A = (unsigned char *)malloc(mm);
+    unsigned char *A = (unsigned char *)calloc(mm, 1);
     for (int i = 0; i < m; ++i) {
         r[i] = dot(n, J + (size_t)i * n, a) - aref[i];
         A[i] = active ? active[i] : (r[i] < 0.0);
@@ -399,7 +404,7 @@ int oracle_unrolled_vjp(int n, int m, const double *M, const double *J, const do
     unsigned char *tAp = (unsigned char *)malloc((size_t)K1 * mm);
     double *tAlpha = (double *)malloc(sizeof(double) * K1);
     double *tC = (double *)malloc(sizeof(double) * K1);
-    double *a = (double *)malloc(sizeof(double) * n1);
+    double *a = (double *)calloc(n1, sizeof(double));
     double *F = (double *)malloc(sizeof(double) * n1);
     double *negF = (double *)malloc(sizeof(double) * n1);
     double *p = (double *)malloc(sizeof(double) * n1);
@@ -409,9 +414,12 @@ int oracle_unrolled_vjp(int n, int m, const double *M, const double *J, const do
     for (int j = 0; j < n; ++j) a[j] = a0[j];
     int steps = 0, st = ST_MAXITER;
     double step_inf = -1.0;
+    unsigned char *Aprev = (unsigned char *)malloc(mm);
     for (int k = 0; k < K; ++k) {
+        if (k > 0) memcpy(Aprev, Ak, m);
         eval_residual(n, m, M, J, a0, aref, D, a, r, Ak, F);
-        if (converged(n, M, F, step_inf, a, tol)) { st = ST_CONVERGED; break; }
+        int same = k > 0 && (m == 0 || memcmp(Aprev, Ak, m) == 0);
+        if (converged(n, M, F, step_inf, same, a, tol)) { st = ST_CONVERGED; break; }
         assemble_H(n, m, M, J, D, Ak, H);
         for (int j = 0; j < n; ++j) negF[j] = -F[j];
         qr_solve(n, H, negF, p);
@@ -434,9 +442,12 @@ int oracle_unrolled_vjp(int n, int m, const double *M, const double *J, const do
     }
     if (st != ST_CONVERGED) {
         /* the K-th iterate is returned; classify it like the forward does */
+        if (K > 0) memcpy(Aprev, Ak, m);
         eval_residual(n, m, M, J, a0, aref, D, a, r, Ak, F);
-        st = converged(n, M, F, step_inf, a, tol) ? ST_CONVERGED : ST_MAXITER;
+        int same = K > 0 && (m == 0 || memcmp(Aprev, Ak, m) == 0);
+        st = converged(n, M, F, step_inf, same, a, tol) ? ST_CONVERGED : ST_MAXITER;
     }
+    free(Aprev);
     memcpy(a_out, a, sizeof(double) * n);
     *iters = steps;
     *status = st;

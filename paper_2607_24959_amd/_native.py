@@ -1,0 +1,117 @@
+"""ctypes binding of libcs.so: the C ABI of include/cs.h, nothing more.
+
+Every function here marshals arguments and calls the library; all of the
+method runs in the HIP kernels.  Importing this module loads the library and
+raises if it has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcs.so")
+
+CS_OK, CS_EINVAL, CS_ENOSPC, CS_EHIP, CS_EUNSUPPORTED = 0, -1, -2, -3, -4
+CS_F32, CS_F64 = 0, 1
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL = 1, 2, 4, 8, 16
+NV_MAX, NROWS_MAX = 128, 4096
+PATH_AUTO, PATH_TEAM, PATH_SMALL = 0, 1, 2
+
+EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
+            "cs_unrolled_tape_bytes", "cs_strerror", "cs_version")
+
+
+class CsBatch(C.Structure):
+    _fields_ = [
+        ("B", C.c_int32), ("dtype", C.c_int32),
+        ("nv_uniform", C.c_int32), ("nrows_uniform", C.c_int32),
+        ("nv", C.c_void_p), ("nrows", C.c_void_p),
+        ("off_nn", C.c_void_p), ("off_mn", C.c_void_p),
+        ("off_n", C.c_void_p), ("off_m", C.c_void_p),
+        ("order", C.c_void_p),
+        ("nv_max", C.c_int32), ("nrows_max", C.c_int32),
+        ("total_nn", C.c_int64), ("total_mn", C.c_int64),
+        ("total_n", C.c_int64), ("total_m", C.c_int64),
+        ("path", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class CsSolverParams(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("flags", C.c_int32), ("tol", C.c_double)]
+
+
+class CsError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libcs.so is not built ({LIB_PATH}); run "
+                              "paper_2607_24959_amd.build.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, sz, i32 = C.c_void_p, C.c_size_t, C.c_int32
+        pb, pp = C.POINTER(CsBatch), C.POINTER(CsSolverParams)
+        L.cs_version.restype = C.c_int
+        L.cs_strerror.restype = C.c_char_p
+        L.cs_strerror.argtypes = [C.c_int]
+        L.cs_state_bytes.restype = sz
+        L.cs_state_bytes.argtypes = [pb]
+        L.cs_unrolled_tape_bytes.restype = sz
+        L.cs_unrolled_tape_bytes.argtypes = [pb, i32]
+        L.cs_forward.restype = C.c_int
+        L.cs_forward.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+        L.cs_ift_vjp.restype = C.c_int
+        L.cs_ift_vjp.argtypes = [pb, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cs_unrolled_vjp.restype = C.c_int
+        L.cs_unrolled_vjp.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                      sz, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().cs_strerror(int(code)).decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != CS_OK:
+        raise CsError(code, where)
+
+
+def version() -> int:
+    return int(lib().cs_version())
+
+
+def state_bytes(batch: CsBatch) -> int:
+    return int(lib().cs_state_bytes(C.byref(batch)))
+
+
+def tape_bytes(batch: CsBatch, K: int) -> int:
+    return int(lib().cs_unrolled_tape_bytes(C.byref(batch), int(K)))
+
+
+def forward(batch, params, M, J, a0, aref, D, a_init, a_out, state, state_nbytes, status, iters,
+            stream):
+    return lib().cs_forward(C.byref(batch), C.byref(params), M, J, a0, aref, D, a_init, a_out,
+                            state, state_nbytes, status, iters, stream)
+
+
+def ift_vjp(batch, state, state_nbytes, M, J, a0, aref, D, a, abar, a0bar, arefbar, Jbar, Dbar,
+            Mbar, stream):
+    return lib().cs_ift_vjp(C.byref(batch), state, state_nbytes, M, J, a0, aref, D, a, abar,
+                            a0bar, arefbar, Jbar, Dbar, Mbar, stream)
+
+
+def unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar, Dbar, Mbar,
+                 tape, tape_nbytes, status, iters, stream):
+    return lib().cs_unrolled_vjp(C.byref(batch), C.byref(params), M, J, a0, aref, D, abar, a_out,
+                                 a0bar, arefbar, Jbar, Dbar, Mbar, tape, tape_nbytes, status,
+                                 iters, stream)

@@ -1,0 +1,338 @@
+// cs_api.hip -- extern "C" entry points of libcs.so (see include/cs.h).
+//
+// Host side only: argument validation, buffer-size queries, the choice of
+// kernel family for the batch's shapes, and launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "cs.h"
+#include "cs_generic.hpp"
+#include "cs_small.hpp"
+
+namespace {
+
+constexpr int kAbiVersion = 1;
+constexpr int kMaxIterCap = 100000;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+struct HostBatch {
+    int B, dtype, nmax, mmax, path;
+    bool packed;
+    int64_t tot_nn, tot_mn, tot_n, tot_m;
+    cs::BatchView bv;
+    size_t s;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int describe(const cs_batch *b, HostBatch &hb) {
+    if (!b) return CS_EINVAL;
+    if (b->B < 0) return CS_EINVAL;
+    if (b->dtype != CS_F32 && b->dtype != CS_F64) return CS_EINVAL;
+    if (b->path != CS_PATH_AUTO && b->path != CS_PATH_TEAM && b->path != CS_PATH_SMALL)
+        return CS_EINVAL;
+    if (b->reserved != 0) return CS_EINVAL;
+    hb.path = b->path;
+    hb.B = b->B;
+    hb.dtype = b->dtype;
+    hb.s = b->dtype == CS_F32 ? sizeof(float) : sizeof(double);
+    hb.packed = b->nv != nullptr || b->nrows != nullptr || b->off_nn != nullptr ||
+                b->off_mn != nullptr || b->off_n != nullptr || b->off_m != nullptr;
+    if (hb.packed) {
+        if (!b->nv || !b->nrows || !b->off_nn || !b->off_mn || !b->off_n || !b->off_m)
+            return CS_EINVAL;
+        if (b->nv_max < 1 || b->nv_max > CS_NV_MAX) return CS_EINVAL;
+        if (b->nrows_max < 0 || b->nrows_max > CS_NROWS_MAX) return CS_EINVAL;
+        if (b->total_nn < 0 || b->total_mn < 0 || b->total_n < 0 || b->total_m < 0)
+            return CS_EINVAL;
+        hb.nmax = b->nv_max;
+        hb.mmax = b->nrows_max;
+        hb.tot_nn = b->total_nn;
+        hb.tot_mn = b->total_mn;
+        hb.tot_n = b->total_n;
+        hb.tot_m = b->total_m;
+    } else {
+        if (b->nv_uniform < 1 || b->nv_uniform > CS_NV_MAX) return CS_EINVAL;
+        if (b->nrows_uniform < 0 || b->nrows_uniform > CS_NROWS_MAX) return CS_EINVAL;
+        const int64_t B = b->B, n = b->nv_uniform, m = b->nrows_uniform;
+        hb.nmax = (int)n;
+        hb.mmax = (int)m;
+        hb.tot_nn = B * n * n;
+        hb.tot_mn = B * m * n;
+        hb.tot_n = B * n;
+        hb.tot_m = B * m;
+    }
+    hb.bv.B = b->B;
+    hb.bv.nv_u = b->nv_uniform;
+    hb.bv.nr_u = b->nrows_uniform;
+    hb.bv.nv = b->nv;
+    hb.bv.nr = b->nrows;
+    hb.bv.off_nn = b->off_nn;
+    hb.bv.off_mn = b->off_mn;
+    hb.bv.off_n = b->off_n;
+    hb.bv.off_m = b->off_m;
+    hb.bv.order = b->order;
+    return CS_OK;
+}
+
+size_t state_bytes(const HostBatch &hb) {
+    return align256(hb.s * (size_t)hb.tot_nn) + (size_t)hb.tot_m;
+}
+
+size_t tape_T_elems(const HostBatch &hb, int K) {
+    return (size_t)K * (2 * (size_t)hb.tot_n + (size_t)hb.tot_nn + 2 * (size_t)hb.tot_m +
+                        2 * (size_t)hb.B);
+}
+
+size_t tape_bytes(const HostBatch &hb, int K) {
+    return align256(hb.s * tape_T_elems(hb, K)) + (size_t)K * 2 * (size_t)hb.tot_m;
+}
+
+int check_params(const cs_solver_params *p) {
+    if (!p) return CS_EINVAL;
+    if (p->max_iter < 0 || p->max_iter > kMaxIterCap) return CS_EINVAL;
+    if (p->flags != 0) return CS_EINVAL;
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return CS_EINVAL;
+    return CS_OK;
+}
+
+// Kernel family for this batch: 1 = small, 0 = team, <0 = error code.
+int choose_small(const HostBatch &hb) {
+    const bool fits = cs::small_supported(hb.nmax, hb.mmax, hb.packed, (int)hb.s);
+    if (hb.path == CS_PATH_SMALL) return fits ? 1 : CS_EUNSUPPORTED;
+    if (hb.path == CS_PATH_TEAM) return 0;
+    return fits ? 1 : 0;
+}
+
+int choose_small_unrolled(const HostBatch &hb) {
+    const bool fits = cs::small_unrolled_supported(hb.nmax, hb.mmax, hb.packed, (int)hb.s);
+    if (hb.path == CS_PATH_SMALL) return fits ? 1 : CS_EUNSUPPORTED;
+    if (hb.path == CS_PATH_TEAM) return 0;
+    return fits ? 1 : 0;
+}
+
+// Generic family: team size by shape.
+inline int generic_nt(const HostBatch &hb) {
+    return (hb.nmax <= 32 && hb.mmax <= 32 * 64) ? 64 : 256;
+}
+
+template <typename K>
+int prepare(K kernel, size_t lds) {
+    if (lds > kLdsLimit) return CS_EUNSUPPORTED;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return CS_EHIP;
+    return CS_OK;
+}
+
+inline unsigned grid_for(int B) { return (unsigned)(B < (1 << 20) ? B : (1 << 20)); }
+
+int launch_status() {
+    return hipGetLastError() == hipSuccess ? CS_OK : CS_EHIP;
+}
+
+template <typename T>
+int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, const void *J,
+              const void *a0, const void *aref, const void *D, const void *a_init, void *a_out,
+              void *state, int32_t *status, int32_t *iters, hipStream_t stream) {
+    T *fac = static_cast<T *>(state);
+    uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * (size_t)hb.tot_nn);
+    const int sm = choose_small(hb);
+    if (sm < 0) return sm;
+    if (sm == 1) {
+        return cs::launch_small_forward<T>(hb.bv, hb.nmax, hb.mmax, p->max_iter, (T)p->tol,
+                                           (const T *)M, (const T *)J, (const T *)a0,
+                                           (const T *)aref, (const T *)D, (const T *)a_init,
+                                           (T *)a_out, fac, mask, status, iters, stream);
+    }
+    const int NT = generic_nt(hb);
+    const size_t lds = cs::gen_lds_bytes(hb.nmax, hb.mmax, NT, hb.s);
+    int rc;
+    if (NT == 64) {
+        auto k = cs::k_forward_generic<T, 64>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, p->max_iter,
+                           (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J,
+                           (const T *)a0, (const T *)aref, (const T *)D, (const T *)a_init,
+                           (T *)a_out, fac, mask, status, iters);
+    } else {
+        auto k = cs::k_forward_generic<T, 256>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, p->max_iter,
+                           (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J,
+                           (const T *)a0, (const T *)aref, (const T *)D, (const T *)a_init,
+                           (T *)a_out, fac, mask, status, iters);
+    }
+    return launch_status();
+}
+
+template <typename T>
+int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, const void *a0,
+          const void *aref, const void *D, const void *a, const void *abar, void *a0bar,
+          void *arefbar, void *Jbar, void *Dbar, void *Mbar, hipStream_t stream) {
+    const T *fac = static_cast<const T *>(state);
+    const uint8_t *mask =
+        static_cast<const uint8_t *>(state) + align256(hb.s * (size_t)hb.tot_nn);
+    const int sm = choose_small(hb);
+    if (sm < 0) return sm;
+    if (sm == 1) {
+        return cs::launch_small_vjp<T>(hb.bv, hb.nmax, hb.mmax, fac, mask, (const T *)M,
+                                       (const T *)J, (const T *)a0, (const T *)aref,
+                                       (const T *)D, (const T *)a, (const T *)abar, (T *)a0bar,
+                                       (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, stream);
+    }
+    const int NT = generic_nt(hb);
+    const size_t lds = cs::gen_lds_bytes(hb.nmax, hb.mmax, NT, hb.s);
+    int rc;
+    if (NT == 64) {
+        auto k = cs::k_ift_vjp_generic<T, 64>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, hb.nmax,
+                           hb.mmax, fac, mask, (const T *)M, (const T *)J, (const T *)a0,
+                           (const T *)aref, (const T *)D, (const T *)a, (const T *)abar,
+                           (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar);
+    } else {
+        auto k = cs::k_ift_vjp_generic<T, 256>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, hb.nmax,
+                           hb.mmax, fac, mask, (const T *)M, (const T *)J, (const T *)a0,
+                           (const T *)aref, (const T *)D, (const T *)a, (const T *)abar,
+                           (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar);
+    }
+    return launch_status();
+}
+
+template <typename T>
+int unrolled_t(const HostBatch &hb, const cs_solver_params *p, const void *M, const void *J,
+               const void *a0, const void *aref, const void *D, const void *abar, void *a_out,
+               void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar, void *tape,
+               int32_t *status, int32_t *iters, hipStream_t stream) {
+    const int K = p->max_iter;
+    T *tT = static_cast<T *>(tape);
+    uint8_t *tB = static_cast<uint8_t *>(tape) + align256(hb.s * tape_T_elems(hb, K));
+    const int sm = choose_small_unrolled(hb);
+    if (sm < 0) return sm;
+    if (sm == 1) {
+        return cs::launch_small_unrolled<T>(hb.bv, hb.nmax, hb.mmax, K, (T)p->tol, (const T *)M,
+                                            (const T *)J, (const T *)a0, (const T *)aref,
+                                            (const T *)D, (const T *)abar, (T *)a_out,
+                                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar,
+                                            (T *)Mbar, tT, tB, status, iters, stream);
+    }
+    const int NT = generic_nt(hb);
+    const size_t lds = cs::gen_lds_bytes(hb.nmax, hb.mmax, NT, hb.s);
+    int rc;
+    if (NT == 64) {
+        auto k = cs::k_unrolled_generic<T, 64>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, K, (T)p->tol,
+                           hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
+                           (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
+                           (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,
+                           status, iters);
+    } else {
+        auto k = cs::k_unrolled_generic<T, 256>;
+        if ((rc = prepare(k, lds)) != CS_OK) return rc;
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, K, (T)p->tol,
+                           hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
+                           (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
+                           (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,
+                           status, iters);
+    }
+    return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+int cs_version(void) { return kAbiVersion; }
+
+const char *cs_strerror(int code) {
+    switch (code) {
+    case CS_OK: return "ok";
+    case CS_EINVAL: return "invalid argument";
+    case CS_ENOSPC: return "caller buffer too small";
+    case CS_EHIP: return "HIP launch error";
+    case CS_EUNSUPPORTED: return "unsupported shape";
+    default: return "unknown error";
+    }
+}
+
+size_t cs_state_bytes(const cs_batch *batch) {
+    HostBatch hb;
+    if (describe(batch, hb) != CS_OK) return 0;
+    return state_bytes(hb);
+}
+
+size_t cs_unrolled_tape_bytes(const cs_batch *batch, int32_t K) {
+    HostBatch hb;
+    if (K < 0 || describe(batch, hb) != CS_OK) return 0;
+    return tape_bytes(hb, K);
+}
+
+int cs_forward(const cs_batch *batch, const cs_solver_params *params, const void *M,
+               const void *J, const void *a0, const void *aref, const void *D,
+               const void *a_init, void *a_out, void *state, size_t state_bytes_given,
+               int32_t *status, int32_t *iters, void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = check_params(params)) != CS_OK) return rc;
+    if (hb.B == 0) return CS_OK;
+    if (!M || !a0 || !a_out || !state || !status) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hb.dtype == CS_F32)
+        return forward_t<float>(hb, params, M, J, a0, aref, D, a_init, a_out, state, status,
+                                iters, s);
+    return forward_t<double>(hb, params, M, J, a0, aref, D, a_init, a_out, state, status, iters,
+                             s);
+}
+
+int cs_ift_vjp(const cs_batch *batch, const void *state, size_t state_bytes_given, const void *M,
+               const void *J, const void *a0, const void *aref, const void *D, const void *a,
+               const void *abar, void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar,
+               void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if (hb.B == 0) return CS_OK;
+    if (!state || !M || !a0 || !a || !abar) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hb.dtype == CS_F32)
+        return vjp_t<float>(hb, state, M, J, a0, aref, D, a, abar, a0bar, arefbar, Jbar, Dbar,
+                            Mbar, s);
+    return vjp_t<double>(hb, state, M, J, a0, aref, D, a, abar, a0bar, arefbar, Jbar, Dbar, Mbar,
+                         s);
+}
+
+int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                    const void *J, const void *a0, const void *aref, const void *D,
+                    const void *abar, void *a_out, void *a0bar, void *arefbar, void *Jbar,
+                    void *Dbar, void *Mbar, void *tape, size_t tape_bytes_given,
+                    int32_t *status, int32_t *iters, void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = check_params(params)) != CS_OK) return rc;
+    if (hb.B == 0) return CS_OK;
+    if (!M || !a0 || !abar || !a_out || !a0bar || !Mbar || !status) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D || !arefbar || !Jbar || !Dbar)) return CS_EINVAL;
+    if (params->max_iter > 0 && !tape) return CS_EINVAL;
+    if (tape_bytes_given < tape_bytes(hb, params->max_iter)) return CS_ENOSPC;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hb.dtype == CS_F32)
+        return unrolled_t<float>(hb, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar,
+                                 Jbar, Dbar, Mbar, tape, status, iters, s);
+    return unrolled_t<double>(hb, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
+                              Dbar, Mbar, tape, status, iters, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+"""Shared helpers of the GPU parity tests (HIP path vs FP64 oracle)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2607_24959_amd import solver, synth
+
+KEYS = ("M", "J", "a0", "aref", "D")
+GKEYS = ("a0", "aref", "J", "D", "M")
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def np64(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def gpu_uniform(b: synth.UniformBatch, dtype, max_iter, tol, vjp=True, order=None, path=0):
+    batch = solver.Batch.uniform(b.B, b.n, b.m, dtype, order=order, path=path)
+    t = {k: dev(getattr(b, k), dtype) for k in KEYS + ("abar",)}
+    sol = solver.forward(batch, *(t[k] for k in KEYS), max_iter=max_iter, tol=tol)
+    out = dict(a=sol.a, status=sol.status, iters=sol.iters, state=sol.state)
+    if vjp:
+        g = solver.ift_vjp(batch, sol, *(t[k] for k in KEYS), t["abar"])
+        out.update(zip(GKEYS, g))
+    torch.cuda.synchronize()
+    res = {k: (np64(v) if v.dtype.is_floating_point else v.cpu().numpy()) for k, v in out.items()
+           if k != "state"}
+    sb = batch.state_bytes()
+    al = (4 if dtype == torch.float32 else 8) * b.B * b.n * b.n
+    al = (al + 255) // 256 * 256
+    res["active"] = sol.state[al:al + b.B * b.m].cpu().numpy().reshape(b.B, b.m).astype(bool)
+    assert sol.state.numel() >= sb
+    return res
+
+
+def gpu_unrolled_uniform(b: synth.UniformBatch, dtype, K, tol, path=0):
+    batch = solver.Batch.uniform(b.B, b.n, b.m, dtype, path=path)
+    t = {k: dev(getattr(b, k), dtype) for k in KEYS + ("abar",)}
+    out = solver.unrolled_vjp(batch, *(t[k] for k in KEYS), t["abar"], K=K, tol=tol)
+    torch.cuda.synchronize()
+    return {k: (np64(v) if isinstance(v, torch.Tensor) and v.dtype.is_floating_point else
+                (v.cpu().numpy() if isinstance(v, torch.Tensor) else v)) for k, v in out.items()}
+
+
+def oracle_uniform(b64: synth.UniformBatch, max_iter, tol, vjp=True):
+    P = oracle.Packed.uniform(b64.M, b64.J, b64.a0, b64.aref, b64.D, b64.abar)
+    fw = P.forward(max_iter=max_iter, tol=tol)
+    out = dict(a=fw["a"].reshape(b64.B, b64.n), status=fw["status"], iters=fw["iters"],
+               active=fw["active"][:b64.B * b64.m].reshape(b64.B, b64.m).astype(bool))
+    if vjp:
+        g = P.ift_vjp(fw["a"], fw["active"])
+        out.update(a0=g["a0"], aref=g["aref"], J=g["J"], D=g["D"], M=g["M"])
+    return out
+
+
+def oracle_unrolled_uniform(b64: synth.UniformBatch, K, tol):
+    P = oracle.Packed.uniform(b64.M, b64.J, b64.a0, b64.aref, b64.D, b64.abar)
+    return P.unrolled_vjp(K=K, tol=tol)
+
+
+def rel_rows(x, ref, B):
+    """Per-instance norm-wise relative error of two [B, ...] arrays."""
+    x = np.asarray(x).reshape(B, -1)
+    ref = np.asarray(ref).reshape(B, -1)
+    num = np.linalg.norm(x - ref, axis=1)
+    den = np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+    return num / den
+
+
+def margins(b64: synth.UniformBatch, a):
+    """Relative distance of each row's residual from the cone boundary at a."""
+    a = a.reshape(b64.B, b64.n)
+    r = np.einsum("bij,bj->bi", b64.J, a) - b64.aref
+    scale = np.abs(b64.aref) + np.einsum("bij,bj->bi", np.abs(b64.J), np.abs(a)) + 1e-300
+    return np.abs(r) / scale
