@@ -88,7 +88,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * 2 ** 20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (instances are "
               "independent, so a multi-GPU run would be B/G instances per GPU at the same "
@@ -146,8 +158,7 @@ def main():
     st = bufs[0][1].status.cpu().numpy()
     it = bufs[0][1].iters.cpu().numpy()
     sb = batch.state_bytes()
-    al = (4 * B * NV * NV + 255) // 256 * 256
-    act = bufs[0][1].state[al:al + B * M_ROWS].cpu().numpy().reshape(B, M_ROWS).sum(1)
+    act = batch.active_sets(bufs[0][1]).reshape(B, M_ROWS).sum(1)
     flops_per_launch = float(np.sum(forward_flops(NV, M_ROWS, act, it)))
     fwd_s = float(np.mean(t_fwd)) / 1e3
     vjp_s = float(np.mean(t_vjp)) / 1e3

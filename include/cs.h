@@ -101,11 +101,16 @@ typedef struct cs_solver_params {
 } cs_solver_params;
 
 /* Bytes of the `state` buffer cs_forward writes and cs_ift_vjp reads: the
- * Cholesky factor of H(A*) (n x n slot per instance, lower triangle used) and
- * the active set A* (one byte per row).  0 on invalid arguments. */
+ * Cholesky factor of H(A*) as a packed lower triangle per instance (n (n+1)/2
+ * values, instance i at element (off_nn[i] + off_n[i]) / 2), then, 256-byte
+ * aligned, the active set A* (one byte per row, instance i at off_m[i]).
+ * 0 on invalid arguments. */
 size_t cs_state_bytes(const cs_batch *batch);
 
-/* Bytes of the tape cs_unrolled_vjp needs for K recorded steps. */
+/* Bytes of the tape cs_unrolled_vjp needs for K recorded steps: per instance
+ * and step (a_k, p_k, the packed factor of H_k, r_k, q_k, alpha_k, c_k) in the
+ * batch's dtype plus the step's active set and line-search piece (one byte per
+ * row each).  Grows linearly in K. */
 size_t cs_unrolled_tape_bytes(const cs_batch *batch, int32_t K);
 
 /* Forward solve (Sec. III-B): from a_init (a0 when NULL) take Newton steps

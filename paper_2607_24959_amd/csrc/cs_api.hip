@@ -78,12 +78,15 @@ int describe(const cs_batch *b, HostBatch &hb) {
     return CS_OK;
 }
 
+// Packed lower triangles: sum_i n_i (n_i + 1) / 2 = (total_nn + total_n) / 2.
+size_t factor_elems(const HostBatch &hb) { return (size_t)(hb.tot_nn + hb.tot_n) / 2; }
+
 size_t state_bytes(const HostBatch &hb) {
-    return align256(hb.s * (size_t)hb.tot_nn) + (size_t)hb.tot_m;
+    return align256(hb.s * factor_elems(hb)) + (size_t)hb.tot_m;
 }
 
 size_t tape_T_elems(const HostBatch &hb, int K) {
-    return (size_t)K * (2 * (size_t)hb.tot_n + (size_t)hb.tot_nn + 2 * (size_t)hb.tot_m +
+    return (size_t)K * (2 * (size_t)hb.tot_n + factor_elems(hb) + 2 * (size_t)hb.tot_m +
                         2 * (size_t)hb.B);
 }
 
@@ -139,7 +142,7 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
               const void *a0, const void *aref, const void *D, const void *a_init, void *a_out,
               void *state, int32_t *status, int32_t *iters, hipStream_t stream) {
     T *fac = static_cast<T *>(state);
-    uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * (size_t)hb.tot_nn);
+    uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int sm = choose_small(hb);
     if (sm < 0) return sm;
     if (sm == 1) {
@@ -175,7 +178,7 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
           void *arefbar, void *Jbar, void *Dbar, void *Mbar, hipStream_t stream) {
     const T *fac = static_cast<const T *>(state);
     const uint8_t *mask =
-        static_cast<const uint8_t *>(state) + align256(hb.s * (size_t)hb.tot_nn);
+        static_cast<const uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int sm = choose_small(hb);
     if (sm < 0) return sm;
     if (sm == 1) {

@@ -55,6 +55,25 @@ __device__ inline Inst inst_at(const BatchView &bv, int w) {
     return I;
 }
 
+// Layouts shared by every kernel family.
+//  state: factor region, instance i's Cholesky factor of H(A*) as a packed
+//  lower triangle (entry (j, l), l <= j, at j (j + 1) / 2 + l) starting at
+//  element (off_nn[i] + off_n[i]) / 2 = sum_{b < i} n_b (n_b + 1) / 2; then
+//  (256-byte aligned) one byte of A* per row at off_m[i].
+//  tape: T region, instance i's K records start at element
+//  K (2 off_n + (off_nn + off_n) / 2 + 2 off_m + 2 i), each record being
+//  [a_k (n) | p_k (n) | L_k (n (n + 1) / 2) | r_k (m) | q_k (m) | alpha_k | c_k];
+//  byte region (256-byte aligned after it): K records [A_k (m) | A'_k (m)]
+//  at K 2 off_m[i].
+__host__ __device__ inline int64_t rec_T_elems(int n, int m) {
+    return 2 * (int64_t)n + (int64_t)n * (n + 1) / 2 + 2 * (int64_t)m + 2;
+}
+__device__ inline int64_t fac_offset(const Inst &I) { return (I.onn + I.on) / 2; }
+__device__ inline int64_t tape_T_offset(const Inst &I, int K) {
+    return (int64_t)K * (2 * I.on + (I.onn + I.on) / 2 + 2 * I.om + 2 * (int64_t)I.b);
+}
+__device__ inline int64_t tape_B_offset(const Inst &I, int K) { return (int64_t)K * 2 * I.om; }
+
 template <typename T> __device__ inline T inf_val();
 template <> __device__ inline float inf_val<float>() { return __builtin_huge_valf(); }
 template <> __device__ inline double inf_val<double>() { return __builtin_huge_val(); }

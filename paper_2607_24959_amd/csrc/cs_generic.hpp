@@ -217,10 +217,11 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
         const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
         const T nanv = T(__builtin_nan(""));
         for (int j = tid; j < n; j += NT) gaout[I.on + j] = ok ? L.a[j] : nanv;
+        T *fac = gfac + fac_offset(I);
         for (int e = tid; e < n * n; e += NT) {
             const int j = e / n, l = e - (e / n) * n;
-            if (l < j) gfac[I.onn + e] = ok ? L.H[e] : nanv;
-            else if (l == j) gfac[I.onn + e] = ok ? L.diag[j] : nanv;
+            if (l < j) fac[j * (j + 1) / 2 + l] = ok ? L.H[e] : nanv;
+            else if (l == j) fac[j * (j + 1) / 2 + l] = ok ? L.diag[j] : nanv;
         }
         for (int i = tid; i < m; i += NT) gmask[I.om + i] = ok ? L.A[i] : 0;
         if (tid == 0) {
@@ -247,10 +248,11 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
         const Inst I = inst_at(bv, w);
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn, *aref = garef + I.om, *D = gD + I.om;
+        const T *fac = gfac + fac_offset(I);
         for (int e = tid; e < n * n; e += NT) {
             const int j = e / n, l = e - (e / n) * n;
-            if (l < j) L.H[e] = gfac[I.onn + e];
-            else if (l == j) L.diag[j] = gfac[I.onn + e];
+            if (l < j) L.H[e] = fac[j * (j + 1) / 2 + l];
+            else if (l == j) L.diag[j] = fac[j * (j + 1) / 2 + l];
         }
         for (int j = tid; j < n; j += NT) {
             L.a[j] = ga[I.on + j];
@@ -321,11 +323,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
 
 // Unrolled VJP ----------------------------------------------------------------
 //
-// Tape layout.  T region: instance i starts at element
-//   K (2 off_n + off_nn + 2 off_m + 2 i)
-// and holds K records [a_k (n) | p_k (n) | L_k (n x n, diagonal in place) |
-// r_k (m) | q_k (m) | alpha_k | c_k].  Byte region (after the T region,
-// 256-byte aligned): instance i at K 2 off_m, records [A_k (m) | A'_k (m)].
+// Tape layout: see the comment above rec_T_elems in cs_device.hpp.
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_unrolled_generic(
@@ -345,9 +343,10 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 *D = gD + I.om;
         T *a0bar = ga0bar + I.on, *arefbar = garefbar + I.om, *Jbar = gJbar + I.omn,
           *Dbar = gDbar + I.om, *Mbar = gMbar + I.onn;
-        const size_t recT = 2 * (size_t)n + (size_t)n * n + 2 * (size_t)m + 2;
-        T *tT = tapeT + (size_t)K * (2 * I.on + I.onn + 2 * I.om + 2 * (int64_t)I.b);
-        uint8_t *tB = tapeB + (size_t)K * 2 * I.om;
+        const int ne = n * (n + 1) / 2;
+        const size_t recT = (size_t)rec_T_elems(n, m);
+        T *tT = tapeT + tape_T_offset(I, K);
+        uint8_t *tB = tapeB + tape_B_offset(I, K);
 
         // zero the accumulated gradients
         for (int j = tid; j < n; j += NT) a0bar[j] = T(0);
@@ -441,17 +440,18 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 }
                 for (int e = tid; e < n * n; e += NT) {
                     const int j = e / n, l = e - (e / n) * n;
-                    rec[2 * n + e] = (l < j) ? L.H[e] : (l == j ? L.diag[j] : T(0));
+                    if (l < j) rec[2 * n + j * (j + 1) / 2 + l] = L.H[e];
+                    else if (l == j) rec[2 * n + j * (j + 1) / 2 + l] = L.diag[j];
                 }
                 for (int i = tid, jj = 0; i < m; i += NT, ++jj) {
-                    rec[2 * n + n * n + i] = L.r[i];
-                    rec[2 * n + n * n + m + i] = L.q[i];
+                    rec[2 * n + ne + i] = L.r[i];
+                    rec[2 * n + ne + m + i] = L.q[i];
                     recB[i] = L.A[i];
                     recB[m + i] = (bits >> jj) & 1u;
                 }
                 if (tid == 0) {
-                    rec[2 * n + n * n + 2 * m] = alpha;
-                    rec[2 * n + n * n + 2 * m + 1] = cpiece;
+                    rec[2 * n + ne + 2 * m] = alpha;
+                    rec[2 * n + ne + 2 * m + 1] = cpiece;
                 }
                 step_inf = T(0);
                 for (int j = 0; j < n; ++j) step_inf = fmax(step_inf, fabs(alpha * L.p[j]));
@@ -489,16 +489,16 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
         for (int k = (ok ? steps : 0) - 1; k >= 0; --k) {
             const T *rec = tT + (size_t)k * recT;
             const uint8_t *recB = tB + (size_t)k * 2 * m;
-            const T *rr = rec + 2 * n + n * n, *rq = rr + m;
-            const T alpha = rec[2 * n + n * n + 2 * m], c = rec[2 * n + n * n + 2 * m + 1];
+            const T *rr = rec + 2 * n + ne, *rq = rr + m;
+            const T alpha = rec[2 * n + ne + 2 * m], c = rec[2 * n + ne + 2 * m + 1];
             for (int j = tid; j < n; j += NT) {
                 L.a[j] = rec[j];
                 L.p[j] = rec[n + j];
             }
             for (int e = tid; e < n * n; e += NT) {
                 const int j = e / n, l = e - (e / n) * n;
-                if (l < j) L.H[e] = rec[2 * n + e];
-                else if (l == j) L.diag[j] = rec[2 * n + e];
+                if (l < j) L.H[e] = rec[2 * n + j * (j + 1) / 2 + l];
+                else if (l == j) L.diag[j] = rec[2 * n + j * (j + 1) / 2 + l];
             }
             for (int i = tid; i < m; i += NT) {
                 L.r[i] = rr[i];

@@ -2,12 +2,15 @@
 //
 // Mapping: a group of 16 lanes (one DPP row) owns one instance, so a wave
 // solves four instances and a 256-thread workgroup sixteen.  Lane g of a group
-// keeps rows i = g + 16 jj (jj < R) of J, aref, D, r, q in registers.  Every
-// lane also keeps the whole lower triangle of M and of the Newton matrix
-// (NP (NP + 1) / 2 values) and factors/solves it redundantly, so the only
-// cross-lane traffic is the 16-lane all-reduce of row sums (four DPP adds per
-// value).  n <= NP is handled by padding: padded coordinates have zero J
-// columns, unit mass and a0 = a = 0, so they stay exactly zero.
+// owns the contiguous block of rows g R .. g R + R - 1 of J, aref, D, r, q and
+// keeps it in registers; a block of a J row-major matrix is contiguous, so it
+// is read (and J-bar written) with 16-byte vector accesses.  Every lane also
+// keeps the lower triangle of M and of the Newton matrix (NP (NP + 1) / 2
+// values) and factors/solves it redundantly, so the only cross-lane traffic is
+// the 16-lane all-reduce of row sums (four DPP adds per value).  n <= NP is
+// handled by padding: padded coordinates have zero J columns, unit mass and
+// a0 = a = 0, so they stay exactly zero.  Rows past m have J = D = aref = 0,
+// so they are never active and contribute nothing.
 //
 // The all-reduce gives every lane of a group bit-identical totals (each DPP
 // step adds the same two partials, only commuted), so every branch below is
@@ -37,6 +40,17 @@ template <> __device__ inline double gsum16<double>(double v) {
     return v;
 }
 
+template <typename T> __device__ inline T fast_rsq(T x);
+template <> __device__ inline float fast_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ inline double fast_rsq<double>(double x) { return 1.0 / sqrt(x); }
+template <typename T> __device__ inline T fast_rcp(T x);
+template <> __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double fast_rcp<double>(double x) { return 1.0 / x; }
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); static constexpr int V = 4; };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int V = 2; };
+
 template <int NP> struct Tri {
     static constexpr int NE = NP * (NP + 1) / 2;
     __host__ __device__ static constexpr int idx(int j, int l) { return j * (j + 1) / 2 + l; }  // l <= j
@@ -53,9 +67,8 @@ __device__ inline bool reg_cholesky(T (&H)[Tri<NP>::NE], T (&inv)[NP]) {
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= H[Tri<NP>::idx(j, k)] * H[Tri<NP>::idx(j, k)];
         ok = ok && (s > T(0));
-        const T d = sqrt(s);
-        H[Tri<NP>::idx(j, j)] = d;
-        const T iv = T(1) / d;
+        const T iv = fast_rsq(s);
+        H[Tri<NP>::idx(j, j)] = s * iv;
         inv[j] = iv;
 #pragma unroll
         for (int i = j + 1; i < NP; ++i) {
@@ -101,66 +114,197 @@ __device__ inline void sym_mv(const T (&Ml)[Tri<NP>::NE], const T (&v)[NP], T (&
     }
 }
 
-// Per-group instance context: loads of one instance into registers.
+// Load CNT contiguous values starting at p; 16-byte vectors when `vec`,
+// otherwise element by element (elements past `live` read as 0).
+template <typename T, int CNT>
+__device__ inline void load_run(const T *__restrict__ p, bool vec, int live, T (&out)[CNT]) {
+    constexpr int V = Vec16<T>::V;
+    if constexpr (CNT % V == 0) {
+        if (vec) {
+            typedef typename Vec16<T>::type VT;
+            const VT *pv = reinterpret_cast<const VT *>(p);
+#pragma unroll
+            for (int v = 0; v < CNT / V; ++v) {
+                const VT x = pv[v];
+#pragma unroll
+                for (int e = 0; e < V; ++e) out[v * V + e] = x[e];
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CNT; ++e) out[e] = e < live ? p[e] : T(0);
+}
+
+template <typename T, int CNT>
+__device__ inline void store_run(T *__restrict__ p, bool vec, int live, const T (&in)[CNT]) {
+    constexpr int V = Vec16<T>::V;
+    if constexpr (CNT % V == 0) {
+        if (vec) {
+            typedef typename Vec16<T>::type VT;
+            VT *pv = reinterpret_cast<VT *>(p);
+#pragma unroll
+            for (int v = 0; v < CNT / V; ++v) {
+                VT x;
+#pragma unroll
+                for (int e = 0; e < V; ++e) x[e] = in[v * V + e];
+                pv[v] = x;
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CNT; ++e)
+        if (e < live) p[e] = in[e];
+}
+
+__device__ inline bool aligned16(const void *p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Per-group instance context: one instance's data in registers.
 template <typename T, int NP, int R>
 struct SmallInst {
-    int n, m;
+    int n, m, i0;        // i0: first row of this lane's block
+    bool full;           // this lane's block is R full rows of width NP
     T J[R][NP];
     T aref[R], D[R];
     T Ml[Tri<NP>::NE];
     T a0[NP];
     bool bad;
 
-    __device__ inline void load(const Inst &I, int g, const T *__restrict__ gM, const T *__restrict__ gJ,
-                                const T *__restrict__ ga0, const T *__restrict__ garef,
-                                const T *__restrict__ gD) {
+    __device__ inline void load(const Inst &I, int g, const T *__restrict__ gM,
+                                const T *__restrict__ gJ, const T *__restrict__ ga0,
+                                const T *__restrict__ garef, const T *__restrict__ gD) {
         n = I.n;
         m = I.m;
+        i0 = g * R;
+        full = (n == NP) && (i0 + R <= m);
         bad = false;
-        const T *Jb = gJ + I.omn;
+        const T *Jb = gJ + I.omn + (int64_t)i0 * n;
+        if (full) {
+            T flat[R * NP];
+            load_run<T, R * NP>(Jb, aligned16(Jb), R * NP, flat);
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) J[jj][j] = flat[jj * NP + j];
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+                for (int j = 0; j < NP; ++j)
+                    J[jj][j] = (i0 + jj < m && j < n) ? Jb[(int64_t)jj * n + j] : T(0);
+        }
+        const int live = m - i0;
+        const T *ar = garef + I.om + i0, *dd = gD + I.om + i0;
+        load_run<T, R>(ar, live >= R && aligned16(ar), live, aref);
+        load_run<T, R>(dd, live >= R && aligned16(dd), live, D);
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) {
-            const int i = g + SG * jj;
-            const bool live = i < m;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                T x = (live && j < n) ? Jb[(size_t)i * n + j] : T(0);
-                bad |= !finite_val(x);
-                J[jj][j] = x;
-            }
-            aref[jj] = live ? garef[I.om + i] : T(0);
-            D[jj] = live ? gD[I.om + i] : T(0);
             bad |= !finite_val(aref[jj]) || !finite_val(D[jj]);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) bad |= !finite_val(J[jj][j]);
         }
         const T *Mb = gM + I.onn;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
 #pragma unroll
             for (int l = 0; l <= j; ++l) {
-                T x = (j < n && l < n) ? Mb[j * n + l] : (j == l ? T(1) : T(0));
+                const T x = (j < n) ? Mb[j * n + l] : (j == l ? T(1) : T(0));
                 bad |= !finite_val(x);
                 Ml[Tri<NP>::idx(j, l)] = x;
             }
             a0[j] = j < n ? ga0[I.on + j] : T(0);
             bad |= !finite_val(a0[j]);
         }
-        // every lane checked a different part of J; the group agrees on `bad`
-        T flag = bad ? T(1) : T(0);
-        bad = gsum16(flag) != T(0);
+        bad = gsum16(bad ? T(1) : T(0)) != T(0);
     }
 };
 
+// Where one instance's unrolled-trace records go (unused when not taping).
+template <typename T>
+struct StepTape {
+    T *tT;          // this instance's T records
+    uint8_t *tB;    // this instance's byte records
+    int n, m, recT;
+};
+
+// Exact line search along p in registers (Sec. III-B, eq. 10); the method is
+// the safeguarded piece Newton of team_line_search in cs_device.hpp.  Returns
+// alpha; the accepted piece's rows (bits) and slope c are returned for the tape.
+template <typename T, int R>
+__device__ inline T small_line_search(const T (&r)[R], const T (&q)[R], const T (&D)[R], T c0, T b0,
+                                      uint32_t &bits_out, T &c_out, int &fail) {
+    T dqq[R], dqr[R];
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+        const T dq = D[jj] * q[jj];
+        dqq[jj] = dq * q[jj];
+        dqr[jj] = dq * r[jj];
+    }
+    auto piece = [&](T t, uint32_t &bits, T &c, T &b) {
+        T sc = T(0), sb = T(0);
+        uint32_t bb = 0;
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            const bool pa = r[jj] + t * q[jj] < T(0);
+            sc += pa ? dqq[jj] : T(0);
+            sb += pa ? dqr[jj] : T(0);
+            bb |= (pa ? 1u : 0u) << jj;
+        }
+        c = c0 + gsum16(sc);
+        b = b0 + gsum16(sb);
+        bits = bb;
+    };
+    T t = T(1), c, b;
+    uint32_t bits;
+    piece(t, bits, c, b);
+    T lo = T(0), hi = inf_val<T>();
+    T alpha = t;
+    fail = 1;
+    const T eps = T(sizeof(T) == 4 ? 1.1920929e-7 : 2.220446049250313e-16);
+    for (int it = 0; it < 96; ++it) {
+        const T gp = c * t + b;
+        if (gp == T(0)) { alpha = t; fail = 0; break; }
+        if (gp < T(0)) lo = t; else hi = t;
+        if (hi < inf_val<T>() && hi - lo <= T(32) * eps * hi) { alpha = t; fail = 0; break; }
+        T cand = -b * fast_rcp(c);
+        const bool newton = (cand > lo) && (cand < hi);
+        if (!newton) cand = (hi < inf_val<T>()) ? T(0.5) * (lo + hi) : T(2) * lo + T(1);
+        uint32_t nb;
+        T nc, nbv;
+        piece(cand, nb, nc, nbv);
+        const T mism = gsum16(T(__builtin_popcount(nb ^ bits)));
+        bits = nb;
+        c = nc;
+        b = nbv;
+        t = cand;
+        alpha = cand;
+        if (newton && mism == T(0)) { fail = 0; break; }
+    }
+    bits_out = bits;
+    c_out = c;
+    return alpha;
+}
+
 // One Newton solve of the group's instance.  On return a holds the iterate,
 // H/inv the Cholesky factor of H(A(a)) (valid when st has CONVERGED/MAXITER)
-// and act the active rows of this lane.
-template <typename T, int NP, int R>
-__device__ inline int small_solve(SmallInst<T, NP, R> &S, int max_iter, T tol, T (&a)[NP],
-                                  T (&H)[Tri<NP>::NE], T (&inv)[NP], bool (&act)[R], int &iters) {
+// and act the active rows of this lane.  When TAPE, every step taken is
+// recorded in tp (the unrolled VJP's K is max_iter).
+template <bool TAPE, typename T, int NP, int R>
+__device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T tol, T (&a)[NP],
+                                  T (&H)[Tri<NP>::NE], T (&inv)[NP], bool (&act)[R], int &iters,
+                                  const StepTape<T> &tp) {
+    constexpr int NE = Tri<NP>::NE;
+    const int g = threadIdx.x & (SG - 1);
     iters = 0;
-    {   // M must be positive definite
-        T Hc[Tri<NP>::NE];
 #pragma unroll
-        for (int e = 0; e < Tri<NP>::NE; ++e) Hc[e] = S.Ml[e];
+    for (int jj = 0; jj < R; ++jj) act[jj] = false;
+    {   // M must be positive definite
+        T Hc[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) Hc[e] = S.Ml[e];
         if (!reg_cholesky<T, NP>(Hc, inv)) return ST_NOTSPD;
     }
     T trM = T(0);
@@ -169,12 +313,10 @@ __device__ inline int small_solve(SmallInst<T, NP, R> &S, int max_iter, T tol, T
     trM -= T(NP - S.n);   // padded coordinates carry unit mass
     T step_inf = T(-1);
     int st = 0, lsfail = 0;
-    T r[R];
-#pragma unroll
-    for (int jj = 0; jj < R; ++jj) act[jj] = false;
+    bool have_factor = false;
     for (int k = 0;; ++k) {
-        // residual, active set, gradient (eq. 6)
-        T d[NP], F[NP], w[R];
+        // residual, active set and gradient (eq. 6)
+        T d[NP], F[NP], r[R], wD[R];
         bool changed = false;
 #pragma unroll
         for (int j = 0; j < NP; ++j) d[j] = a[j] - S.a0[j];
@@ -184,39 +326,47 @@ __device__ inline int small_solve(SmallInst<T, NP, R> &S, int max_iter, T tol, T
 #pragma unroll
             for (int j = 0; j < NP; ++j) s += S.J[jj][j] * a[j];
             r[jj] = s - S.aref[jj];
-            const bool live = (int)(threadIdx.x & (SG - 1)) + SG * jj < S.m;
-            const bool an = live && r[jj] < T(0);
+            const bool an = r[jj] < T(0);
             changed |= an != act[jj];
             act[jj] = an;
-            w[jj] = an ? S.D[jj] * r[jj] : T(0);
+            wD[jj] = an ? S.D[jj] : T(0);
         }
         sym_mv<T, NP>(S.Ml, d, F);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             T s = T(0);
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * w[jj];
+            for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * (wD[jj] * r[jj]);
             F[j] += gsum16(s);
         }
-        const bool same = gsum16(changed ? T(1) : T(0)) == T(0);
+        const bool same = (k > 0) && gsum16(changed ? T(1) : T(0)) == T(0);
         T g2 = T(0), anorm = T(0);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             g2 += F[j] * F[j];
             anorm = fmax(anorm, fabs(a[j]));
         }
-        // Newton matrix (eq. 9) -- assembled every pass, also for the state
+        // Newton matrix (eq. 9); it depends on the active set only, so an
+        // unchanged set keeps the previous factor
+        if (!(same && have_factor)) {
+            T tj[R][NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
+            for (int jj = 0; jj < R; ++jj)
 #pragma unroll
-            for (int l = 0; l <= j; ++l) {
-                T s = T(0);
+                for (int j = 0; j < NP; ++j) tj[jj][j] = wD[jj] * S.J[jj][j];
 #pragma unroll
-                for (int jj = 0; jj < R; ++jj) s += (act[jj] ? S.D[jj] : T(0)) * S.J[jj][j] * S.J[jj][l];
-                H[Tri<NP>::idx(j, l)] = S.Ml[Tri<NP>::idx(j, l)] + gsum16(s);
+            for (int j = 0; j < NP; ++j) {
+#pragma unroll
+                for (int l = 0; l <= j; ++l) {
+                    T s = T(0);
+#pragma unroll
+                    for (int jj = 0; jj < R; ++jj) s += tj[jj][j] * S.J[jj][l];
+                    H[Tri<NP>::idx(j, l)] = S.Ml[Tri<NP>::idx(j, l)] + gsum16(s);
+                }
             }
+            if (!reg_cholesky<T, NP>(H, inv)) { st = ST_NOTSPD; break; }
+            have_factor = true;
         }
-        if (!reg_cholesky<T, NP>(H, inv)) { st = ST_NOTSPD; break; }
         if (sqrt(g2) <= tol * trM ||
             (step_inf >= T(0) && same && step_inf <= tol * (T(1) + anorm))) {
             st = ST_CONVERGED;
@@ -227,7 +377,6 @@ __device__ inline int small_solve(SmallInst<T, NP, R> &S, int max_iter, T tol, T
 #pragma unroll
         for (int j = 0; j < NP; ++j) nF[j] = -F[j];
         reg_chol_solve<T, NP>(H, inv, nF, p);
-        // exact line search (eq. 10)
         T q[R];
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) {
@@ -244,58 +393,43 @@ __device__ inline int small_solve(SmallInst<T, NP, R> &S, int max_iter, T tol, T
             c0 += p[j] * Mp[j];
             b0 += Mp[j] * d[j];
         }
-        T alpha;
-        {
-            T t = T(1), c, b;
-            uint32_t bits = 0;
-            {
-                T sc = T(0), sb = T(0);
+        uint32_t bits;
+        T cpiece;
+        int fail;
+        const T alpha = small_line_search<T, R>(r, q, S.D, c0, b0, bits, cpiece, fail);
+        lsfail |= fail;
+        if constexpr (TAPE) {
+            T *rec = tp.tT + (int64_t)k * tp.recT;
+            uint8_t *recB = tp.tB + (int64_t)k * 2 * tp.m;
+            const int n = tp.n, m = tp.m;
 #pragma unroll
-                for (int jj = 0; jj < R; ++jj) {
-                    const bool live = (int)(threadIdx.x & (SG - 1)) + SG * jj < S.m;
-                    if (live && r[jj] + t * q[jj] < T(0)) {
-                        const T dq = S.D[jj] * q[jj];
-                        sc += dq * q[jj];
-                        sb += dq * r[jj];
-                        bits |= 1u << jj;
-                    }
+            for (int j = 0; j < NP; ++j)
+                if (j == g && j < n) {
+                    rec[j] = a[j];
+                    rec[n + j] = p[j];
                 }
-                c = c0 + gsum16(sc);
-                b = b0 + gsum16(sb);
-            }
-            T lo = T(0), hi = inf_val<T>();
-            alpha = t;
-            int fail = 1;
-            const T eps = T(sizeof(T) == 4 ? 1.1920929e-7 : 2.220446049250313e-16);
-            for (int it = 0; it < 96; ++it) {
-                const T gp = c * t + b;
-                if (gp == T(0)) { alpha = t; fail = 0; break; }
-                if (gp < T(0)) lo = t; else hi = t;
-                if (hi < inf_val<T>() && hi - lo <= T(32) * eps * hi) { alpha = t; fail = 0; break; }
-                T cand = -b / c;
-                const bool newton = (cand > lo) && (cand < hi);
-                if (!newton) cand = (hi < inf_val<T>()) ? T(0.5) * (lo + hi) : T(2) * lo + T(1);
-                uint32_t nb = 0;
-                T sc = T(0), sb = T(0);
+            // factor: packed lower triangle of the n x n leading block
 #pragma unroll
-                for (int jj = 0; jj < R; ++jj) {
-                    const bool live = (int)(threadIdx.x & (SG - 1)) + SG * jj < S.m;
-                    if (live && r[jj] + cand * q[jj] < T(0)) {
-                        const T dq = S.D[jj] * q[jj];
-                        sc += dq * q[jj];
-                        sb += dq * r[jj];
-                        nb |= 1u << jj;
-                    }
+            for (int j = 0; j < NP; ++j)
+#pragma unroll
+                for (int l = 0; l <= j; ++l) {
+                    const int e = Tri<NP>::idx(j, l);
+                    if ((e & (SG - 1)) == g && j < n) rec[2 * n + e] = H[e];
                 }
-                const T mism = gsum16(T(__builtin_popcount(nb ^ bits)));
-                c = c0 + gsum16(sc);
-                b = b0 + gsum16(sb);
-                bits = nb;
-                t = cand;
-                alpha = cand;
-                if (newton && mism == T(0)) { fail = 0; break; }
+            const int ne = n * (n + 1) / 2;
+            const int live = m - S.i0;
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+                if (jj < live) {
+                    rec[2 * n + ne + S.i0 + jj] = r[jj];
+                    rec[2 * n + ne + m + S.i0 + jj] = q[jj];
+                    recB[S.i0 + jj] = act[jj] ? 1 : 0;
+                    recB[m + S.i0 + jj] = (bits >> jj) & 1u;
+                }
+            if (g == 0) {
+                rec[2 * n + ne + 2 * m] = alpha;
+                rec[2 * n + ne + 2 * m + 1] = cpiece;
             }
-            lsfail |= fail;
         }
         step_inf = T(0);
 #pragma unroll
@@ -317,6 +451,7 @@ __global__ __launch_bounds__(256) void k_forward_small(
     const T *__restrict__ gD, const T *__restrict__ gainit, T *__restrict__ gaout,
     T *__restrict__ gfac, uint8_t *__restrict__ gmask, int32_t *__restrict__ gstatus,
     int32_t *__restrict__ giters) {
+    constexpr int NE = Tri<NP>::NE;
     const int g = threadIdx.x & (SG - 1);
     const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
     if (w >= nb_inst) return;   // whole groups only: no cross-group traffic follows
@@ -331,33 +466,47 @@ __global__ __launch_bounds__(256) void k_forward_small(
         bad |= !finite_val(a[j]);
     }
     bad = gsum16(bad ? T(1) : T(0)) != T(0);
-    T H[Tri<NP>::NE], inv[NP];
+    T H[NE], inv[NP];
     bool act[R];
     int iters = 0, st;
     if (bad) {
         st = ST_NONFINITE;
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) act[jj] = false;
     } else {
-        st = small_solve<T, NP, R>(S, max_iter, tol, a, H, inv, act, iters);
+        st = small_solve<false, T, NP, R>(S, max_iter, tol, a, H, inv, act, iters,
+                                          StepTape<T>{nullptr, nullptr, 0, 0, 0});
     }
     const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
     const T nanv = T(__builtin_nan(""));
-    // outputs: lane j < n writes a_j; factor entries spread over the group
 #pragma unroll
     for (int j = 0; j < NP; ++j)
         if (j == g && j < S.n) gaout[I.on + j] = ok ? a[j] : nanv;
-    T *fac = gfac + I.onn;
+    T *fac = gfac + fac_offset(I);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NP; ++j)
 #pragma unroll
         for (int l = 0; l <= j; ++l) {
             const int e = Tri<NP>::idx(j, l);
-            if ((e & (SG - 1)) == g && j < S.n) fac[j * S.n + l] = ok ? H[e] : nanv;
+            if ((e & (SG - 1)) == g && j < S.n) fac[e] = ok ? H[e] : nanv;
         }
-    }
+    const int live = S.m - S.i0;
+    uint8_t *mk = gmask + I.om + S.i0;
+    if constexpr (R == 4) {
+        if (live >= 4 && (reinterpret_cast<uintptr_t>(mk) & 3u) == 0) {
+            uint32_t word = 0;
 #pragma unroll
-    for (int jj = 0; jj < R; ++jj) {
-        const int i = g + SG * jj;
-        if (i < S.m) gmask[I.om + i] = (ok && act[jj]) ? 1 : 0;
+            for (int jj = 0; jj < 4; ++jj) word |= (ok && act[jj] ? 1u : 0u) << (8 * jj);
+            *reinterpret_cast<uint32_t *>(mk) = word;
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+                if (jj < live) mk[jj] = (ok && act[jj]) ? 1 : 0;
+        }
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj)
+            if (jj < live) mk[jj] = (ok && act[jj]) ? 1 : 0;
     }
     if (g == 0) {
         gstatus[I.b] = st;
@@ -372,6 +521,7 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     const T *__restrict__ garef, const T *__restrict__ gD, const T *__restrict__ ga,
     const T *__restrict__ gabar, T *__restrict__ ga0bar, T *__restrict__ garefbar,
     T *__restrict__ gJbar, T *__restrict__ gDbar, T *__restrict__ gMbar) {
+    constexpr int NE = Tri<NP>::NE;
     const int g = threadIdx.x & (SG - 1);
     const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
     if (w >= nb_inst) return;
@@ -379,31 +529,31 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     const int n = I.n, m = I.m;
     SmallInst<T, NP, R> S;
     S.load(I, g, gM, gJ, ga0, garef, gD);
-    T L[Tri<NP>::NE], inv[NP], a[NP], ab[NP];
-    const T *fac = gfac + I.onn;
+    T L[NE], inv[NP], a[NP], ab[NP];
+    const T *fac = gfac + fac_offset(I);
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
 #pragma unroll
         for (int l = 0; l <= j; ++l)
-            L[Tri<NP>::idx(j, l)] = (j < n && l < n) ? fac[j * n + l] : (j == l ? T(1) : T(0));
-        inv[j] = T(1) / L[Tri<NP>::idx(j, j)];
+            L[Tri<NP>::idx(j, l)] = (j < n) ? fac[Tri<NP>::idx(j, l)] : (j == l ? T(1) : T(0));
+        inv[j] = fast_rcp(L[Tri<NP>::idx(j, j)]);
         a[j] = j < n ? ga[I.on + j] : T(0);
         ab[j] = j < n ? gabar[I.on + j] : T(0);
     }
+    const int live = m - S.i0;
     bool act[R];
+    {
+        const uint8_t *mk = gmask + I.om + S.i0;
 #pragma unroll
-    for (int jj = 0; jj < R; ++jj) {
-        const int i = g + SG * jj;
-        act[jj] = i < m && gmask[I.om + i] != 0;
+        for (int jj = 0; jj < R; ++jj) act[jj] = jj < live && mk[jj] != 0;
     }
-    // lambda = H^{-1} abar, one step of iterative refinement with
+    // lambda = H^{-1} abar, then one step of iterative refinement with
     // H v = M v + J^T (D o A* o J v)
     T lam[NP];
     reg_chol_solve<T, NP>(L, inv, ab, lam);
     {
-        T Ml_l[NP], res[NP], dl[NP];
-        sym_mv<T, NP>(S.Ml, lam, Ml_l);
-        T t[R];
+        T Mlam[NP], res[NP], dl[NP], t[R];
+        sym_mv<T, NP>(S.Ml, lam, Mlam);
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) {
             T s = T(0);
@@ -416,17 +566,16 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
             T s = T(0);
 #pragma unroll
             for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * t[jj];
-            res[j] = ab[j] - Ml_l[j] - gsum16(s);
+            res[j] = ab[j] - Mlam[j] - gsum16(s);
         }
         reg_chol_solve<T, NP>(L, inv, res, dl);
 #pragma unroll
         for (int j = 0; j < NP; ++j) lam[j] += dl[j];
     }
-    T *Jbar = gJbar ? gJbar + I.omn : nullptr;
+    // per-row cotangents
+    T arb[R], db[R], Jb[R * NP];
 #pragma unroll
     for (int jj = 0; jj < R; ++jj) {
-        const int i = g + SG * jj;
-        if (i >= m) continue;
         T ja = T(0), sig = T(0);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
@@ -435,13 +584,29 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
         }
         const T r = ja - S.aref[jj];
         const T wv = act[jj] ? S.D[jj] * r : T(0);
-        const T ar = act[jj] ? S.D[jj] * sig : T(0);
-        if (garefbar) garefbar[I.om + i] = ar;
-        if (gDbar) gDbar[I.om + i] = act[jj] ? -r * sig : T(0);
-        if (Jbar) {
+        arb[jj] = act[jj] ? S.D[jj] * sig : T(0);
+        db[jj] = act[jj] ? -r * sig : T(0);
 #pragma unroll
-            for (int j = 0; j < NP; ++j)
-                if (j < n) Jbar[(size_t)i * n + j] = -(wv * lam[j] + ar * a[j]);
+        for (int j = 0; j < NP; ++j) Jb[jj * NP + j] = -(wv * lam[j] + arb[jj] * a[j]);
+    }
+    if (garefbar) {
+        T *p = garefbar + I.om + S.i0;
+        store_run<T, R>(p, live >= R && aligned16(p), live, arb);
+    }
+    if (gDbar) {
+        T *p = gDbar + I.om + S.i0;
+        store_run<T, R>(p, live >= R && aligned16(p), live, db);
+    }
+    if (gJbar) {
+        T *p = gJbar + I.omn + (int64_t)S.i0 * n;
+        if (S.full) {
+            store_run<T, R * NP>(p, aligned16(p), R * NP, Jb);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+                for (int j = 0; j < NP; ++j)
+                    if (jj < live && j < n) p[(int64_t)jj * n + j] = Jb[jj * NP + j];
         }
     }
     if (ga0bar) {
@@ -453,14 +618,196 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     }
     if (gMbar) {
         T *Mb = gMbar + I.onn;
+#pragma unroll
+        for (int e = 0; e < NP * NP; ++e) {
+            const int j = e / NP, l = e % NP;
+            if ((e & (SG - 1)) == g && j < n && l < n) Mb[j * n + l] = -lam[j] * (a[l] - S.a0[l]);
+        }
+    }
+}
+
+// Unrolled VJP: the K-step solve with its tape, then the reverse sweep with
+// every cotangent accumulated in registers (J-bar rows, D-bar, aref-bar by the
+// lane owning the row; M-bar entry f by lane f mod 16).
+template <typename T, int NP, int R>
+__global__ __launch_bounds__(256) void k_unrolled_small(
+    BatchView bv, int nb_inst, int K, T tol, const T *__restrict__ gM, const T *__restrict__ gJ,
+    const T *__restrict__ ga0, const T *__restrict__ garef, const T *__restrict__ gD,
+    const T *__restrict__ gabar, T *__restrict__ gaout, T *__restrict__ ga0bar,
+    T *__restrict__ garefbar, T *__restrict__ gJbar, T *__restrict__ gDbar, T *__restrict__ gMbar,
+    T *__restrict__ tapeT, uint8_t *__restrict__ tapeB, int32_t *__restrict__ gstatus,
+    int32_t *__restrict__ giters) {
+    constexpr int NE = Tri<NP>::NE;
+    constexpr int MBL = (NP * NP + SG - 1) / SG;   // M-bar entries per lane
+    const int g = threadIdx.x & (SG - 1);
+    const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
+    if (w >= nb_inst) return;
+    const Inst I = inst_at(bv, w);
+    const int n = I.n, m = I.m;
+    SmallInst<T, NP, R> S;
+    S.load(I, g, gM, gJ, ga0, garef, gD);
+    T a[NP], ab[NP];
+    bool bad = S.bad;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        a[j] = S.a0[j];
+        ab[j] = j < n ? gabar[I.on + j] : T(0);
+        bad |= !finite_val(ab[j]);
+    }
+    bad = gsum16(bad ? T(1) : T(0)) != T(0);
+    const int ne = n * (n + 1) / 2;
+    const int recT = 2 * n + ne + 2 * m + 2;
+    const StepTape<T> tp{tapeT + tape_T_offset(I, K), tapeB + tape_B_offset(I, K), n, m, recT};
+    T H[NE], inv[NP];
+    bool act[R];
+    int steps = 0, st;
+    if (bad) {
+        st = ST_NONFINITE;
+    } else {
+        st = small_solve<true, T, NP, R>(S, K, tol, a, H, inv, act, steps, tp);
+    }
+    const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
+    const T nanv = T(__builtin_nan(""));
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+        if (j == g && j < n) gaout[I.on + j] = ok ? a[j] : nanv;
+
+    // reverse sweep
+    T Jb[R][NP], arb[R], db[R], Mb[MBL], a0b[NP];
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+        arb[jj] = T(0);
+        db[jj] = T(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) Jb[jj][j] = T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < MBL; ++e) Mb[e] = T(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) a0b[j] = T(0);
+    const int live = m - S.i0;
+    for (int k = (ok ? steps : 0) - 1; k >= 0; --k) {
+        const T *rec = tp.tT + (int64_t)k * recT;
+        const uint8_t *recB = tp.tB + (int64_t)k * 2 * m;
+        T ak[NP], p[NP], Lk[NE], iv[NP], r[R], q[R];
+        bool A[R], Ap[R];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            ak[j] = j < n ? rec[j] : T(0);
+            p[j] = j < n ? rec[n + j] : T(0);
+#pragma unroll
+            for (int l = 0; l <= j; ++l)
+                Lk[Tri<NP>::idx(j, l)] = j < n ? rec[2 * n + Tri<NP>::idx(j, l)] : (j == l ? T(1) : T(0));
+            iv[j] = fast_rcp(Lk[Tri<NP>::idx(j, j)]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            const bool lv = jj < live;
+            r[jj] = lv ? rec[2 * n + ne + S.i0 + jj] : T(0);
+            q[jj] = lv ? rec[2 * n + ne + m + S.i0 + jj] : T(0);
+            A[jj] = lv && recB[S.i0 + jj] != 0;
+            Ap[jj] = lv && recB[m + S.i0 + jj] != 0;
+        }
+        const T alpha = rec[2 * n + ne + 2 * m], c = rec[2 * n + ne + 2 * m + 1];
         T d[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) d[j] = a[j] - S.a0[j];
+        for (int j = 0; j < NP; ++j) d[j] = ak[j] - S.a0[j];
+        // a_{k+1} = a_k + alpha p with alpha = -b / c
+        T alphab = T(0);
 #pragma unroll
-        for (int j = 0; j < NP; ++j)
+        for (int j = 0; j < NP; ++j) alphab += ab[j] * p[j];
+        const T bb = -alphab / c;
+        const T cb = -alphab * alpha / c;
+        T qb[R], rb[R];
 #pragma unroll
-            for (int l = 0; l < NP; ++l)
-                if (((j * NP + l) & (SG - 1)) == g && j < n && l < n) Mb[j * n + l] = -lam[j] * d[l];
+        for (int jj = 0; jj < R; ++jj) {
+            const T dd = S.D[jj];
+            qb[jj] = Ap[jj] ? T(2) * cb * dd * q[jj] + bb * dd * r[jj] : T(0);
+            rb[jj] = Ap[jj] ? bb * dd * q[jj] : T(0);
+            db[jj] += Ap[jj] ? cb * q[jj] * q[jj] + bb * q[jj] * r[jj] : T(0);
+        }
+        T Mp[NP], Md[NP], pb[NP];
+        sym_mv<T, NP>(S.Ml, p, Mp);
+        sym_mv<T, NP>(S.Ml, d, Md);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * qb[jj];
+            pb[j] = alpha * ab[j] + T(2) * cb * Mp[j] + bb * Md[j] + gsum16(s);
+        }
+        // p = -H^{-1} g: u = H^{-1} pbar, gbar = -u, Hbar = -u p^T
+        T u[NP];
+        reg_chol_solve<T, NP>(Lk, iv, pb, u);
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            T ju = T(0);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) ju += S.J[jj][j] * u[j];
+            const T dd = S.D[jj];
+            db[jj] += A[jj] ? -ju * (q[jj] + r[jj]) : T(0);
+            rb[jj] += A[jj] ? -dd * ju : T(0);
+            const T cp = qb[jj] - (A[jj] ? dd * ju : T(0));
+            const T cu = A[jj] ? -dd * (q[jj] + r[jj]) : T(0);
+            arb[jj] -= rb[jj];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) Jb[jj][j] += cp * p[j] + cu * u[j] + rb[jj] * ak[j];
+        }
+        T Mu[NP];
+        sym_mv<T, NP>(S.Ml, u, Mu);
+#pragma unroll
+        for (int e = 0; e < MBL; ++e) {
+            const int f = g + SG * e;
+            if (f < NP * NP) {
+                const int j = f / NP, l = f % NP;
+                Mb[e] += p[j] * (cb * p[l] + bb * d[l]) - u[j] * (p[l] + d[l]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * rb[jj];
+            const T through_m = bb * Mp[j] - Mu[j];
+            ab[j] = ab[j] + through_m + gsum16(s);
+            a0b[j] -= through_m;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+        if (j == g && j < n) ga0bar[I.on + j] = ok ? a0b[j] + ab[j] : nanv;
+    {
+        T *p1 = garefbar + I.om + S.i0, *p2 = gDbar + I.om + S.i0;
+        store_run<T, R>(p1, live >= R && aligned16(p1), live, arb);
+        store_run<T, R>(p2, live >= R && aligned16(p2), live, db);
+        T *pj = gJbar + I.omn + (int64_t)S.i0 * n;
+        if (S.full) {
+            T flat[R * NP];
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) flat[jj * NP + j] = Jb[jj][j];
+            store_run<T, R * NP>(pj, aligned16(pj), R * NP, flat);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+                for (int j = 0; j < NP; ++j)
+                    if (jj < live && j < n) pj[(int64_t)jj * n + j] = Jb[jj][j];
+        }
+        T *pm = gMbar + I.onn;
+#pragma unroll
+        for (int e = 0; e < MBL; ++e) {
+            const int f = g + SG * e;
+            if (f < NP * NP) {
+                const int j = f / NP, l = f % NP;
+                if (j < n && l < n) pm[j * n + l] = Mb[e];
+            }
+        }
+    }
+    if (g == 0) {
+        gstatus[I.b] = st;
+        if (giters) giters[I.b] = steps;
     }
 }
 
@@ -487,23 +834,32 @@ inline bool small_supported(int nmax, int mmax, bool packed, int s) {
     return !packed && np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 12 : np <= 6);
 }
 
-inline bool small_unrolled_supported(int, int, bool, int) { return false; }
+// The unrolled kernel also keeps the J-bar rows and M-bar in registers.
+inline bool small_unrolled_supported(int nmax, int mmax, bool packed, int s) {
+    const int np = small_np(nmax);
+    return !packed && np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 9 : np <= 6);
+}
 
 #define CS_SMALL_DISPATCH(NPV, RV, CALL)                                                      \
     if (np == NPV && rr == RV) { CALL(NPV, RV); }
 
-#define CS_SMALL_ALL(CALL)                                                                    \
-    if constexpr (sizeof(T) == 4) {                                                           \
-        CS_SMALL_DISPATCH(3, 1, CALL) else CS_SMALL_DISPATCH(3, 2, CALL) else CS_SMALL_DISPATCH(3, 4, CALL) \
-        else CS_SMALL_DISPATCH(6, 1, CALL) else CS_SMALL_DISPATCH(6, 2, CALL) else CS_SMALL_DISPATCH(6, 4, CALL) \
-        else CS_SMALL_DISPATCH(9, 1, CALL) else CS_SMALL_DISPATCH(9, 2, CALL) else CS_SMALL_DISPATCH(9, 4, CALL) \
-        else CS_SMALL_DISPATCH(12, 1, CALL) else CS_SMALL_DISPATCH(12, 2, CALL) else CS_SMALL_DISPATCH(12, 4, CALL) \
-        else { return -4; }                                                                   \
-    } else {                                                                                  \
-        CS_SMALL_DISPATCH(3, 1, CALL) else CS_SMALL_DISPATCH(3, 2, CALL) else CS_SMALL_DISPATCH(3, 4, CALL) \
-        else CS_SMALL_DISPATCH(6, 1, CALL) else CS_SMALL_DISPATCH(6, 2, CALL) else CS_SMALL_DISPATCH(6, 4, CALL) \
-        else { return -4; }                                                                   \
-    }
+#define CS_SMALL_F64(CALL)                                                                    \
+    CS_SMALL_DISPATCH(3, 1, CALL) else CS_SMALL_DISPATCH(3, 2, CALL) else CS_SMALL_DISPATCH(3, 4, CALL) \
+    else CS_SMALL_DISPATCH(6, 1, CALL) else CS_SMALL_DISPATCH(6, 2, CALL) else CS_SMALL_DISPATCH(6, 4, CALL) \
+    else { return -4; }
+
+#define CS_SMALL_F32_9(CALL)                                                                  \
+    CS_SMALL_DISPATCH(3, 1, CALL) else CS_SMALL_DISPATCH(3, 2, CALL) else CS_SMALL_DISPATCH(3, 4, CALL) \
+    else CS_SMALL_DISPATCH(6, 1, CALL) else CS_SMALL_DISPATCH(6, 2, CALL) else CS_SMALL_DISPATCH(6, 4, CALL) \
+    else CS_SMALL_DISPATCH(9, 1, CALL) else CS_SMALL_DISPATCH(9, 2, CALL) else CS_SMALL_DISPATCH(9, 4, CALL) \
+    else { return -4; }
+
+#define CS_SMALL_F32_12(CALL)                                                                 \
+    CS_SMALL_DISPATCH(3, 1, CALL) else CS_SMALL_DISPATCH(3, 2, CALL) else CS_SMALL_DISPATCH(3, 4, CALL) \
+    else CS_SMALL_DISPATCH(6, 1, CALL) else CS_SMALL_DISPATCH(6, 2, CALL) else CS_SMALL_DISPATCH(6, 4, CALL) \
+    else CS_SMALL_DISPATCH(9, 1, CALL) else CS_SMALL_DISPATCH(9, 2, CALL) else CS_SMALL_DISPATCH(9, 4, CALL) \
+    else CS_SMALL_DISPATCH(12, 1, CALL) else CS_SMALL_DISPATCH(12, 2, CALL) else CS_SMALL_DISPATCH(12, 4, CALL) \
+    else { return -4; }
 
 template <typename T>
 int launch_small_forward(const BatchView &bv, int nmax, int mmax, int max_iter, T tol, const T *M,
@@ -516,7 +872,7 @@ int launch_small_forward(const BatchView &bv, int nmax, int mmax, int max_iter, 
 #define CS_CALL_FWD(NPV, RV)                                                                  \
     hipLaunchKernelGGL((k_forward_small<T, NPV, RV>), grid, block, 0, stream, bv, nb, max_iter, \
                        tol, M, J, a0, aref, D, a_init, a_out, fac, mask, status, iters);
-    CS_SMALL_ALL(CS_CALL_FWD)
+    if constexpr (sizeof(T) == 4) { CS_SMALL_F32_12(CS_CALL_FWD) } else { CS_SMALL_F64(CS_CALL_FWD) }
 #undef CS_CALL_FWD
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
@@ -532,16 +888,26 @@ int launch_small_vjp(const BatchView &bv, int nmax, int mmax, const T *fac, cons
 #define CS_CALL_VJP(NPV, RV)                                                                  \
     hipLaunchKernelGGL((k_ift_vjp_small<T, NPV, RV>), grid, block, 0, stream, bv, nb, fac, mask, \
                        M, J, a0, aref, D, a, abar, a0bar, arefbar, Jbar, Dbar, Mbar);
-    CS_SMALL_ALL(CS_CALL_VJP)
+    if constexpr (sizeof(T) == 4) { CS_SMALL_F32_12(CS_CALL_VJP) } else { CS_SMALL_F64(CS_CALL_VJP) }
 #undef CS_CALL_VJP
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 template <typename T>
-int launch_small_unrolled(const BatchView &, int, int, int, T, const T *, const T *, const T *,
-                          const T *, const T *, const T *, T *, T *, T *, T *, T *, T *, T *,
-                          uint8_t *, int32_t *, int32_t *, hipStream_t) {
-    return -4;
+int launch_small_unrolled(const BatchView &bv, int nmax, int mmax, int K, T tol, const T *M,
+                          const T *J, const T *a0, const T *aref, const T *D, const T *abar,
+                          T *a_out, T *a0bar, T *arefbar, T *Jbar, T *Dbar, T *Mbar, T *tapeT,
+                          uint8_t *tapeB, int32_t *status, int32_t *iters, hipStream_t stream) {
+    const int np = small_np(nmax), rr = small_r(mmax);
+    const int nb = bv.B;
+    const dim3 grid((nb + 15) / 16), block(256);
+#define CS_CALL_UNR(NPV, RV)                                                                  \
+    hipLaunchKernelGGL((k_unrolled_small<T, NPV, RV>), grid, block, 0, stream, bv, nb, K, tol, M, \
+                       J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar, Dbar, Mbar, tapeT,      \
+                       tapeB, status, iters);
+    if constexpr (sizeof(T) == 4) { CS_SMALL_F32_9(CS_CALL_UNR) } else { CS_SMALL_F64(CS_CALL_UNR) }
+#undef CS_CALL_UNR
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 }  // namespace cs

@@ -106,6 +106,16 @@ class Batch:
     def state_bytes(self) -> int:
         return N.state_bytes(self.desc)
 
+    def mask_offset(self) -> int:
+        """Byte offset of the active-set bytes inside the state buffer."""
+        s = 4 if self.dtype == torch.float32 else 8
+        return (s * (self.total_nn + self.total_n) // 2 + 255) // 256 * 256
+
+    def active_sets(self, sol) -> np.ndarray:
+        """Active set A* of every row (host copy, flat, off_m layout)."""
+        o = self.mask_offset()
+        return sol.state[o:o + self.total_m].cpu().numpy().astype(bool)
+
     def tape_bytes(self, K: int) -> int:
         return N.tape_bytes(self.desc, K)
 

@@ -30,11 +30,8 @@ def gpu_uniform(b: synth.UniformBatch, dtype, max_iter, tol, vjp=True, order=Non
     torch.cuda.synchronize()
     res = {k: (np64(v) if v.dtype.is_floating_point else v.cpu().numpy()) for k, v in out.items()
            if k != "state"}
-    sb = batch.state_bytes()
-    al = (4 if dtype == torch.float32 else 8) * b.B * b.n * b.n
-    al = (al + 255) // 256 * 256
-    res["active"] = sol.state[al:al + b.B * b.m].cpu().numpy().reshape(b.B, b.m).astype(bool)
-    assert sol.state.numel() >= sb
+    res["active"] = batch.active_sets(sol).reshape(b.B, b.m)
+    assert sol.state.numel() >= batch.state_bytes()
     return res
 
 

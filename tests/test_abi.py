@@ -41,12 +41,12 @@ def test_version_and_strerror():
 def test_state_and_tape_sizes_uniform():
     b = solver.Batch.uniform(4096, 9, 64, torch.float32, device="cpu")
     al = lambda x: (x + 255) // 256 * 256
-    assert b.state_bytes() == al(4 * 4096 * 81) + 4096 * 64
+    assert b.state_bytes() == al(4 * 4096 * 45) + 4096 * 64
     for K in (0, 1, 10):
-        recT = 2 * 9 + 81 + 2 * 64 + 2
+        recT = 2 * 9 + 45 + 2 * 64 + 2
         assert b.tape_bytes(K) == al(4 * K * 4096 * recT) + K * 2 * 4096 * 64
     b64 = solver.Batch.uniform(64, 6, 16, torch.float64, device="cpu")
-    assert b64.state_bytes() == al(8 * 64 * 36) + 64 * 16
+    assert b64.state_bytes() == al(8 * 64 * 21) + 64 * 16
 
 
 def test_tape_grows_linearly_in_K():
@@ -61,9 +61,9 @@ def test_state_and_tape_sizes_packed():
     nr = np.array([0, 64, 1024, 12])
     b = solver.Batch.packed_from(nv, nr, torch.float32, device="cpu")
     al = lambda x: (x + 255) // 256 * 256
-    assert b.state_bytes() == al(4 * int((nv ** 2).sum())) + int(nr.sum())
+    assert b.state_bytes() == al(4 * int((nv * (nv + 1) // 2).sum())) + int(nr.sum())
     K = 3
-    recT = int((2 * nv + nv ** 2 + 2 * nr + 2).sum())
+    recT = int((2 * nv + nv * (nv + 1) // 2 + 2 * nr + 2).sum())
     assert b.tape_bytes(K) == al(4 * K * recT) + K * 2 * int(nr.sum())
 
 
