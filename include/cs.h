@@ -96,9 +96,20 @@ typedef struct cs_batch {
 
 typedef struct cs_solver_params {
     int32_t max_iter;  /* cap on Newton steps (>= 0); the unrolled VJP takes exactly this K */
-    int32_t flags;     /* reserved, must be 0 */
+    int32_t flags;     /* 0, or for cs_unrolled_vjp one of CS_UNROLLED_RECORD / _REPLAY */
     double tol;        /* stopping tolerance (>= 0), see cs_forward */
 } cs_solver_params;
+
+/* cs_unrolled_vjp phases (cs_solver_params.flags).  0 runs both.  RECORD runs
+ * the K-step solve, fills the tape and writes a_out, status and iters (iters
+ * required); gradient outputs are not touched and may be NULL.  REPLAY runs
+ * only the reverse sweep over a tape written by a RECORD call with the same
+ * inputs and K, reading status and iters as that call left them (abar and
+ * every gradient output required); a_out is not touched and may be NULL.
+ * This is how a reverse-mode AD of the solver trace holds the trace from the
+ * forward pass to the backward pass. */
+#define CS_UNROLLED_RECORD 1
+#define CS_UNROLLED_REPLAY 2
 
 /* Bytes of the `state` buffer cs_forward writes and cs_ift_vjp reads: the
  * Cholesky factor of H(A*) as a packed lower triangle per instance (n (n+1)/2

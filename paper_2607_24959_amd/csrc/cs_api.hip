@@ -94,10 +94,10 @@ size_t tape_bytes(const HostBatch &hb, int K) {
     return align256(hb.s * tape_T_elems(hb, K)) + (size_t)K * 2 * (size_t)hb.tot_m;
 }
 
-int check_params(const cs_solver_params *p) {
+int check_params(const cs_solver_params *p, bool unrolled = false) {
     if (!p) return CS_EINVAL;
     if (p->max_iter < 0 || p->max_iter > kMaxIterCap) return CS_EINVAL;
-    if (p->flags != 0) return CS_EINVAL;
+    if (unrolled ? (p->flags < 0 || p->flags > CS_UNROLLED_REPLAY) : p->flags != 0) return CS_EINVAL;
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return CS_EINVAL;
     return CS_OK;
 }
@@ -209,7 +209,7 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
 }
 
 template <typename T>
-int unrolled_t(const HostBatch &hb, const cs_solver_params *p, const void *M, const void *J,
+int unrolled_t(const HostBatch &hb, const cs_solver_params *p, int mode, const void *M, const void *J,
                const void *a0, const void *aref, const void *D, const void *abar, void *a_out,
                void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar, void *tape,
                int32_t *status, int32_t *iters, hipStream_t stream) {
@@ -219,7 +219,7 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, const void *M, co
     const int sm = choose_small_unrolled(hb);
     if (sm < 0) return sm;
     if (sm == 1) {
-        return cs::launch_small_unrolled<T>(hb.bv, hb.nmax, hb.mmax, K, (T)p->tol, (const T *)M,
+        return cs::launch_small_unrolled<T>(hb.bv, hb.nmax, hb.mmax, K, mode, (T)p->tol, (const T *)M,
                                             (const T *)J, (const T *)a0, (const T *)aref,
                                             (const T *)D, (const T *)abar, (T *)a_out,
                                             (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar,
@@ -231,16 +231,16 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, const void *M, co
     if (NT == 64) {
         auto k = cs::k_unrolled_generic<T, 64>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, K, (T)p->tol,
-                           hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, K, mode,
+                           (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,
                            status, iters);
     } else {
         auto k = cs::k_unrolled_generic<T, 256>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, K, (T)p->tol,
-                           hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, K, mode,
+                           (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,
                            status, iters);
@@ -324,17 +324,25 @@ int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params, const
     HostBatch hb;
     int rc = describe(batch, hb);
     if (rc != CS_OK) return rc;
-    if ((rc = check_params(params)) != CS_OK) return rc;
+    if ((rc = check_params(params, true)) != CS_OK) return rc;
     if (hb.B == 0) return CS_OK;
-    if (!M || !a0 || !abar || !a_out || !a0bar || !Mbar || !status) return CS_EINVAL;
-    if (hb.tot_m > 0 && (!J || !aref || !D || !arefbar || !Jbar || !Dbar)) return CS_EINVAL;
+    const int mode = params->flags;
+    if (!M || !a0 || !status) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D)) return CS_EINVAL;
+    if (mode != CS_UNROLLED_REPLAY && !a_out) return CS_EINVAL;
+    if (mode == CS_UNROLLED_RECORD && !iters) return CS_EINVAL;
+    if (mode == CS_UNROLLED_REPLAY && !iters) return CS_EINVAL;
+    if (mode != CS_UNROLLED_RECORD) {
+        if (!abar || !a0bar || !Mbar) return CS_EINVAL;
+        if (hb.tot_m > 0 && (!arefbar || !Jbar || !Dbar)) return CS_EINVAL;
+    }
     if (params->max_iter > 0 && !tape) return CS_EINVAL;
     if (tape_bytes_given < tape_bytes(hb, params->max_iter)) return CS_ENOSPC;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hb.dtype == CS_F32)
-        return unrolled_t<float>(hb, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar,
+        return unrolled_t<float>(hb, params, mode, M, J, a0, aref, D, abar, a_out, a0bar, arefbar,
                                  Jbar, Dbar, Mbar, tape, status, iters, s);
-    return unrolled_t<double>(hb, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
+    return unrolled_t<double>(hb, params, mode, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
                               Dbar, Mbar, tape, status, iters, s);
 }
 

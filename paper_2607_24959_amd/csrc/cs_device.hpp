@@ -19,6 +19,9 @@ enum : int {
     ST_LSFAIL = 16,
 };
 
+// cs_unrolled_vjp phases (cs_solver_params.flags)
+enum : int { ST_BOTH = 0, ST_REC = 1, ST_REP = 2 };
+
 // Device view of the batch descriptor.
 struct BatchView {
     int B, nv_u, nr_u;

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_unrolled_generic(
-    BatchView bv, int K, T tol, int nmax, int mmax, const T *__restrict__ gM,
+    BatchView bv, int K, int mode, T tol, int nmax, int mmax, const T *__restrict__ gM,
     const T *__restrict__ gJ, const T *__restrict__ ga0, const T *__restrict__ garef,
     const T *__restrict__ gD, const T *__restrict__ gabar, T *__restrict__ gaout,
     T *__restrict__ ga0bar, T *__restrict__ garefbar, T *__restrict__ gJbar,
@@ -348,18 +348,21 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
         T *tT = tapeT + tape_T_offset(I, K);
         uint8_t *tB = tapeB + tape_B_offset(I, K);
 
+        const bool do_fwd = mode != ST_REP, do_rev = mode != ST_REC;
         // zero the accumulated gradients
-        for (int j = tid; j < n; j += NT) a0bar[j] = T(0);
-        for (int i = tid; i < m; i += NT) { arefbar[i] = T(0); Dbar[i] = T(0); }
-        for (int e = tid; e < m * n; e += NT) Jbar[e] = T(0);
-        for (int e = tid; e < n * n; e += NT) Mbar[e] = T(0);
+        if (do_rev) {
+            for (int j = tid; j < n; j += NT) a0bar[j] = T(0);
+            for (int i = tid; i < m; i += NT) { arefbar[i] = T(0); Dbar[i] = T(0); }
+            for (int e = tid; e < m * n; e += NT) Jbar[e] = T(0);
+            for (int e = tid; e < n * n; e += NT) Mbar[e] = T(0);
+        }
 
         bool bad = false;
         for (int j = tid; j < n; j += NT) {
             const T x = a0[j];
             L.a0[j] = x;
             L.a[j] = x;
-            bad |= !finite_val(x) || !finite_val(gabar[I.on + j]);
+            bad |= !finite_val(x) || (do_rev && !finite_val(gabar[I.on + j]));
         }
         for (int i = tid; i < m; i += NT) {
             const T d = D[i];
@@ -374,10 +377,16 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
         for (int e = tid; e < m * n; e += NT) bad |= !finite_val(J[e]);
         const int anybad = __syncthreads_or(bad);
         int st = 0, steps = 0;
-        if (anybad) st = ST_NONFINITE;
-        else if (!team_cholesky<NT>(L.H, L.diag, n)) st = ST_NOTSPD;
+        if (!do_fwd) {
+            st = gstatus[I.b] | (anybad ? ST_NONFINITE : 0);
+            steps = giters[I.b];
+        } else if (anybad) {
+            st = ST_NONFINITE;
+        } else if (!team_cholesky<NT>(L.H, L.diag, n)) {
+            st = ST_NOTSPD;
+        }
 
-        if (st == 0) {
+        if (do_fwd && st == 0) {
             // ---- forward K steps with the tape
             T trM = T(0);
             for (int j = 0; j < n; ++j) trM += M[(size_t)j * n + j];
@@ -480,13 +489,17 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
         const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
         const T nanv = T(__builtin_nan(""));
         for (int j = tid; j < n; j += NT) {
-            gaout[I.on + j] = ok ? L.a[j] : nanv;
-            L.ab[j] = gabar[I.on + j];
+            if (do_fwd) gaout[I.on + j] = ok ? L.a[j] : nanv;
+            L.ab[j] = do_rev ? gabar[I.on + j] : T(0);
+        }
+        if (do_fwd && tid == 0) {
+            gstatus[I.b] = st;
+            if (giters) giters[I.b] = steps;
         }
         __syncthreads();
 
         // ---- reverse sweep over the recorded steps
-        for (int k = (ok ? steps : 0) - 1; k >= 0; --k) {
+        for (int k = (ok && do_rev ? steps : 0) - 1; k >= 0; --k) {
             const T *rec = tT + (size_t)k * recT;
             const uint8_t *recB = tB + (size_t)k * 2 * m;
             const T *rr = rec + 2 * n + ne, *rq = rr + m;
@@ -591,11 +604,8 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             __syncthreads();
         }
         // the first iterate is a0
-        for (int j = tid; j < n; j += NT) a0bar[j] += ok ? L.ab[j] : nanv;
-        if (tid == 0) {
-            gstatus[I.b] = st;
-            if (giters) giters[I.b] = steps;
-        }
+        if (do_rev)
+            for (int j = tid; j < n; j += NT) a0bar[j] += ok ? L.ab[j] : nanv;
         __syncthreads();
     }
 }

@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
 // lane owning the row; M-bar entry f by lane f mod 16).
 template <typename T, int NP, int R>
 __global__ __launch_bounds__(256) void k_unrolled_small(
-    BatchView bv, int nb_inst, int K, T tol, const T *__restrict__ gM, const T *__restrict__ gJ,
+    BatchView bv, int nb_inst, int K, int mode, T tol, const T *__restrict__ gM, const T *__restrict__ gJ,
     const T *__restrict__ ga0, const T *__restrict__ garef, const T *__restrict__ gD,
     const T *__restrict__ gabar, T *__restrict__ gaout, T *__restrict__ ga0bar,
     T *__restrict__ garefbar, T *__restrict__ gJbar, T *__restrict__ gDbar, T *__restrict__ gMbar,
@@ -651,26 +651,38 @@ __global__ __launch_bounds__(256) void k_unrolled_small(
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         a[j] = S.a0[j];
-        ab[j] = j < n ? gabar[I.on + j] : T(0);
+        ab[j] = (mode != ST_REC && j < n) ? gabar[I.on + j] : T(0);
         bad |= !finite_val(ab[j]);
     }
     bad = gsum16(bad ? T(1) : T(0)) != T(0);
     const int ne = n * (n + 1) / 2;
     const int recT = 2 * n + ne + 2 * m + 2;
     const StepTape<T> tp{tapeT + tape_T_offset(I, K), tapeB + tape_B_offset(I, K), n, m, recT};
-    T H[NE], inv[NP];
-    bool act[R];
+    const T nanv = T(__builtin_nan(""));
     int steps = 0, st;
-    if (bad) {
-        st = ST_NONFINITE;
+    if (mode == ST_REP) {
+        st = gstatus[I.b];
+        steps = giters[I.b];
+        if (bad) st |= ST_NONFINITE;
     } else {
-        st = small_solve<true, T, NP, R>(S, K, tol, a, H, inv, act, steps, tp);
+        T H[NE], inv[NP];
+        bool act[R];
+        if (bad) {
+            st = ST_NONFINITE;
+        } else {
+            st = small_solve<true, T, NP, R>(S, K, tol, a, H, inv, act, steps, tp);
+        }
+        const bool okf = !(st & (ST_NONFINITE | ST_NOTSPD));
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            if (j == g && j < n) gaout[I.on + j] = okf ? a[j] : nanv;
+        if (g == 0) {
+            gstatus[I.b] = st;
+            if (giters) giters[I.b] = steps;
+        }
+        if (mode == ST_REC) return;
     }
     const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
-    const T nanv = T(__builtin_nan(""));
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-        if (j == g && j < n) gaout[I.on + j] = ok ? a[j] : nanv;
 
     // reverse sweep
     T Jb[R][NP], arb[R], db[R], Mb[MBL], a0b[NP];
@@ -801,13 +813,9 @@ __global__ __launch_bounds__(256) void k_unrolled_small(
             const int f = g + SG * e;
             if (f < NP * NP) {
                 const int j = f / NP, l = f % NP;
-                if (j < n && l < n) pm[j * n + l] = Mb[e];
+                if (j < n && l < n) pm[j * n + l] = ok ? Mb[e] : nanv;
             }
         }
-    }
-    if (g == 0) {
-        gstatus[I.b] = st;
-        if (giters) giters[I.b] = steps;
     }
 }
 
@@ -894,7 +902,7 @@ int launch_small_vjp(const BatchView &bv, int nmax, int mmax, const T *fac, cons
 }
 
 template <typename T>
-int launch_small_unrolled(const BatchView &bv, int nmax, int mmax, int K, T tol, const T *M,
+int launch_small_unrolled(const BatchView &bv, int nmax, int mmax, int K, int mode, T tol, const T *M,
                           const T *J, const T *a0, const T *aref, const T *D, const T *abar,
                           T *a_out, T *a0bar, T *arefbar, T *Jbar, T *Dbar, T *Mbar, T *tapeT,
                           uint8_t *tapeB, int32_t *status, int32_t *iters, hipStream_t stream) {
@@ -902,7 +910,7 @@ int launch_small_unrolled(const BatchView &bv, int nmax, int mmax, int K, T tol,
     const int nb = bv.B;
     const dim3 grid((nb + 15) / 16), block(256);
 #define CS_CALL_UNR(NPV, RV)                                                                  \
-    hipLaunchKernelGGL((k_unrolled_small<T, NPV, RV>), grid, block, 0, stream, bv, nb, K, tol, M, \
+    hipLaunchKernelGGL((k_unrolled_small<T, NPV, RV>), grid, block, 0, stream, bv, nb, K, mode, tol, M, \
                        J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar, Dbar, Mbar, tapeT,      \
                        tapeB, status, iters);
     if constexpr (sizeof(T) == 4) { CS_SMALL_F32_9(CS_CALL_UNR) } else { CS_SMALL_F64(CS_CALL_UNR) }

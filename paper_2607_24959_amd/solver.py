@@ -185,6 +185,44 @@ def ift_vjp(batch: Batch, sol: Solution, M, J, a0, aref, D, abar,
     return out
 
 
+def unrolled_record(batch: Batch, M, J, a0, aref, D, *, K=10, tol=1e-5, tape=None):
+    """Run the K-step solve and record its trace.  Returns dict(a, status, iters, tape)."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D)):
+        batch.check(name, t, s[name])
+    nbytes = batch.tape_bytes(K)
+    if tape is None:
+        tape = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=a0.device)
+    if tape.numel() < nbytes:
+        raise ValueError("tape buffer too small")
+    out = dict(a=torch.empty_like(a0),
+               status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
+               iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device), tape=tape, K=K,
+               tol=tol)
+    p = N.CsSolverParams(int(K), 1, float(tol))
+    rc = N.unrolled_vjp(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), None,
+                        _vp(out["a"]), None, None, None, None, None, _vp(tape), tape.numel(),
+                        _vp(out["status"]), _vp(out["iters"]), _stream(a0.device))
+    N.check(rc, "cs_unrolled_vjp(record)")
+    return out
+
+
+def unrolled_replay(batch: Batch, rec, M, J, a0, aref, D, abar,
+                    needs=(True, True, True, True, True)):
+    """Reverse sweep over a trace from unrolled_record.  Returns (a0bar, arefbar, Jbar, Dbar, Mbar)."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D), ("abar", abar)):
+        batch.check(name, t, s[name])
+    g = tuple(torch.empty_like(x) for x in (a0, aref, J, D, M))
+    p = N.CsSolverParams(int(rec["K"]), 2, float(rec["tol"]))
+    tape = rec["tape"]
+    rc = N.unrolled_vjp(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), _vp(abar),
+                        None, *(_vp(t) for t in g), _vp(tape), tape.numel(), _vp(rec["status"]),
+                        _vp(rec["iters"]), _stream(a0.device))
+    N.check(rc, "cs_unrolled_vjp(replay)")
+    return tuple(x if need else None for x, need in zip(g, needs))
+
+
 def unrolled_vjp(batch: Batch, M, J, a0, aref, D, abar, *, K=10, tol=1e-5, tape=None):
     """Unrolled-trace gradient of abar . a_K.  Returns dict(a, a0, aref, J, D, M, status, iters,
     tape_bytes)."""
