@@ -57,16 +57,19 @@ extern "C" {
 #define CS_ST_NOTSPD 8      /* M (or a Newton matrix) is not positive definite; outputs NaN */
 #define CS_ST_LSFAIL 16     /* the line search hit its safeguard cap (step still taken) */
 
-/* Kernel families (cs_batch.path).  AUTO picks SMALL when the batch is
- * uniform and its shape fits a small-instance kernel (FP32 n <= 12, FP64
- * n <= 6, m <= 64), TEAM otherwise.  TEAM: one workgroup per instance, any
- * supported shape.  SMALL: 16 lanes per instance with the instance held in
- * registers; CS_EUNSUPPORTED when the shape does not fit.  Every family
- * writes the same state layout, so any cs_ift_vjp path can read any
- * cs_forward state. */
+/* Kernel families (cs_batch.path), chosen from the batch's (or subset's)
+ * largest n and m.  SMALL: 16 lanes per instance with the instance held in
+ * registers (FP32 n <= 12, FP64 n <= 6, m <= 64).  CHUNK: one workgroup per
+ * instance, rows of J streamed through LDS in 64-row chunks, Newton matrix
+ * on the matrix cores in FP32 (n <= 128, m <= 2048).  TEAM: one workgroup per
+ * instance, any supported shape.  AUTO takes the first that fits in that
+ * order (the unrolled VJP has SMALL and TEAM only).  A forced family that
+ * does not fit returns CS_EUNSUPPORTED.  Every family writes the same state
+ * layout, so any cs_ift_vjp family can read any cs_forward state. */
 #define CS_PATH_AUTO 0
 #define CS_PATH_TEAM 1
 #define CS_PATH_SMALL 2
+#define CS_PATH_CHUNK 3
 
 /* Largest sizes the library supports per instance. */
 #define CS_NV_MAX 128
@@ -90,8 +93,9 @@ typedef struct cs_batch {
     int64_t total_mn;       /* packed: off_mn[B] */
     int64_t total_n;        /* packed: off_n[B] */
     int64_t total_m;        /* packed: off_m[B] */
-    int32_t path;           /* kernel family: CS_PATH_AUTO, CS_PATH_TEAM or CS_PATH_SMALL */
-    int32_t reserved;       /* must be 0 */
+    int32_t path;           /* kernel family: CS_PATH_AUTO, _TEAM, _SMALL or _CHUNK */
+    int32_t count;          /* solve only order[0 .. count-1] (0: all B; > 0 needs order).
+                             * nv_max / nrows_max may then describe that subset only */
 } cs_batch;
 
 typedef struct cs_solver_params {

@@ -16,7 +16,7 @@ CS_OK, CS_EINVAL, CS_ENOSPC, CS_EHIP, CS_EUNSUPPORTED = 0, -1, -2, -3, -4
 CS_F32, CS_F64 = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL = 1, 2, 4, 8, 16
 NV_MAX, NROWS_MAX = 128, 4096
-PATH_AUTO, PATH_TEAM, PATH_SMALL = 0, 1, 2
+PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK = 0, 1, 2, 3
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version")
@@ -33,7 +33,7 @@ class CsBatch(C.Structure):
         ("nv_max", C.c_int32), ("nrows_max", C.c_int32),
         ("total_nn", C.c_int64), ("total_mn", C.c_int64),
         ("total_n", C.c_int64), ("total_m", C.c_int64),
-        ("path", C.c_int32), ("reserved", C.c_int32),
+        ("path", C.c_int32), ("count", C.c_int32),
     ]
 
 

@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "cs.h"
+#include "cs_chunk.hpp"
 #include "cs_generic.hpp"
 #include "cs_small.hpp"
 
@@ -32,9 +33,9 @@ int describe(const cs_batch *b, HostBatch &hb) {
     if (!b) return CS_EINVAL;
     if (b->B < 0) return CS_EINVAL;
     if (b->dtype != CS_F32 && b->dtype != CS_F64) return CS_EINVAL;
-    if (b->path != CS_PATH_AUTO && b->path != CS_PATH_TEAM && b->path != CS_PATH_SMALL)
-        return CS_EINVAL;
-    if (b->reserved != 0) return CS_EINVAL;
+    if (b->path < CS_PATH_AUTO || b->path > CS_PATH_CHUNK) return CS_EINVAL;
+    if (b->count < 0 || b->count > b->B) return CS_EINVAL;
+    if (b->count > 0 && b->count != b->B && !b->order) return CS_EINVAL;
     hb.path = b->path;
     hb.B = b->B;
     hb.dtype = b->dtype;
@@ -65,7 +66,8 @@ int describe(const cs_batch *b, HostBatch &hb) {
         hb.tot_n = B * n;
         hb.tot_m = B * m;
     }
-    hb.bv.B = b->B;
+    // kernels loop over the instances they solve: order[0 .. count-1]
+    hb.bv.B = b->count > 0 ? b->count : b->B;
     hb.bv.nv_u = b->nv_uniform;
     hb.bv.nr_u = b->nrows_uniform;
     hb.bv.nv = b->nv;
@@ -102,19 +104,28 @@ int check_params(const cs_solver_params *p, bool unrolled = false) {
     return CS_OK;
 }
 
-// Kernel family for this batch: 1 = small, 0 = team, <0 = error code.
-int choose_small(const HostBatch &hb) {
-    const bool fits = cs::small_supported(hb.nmax, hb.mmax, hb.packed, (int)hb.s);
-    if (hb.path == CS_PATH_SMALL) return fits ? 1 : CS_EUNSUPPORTED;
-    if (hb.path == CS_PATH_TEAM) return 0;
-    return fits ? 1 : 0;
+enum { FAM_TEAM = 0, FAM_SMALL = 1, FAM_CHUNK = 2 };
+
+// Kernel family for this batch (FAM_*) or a negative error code.
+int choose_family(const HostBatch &hb) {
+    const bool small = cs::small_supported(hb.nmax, hb.mmax, (int)hb.s);
+    const bool chunk = cs::chunk_supported(hb.nmax, hb.mmax, (int)hb.s);
+    switch (hb.path) {
+    case CS_PATH_SMALL: return small ? FAM_SMALL : CS_EUNSUPPORTED;
+    case CS_PATH_CHUNK: return chunk ? FAM_CHUNK : CS_EUNSUPPORTED;
+    case CS_PATH_TEAM: return FAM_TEAM;
+    default: return small ? FAM_SMALL : (chunk ? FAM_CHUNK : FAM_TEAM);
+    }
 }
 
-int choose_small_unrolled(const HostBatch &hb) {
-    const bool fits = cs::small_unrolled_supported(hb.nmax, hb.mmax, hb.packed, (int)hb.s);
-    if (hb.path == CS_PATH_SMALL) return fits ? 1 : CS_EUNSUPPORTED;
-    if (hb.path == CS_PATH_TEAM) return 0;
-    return fits ? 1 : 0;
+int choose_family_unrolled(const HostBatch &hb) {
+    const bool small = cs::small_unrolled_supported(hb.nmax, hb.mmax, (int)hb.s);
+    switch (hb.path) {
+    case CS_PATH_SMALL: return small ? FAM_SMALL : CS_EUNSUPPORTED;
+    case CS_PATH_CHUNK: return CS_EUNSUPPORTED;
+    case CS_PATH_TEAM: return FAM_TEAM;
+    default: return small ? FAM_SMALL : FAM_TEAM;
+    }
 }
 
 // Generic family: team size by shape.
@@ -125,10 +136,7 @@ inline int generic_nt(const HostBatch &hb) {
 template <typename K>
 int prepare(K kernel, size_t lds) {
     if (lds > kLdsLimit) return CS_EUNSUPPORTED;
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return CS_EHIP;
-    return CS_OK;
+    return cs::ensure_lds(reinterpret_cast<const void *>(kernel), lds) ? CS_OK : CS_EHIP;
 }
 
 inline unsigned grid_for(int B) { return (unsigned)(B < (1 << 20) ? B : (1 << 20)); }
@@ -143,9 +151,17 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
               void *state, int32_t *status, int32_t *iters, hipStream_t stream) {
     T *fac = static_cast<T *>(state);
     uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
-    const int sm = choose_small(hb);
-    if (sm < 0) return sm;
-    if (sm == 1) {
+    const int fam = choose_family(hb);
+    if (fam < 0) return fam;
+    if (fam == FAM_CHUNK) {
+        const int rc = cs::launch_chunk_forward<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, p->max_iter,
+                                                   (T)p->tol, (const T *)M, (const T *)J,
+                                                   (const T *)a0, (const T *)aref, (const T *)D,
+                                                   (const T *)a_init, (T *)a_out, fac, mask,
+                                                   status, iters, stream);
+        return rc == 0 ? CS_OK : CS_EHIP;
+    }
+    if (fam == FAM_SMALL) {
         return cs::launch_small_forward<T>(hb.bv, hb.nmax, hb.mmax, p->max_iter, (T)p->tol,
                                            (const T *)M, (const T *)J, (const T *)a0,
                                            (const T *)aref, (const T *)D, (const T *)a_init,
@@ -157,14 +173,14 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
     if (NT == 64) {
         auto k = cs::k_forward_generic<T, 64>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, p->max_iter,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(64), lds, stream, hb.bv, p->max_iter,
                            (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J,
                            (const T *)a0, (const T *)aref, (const T *)D, (const T *)a_init,
                            (T *)a_out, fac, mask, status, iters);
     } else {
         auto k = cs::k_forward_generic<T, 256>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, p->max_iter,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(256), lds, stream, hb.bv, p->max_iter,
                            (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J,
                            (const T *)a0, (const T *)aref, (const T *)D, (const T *)a_init,
                            (T *)a_out, fac, mask, status, iters);
@@ -179,9 +195,17 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
     const T *fac = static_cast<const T *>(state);
     const uint8_t *mask =
         static_cast<const uint8_t *>(state) + align256(hb.s * factor_elems(hb));
-    const int sm = choose_small(hb);
-    if (sm < 0) return sm;
-    if (sm == 1) {
+    const int fam = choose_family(hb);
+    if (fam < 0) return fam;
+    if (fam == FAM_CHUNK) {
+        const int rc = cs::launch_chunk_vjp<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, fac, mask,
+                                               (const T *)M, (const T *)J, (const T *)a0,
+                                               (const T *)aref, (const T *)D, (const T *)a,
+                                               (const T *)abar, (T *)a0bar, (T *)arefbar,
+                                               (T *)Jbar, (T *)Dbar, (T *)Mbar, stream);
+        return rc == 0 ? CS_OK : CS_EHIP;
+    }
+    if (fam == FAM_SMALL) {
         return cs::launch_small_vjp<T>(hb.bv, hb.nmax, hb.mmax, fac, mask, (const T *)M,
                                        (const T *)J, (const T *)a0, (const T *)aref,
                                        (const T *)D, (const T *)a, (const T *)abar, (T *)a0bar,
@@ -193,14 +217,14 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
     if (NT == 64) {
         auto k = cs::k_ift_vjp_generic<T, 64>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, hb.nmax,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(64), lds, stream, hb.bv, hb.nmax,
                            hb.mmax, fac, mask, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)a, (const T *)abar,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar);
     } else {
         auto k = cs::k_ift_vjp_generic<T, 256>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, hb.nmax,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(256), lds, stream, hb.bv, hb.nmax,
                            hb.mmax, fac, mask, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)a, (const T *)abar,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar);
@@ -216,9 +240,9 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, int mode, const v
     const int K = p->max_iter;
     T *tT = static_cast<T *>(tape);
     uint8_t *tB = static_cast<uint8_t *>(tape) + align256(hb.s * tape_T_elems(hb, K));
-    const int sm = choose_small_unrolled(hb);
-    if (sm < 0) return sm;
-    if (sm == 1) {
+    const int fam = choose_family_unrolled(hb);
+    if (fam < 0) return fam;
+    if (fam == FAM_SMALL) {
         return cs::launch_small_unrolled<T>(hb.bv, hb.nmax, hb.mmax, K, mode, (T)p->tol, (const T *)M,
                                             (const T *)J, (const T *)a0, (const T *)aref,
                                             (const T *)D, (const T *)abar, (T *)a_out,
@@ -231,7 +255,7 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, int mode, const v
     if (NT == 64) {
         auto k = cs::k_unrolled_generic<T, 64>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(64), lds, stream, hb.bv, K, mode,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(64), lds, stream, hb.bv, K, mode,
                            (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,
@@ -239,7 +263,7 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, int mode, const v
     } else {
         auto k = cs::k_unrolled_generic<T, 256>;
         if ((rc = prepare(k, lds)) != CS_OK) return rc;
-        hipLaunchKernelGGL(k, dim3(grid_for(hb.B)), dim3(256), lds, stream, hb.bv, K, mode,
+        hipLaunchKernelGGL(k, dim3(grid_for(hb.bv.B)), dim3(256), lds, stream, hb.bv, K, mode,
                            (T)p->tol, hb.nmax, hb.mmax, (const T *)M, (const T *)J, (const T *)a0,
                            (const T *)aref, (const T *)D, (const T *)abar, (T *)a_out,
                            (T *)a0bar, (T *)arefbar, (T *)Jbar, (T *)Dbar, (T *)Mbar, tT, tB,

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace cs {
 
 enum : int {
@@ -77,6 +79,25 @@ __device__ inline int64_t tape_T_offset(const Inst &I, int K) {
 }
 __device__ inline int64_t tape_B_offset(const Inst &I, int K) { return (int64_t)K * 2 * I.om; }
 
+// Raise a kernel's dynamic-LDS limit once; later launches (for instance inside
+// a captured HIP graph) make no runtime call.  Returns false on a HIP error.
+inline bool ensure_lds(const void *kernel, size_t lds) {
+    static std::mutex mu;
+    static const void *keys[128];
+    static size_t vals[128];
+    static int nk = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    int i = 0;
+    while (i < nk && keys[i] != kernel) ++i;
+    if (i < nk && vals[i] >= lds) return true;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        return false;
+    if (i == nk && nk < 128) keys[nk++] = kernel;
+    if (i < 128) vals[i] = lds;
+    return true;
+}
+
 template <typename T> __device__ inline T inf_val();
 template <> __device__ inline float inf_val<float>() { return __builtin_huge_valf(); }
 template <> __device__ inline double inf_val<double>() { return __builtin_huge_val(); }
@@ -127,35 +148,38 @@ __device__ inline void team_sum(T (&v)[NV], T *sred) {
 // triangle read and overwritten strictly below the diagonal; the diagonal of
 // L goes to diag[]).  Left-looking by columns, one barrier per column.
 // Returns false (team-uniform) when a pivot is not positive.
+// The matrix has row stride ld (ld = n for a dense n x n block).
 template <int NT, typename T>
-__device__ inline bool team_cholesky(T *H, T *diag, int n) {
+__device__ inline bool team_cholesky(T *H, T *diag, int n, int ld) {
     bool ok = true;
     for (int j = 0; j < n; ++j) {
-        T s = H[j * n + j];
-        for (int k = 0; k < j; ++k) s -= H[j * n + k] * H[j * n + k];
+        T s = H[j * ld + j];
+        for (int k = 0; k < j; ++k) s -= H[j * ld + k] * H[j * ld + k];
         ok = ok && (s > T(0));
         const T ljj = sqrt(s);
         const T inv = T(1) / ljj;
         for (int i = j + 1 + (int)threadIdx.x; i < n; i += NT) {
-            T t = H[i * n + j];
-            for (int k = 0; k < j; ++k) t -= H[i * n + k] * H[j * n + k];
-            H[i * n + j] = t * inv;
+            T t = H[i * ld + j];
+            for (int k = 0; k < j; ++k) t -= H[i * ld + k] * H[j * ld + k];
+            H[i * ld + j] = t * inv;
         }
         if ((int)threadIdx.x == (j % NT)) diag[j] = ljj;
         __syncthreads();
     }
     return ok;
 }
+template <int NT, typename T>
+__device__ inline bool team_cholesky(T *H, T *diag, int n) { return team_cholesky<NT>(H, diag, n, n); }
 
 // Solve L L^T x = b with the factor from team_cholesky.  b is overwritten;
 // the solution is returned in x.  One barrier per column and direction.
 template <int NT, typename T>
-__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
+__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
     // forward: L y = b, y stored in x
     for (int j = 0; j < n; ++j) {
         const T yj = b[j] / diag[j];
         if ((int)threadIdx.x == (j % NT)) x[j] = yj;
-        for (int i = j + 1 + (int)threadIdx.x; i < n; i += NT) b[i] -= L[i * n + j] * yj;
+        for (int i = j + 1 + (int)threadIdx.x; i < n; i += NT) b[i] -= L[i * ld + j] * yj;
         __syncthreads();
     }
     // backward: L^T x = y (in place in x)
@@ -163,9 +187,13 @@ __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, in
         const T xj = x[j] / diag[j];
         __syncthreads();
         if ((int)threadIdx.x == (j % NT)) x[j] = xj;
-        for (int i = (int)threadIdx.x; i < j; i += NT) x[i] -= L[j * n + i] * xj;
+        for (int i = (int)threadIdx.x; i < j; i += NT) x[i] -= L[j * ld + i] * xj;
         __syncthreads();
     }
+}
+template <int NT, typename T>
+__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
+    team_chol_solve<NT>(L, diag, b, x, n, n);
 }
 
 // Exact line search along p (Sec. III-B, eq. 10): the minimiser of

@@ -837,15 +837,15 @@ inline int small_r(int m) {
 }
 
 // FP32: n <= 12; FP64 (twice the registers per value): n <= 6.
-inline bool small_supported(int nmax, int mmax, bool packed, int s) {
+inline bool small_supported(int nmax, int mmax, int s) {
     const int np = small_np(nmax);
-    return !packed && np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 12 : np <= 6);
+    return np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 12 : np <= 6);
 }
 
 // The unrolled kernel also keeps the J-bar rows and M-bar in registers.
-inline bool small_unrolled_supported(int nmax, int mmax, bool packed, int s) {
+inline bool small_unrolled_supported(int nmax, int mmax, int s) {
     const int np = small_np(nmax);
-    return !packed && np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 9 : np <= 6);
+    return np != 0 && small_r(mmax) != 0 && (s == 4 ? np <= 9 : np <= 6);
 }
 
 #define CS_SMALL_DISPATCH(NPV, RV, CALL)                                                      \
