@@ -1,0 +1,128 @@
+"""Continuous batching of MPC windows on the GPU.
+
+* every request served by the engine (FP64, mixed shapes n in {3,9,18},
+  0..64 contacts, queued behind a small slot table) returns the same final
+  velocity and actuation gradient as an autograd rollout of that request
+  alone through contact_solve;
+* a request gives the same result alone and inside a mix (FP32);
+* admission never holds more requests than the HBM budget has slots, and the
+  engine's device footprint stays within the budget;
+* a Poisson stream completes and reports latency percentiles.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2607_24959_amd import serve
+from paper_2607_24959_amd.rollout import rollout
+
+pytestmark = pytest.mark.gpu
+
+N_CHOICES = (3, 9, 18)
+NC_MAX = 64
+W = 6
+
+
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _pool(count, dtype, seed=5):
+    return serve.RequestPool(count, N_CHOICES, NC_MAX, W, seed, 18, 4 * NC_MAX, dtype, "cuda")
+
+
+def _serve_all(engine, pool, ids):
+    engine.attach_pool(pool)
+    engine.keep_results = True
+    for k, i in enumerate(ids):
+        engine.submit(serve.Request(rid=k, pool_index=int(i), n=int(pool.n[i]), m=int(pool.m[i])))
+    ticks = 0
+    while len(engine.finished) < len(ids):
+        engine.tick(float("inf"))
+        ticks += 1
+        assert ticks <= 2 * W * len(ids) + 4
+    torch.cuda.synchronize()
+    return ticks
+
+
+def _reference(pool, i, max_iter, tol):
+    """Autograd rollout of one request alone (IFT backward)."""
+    n, m = int(pool.n[i]), int(pool.m[i])
+    M = pool.Mp[i, :n, :n].unsqueeze(0)
+    J = pool.Jp[i, :m, :n].unsqueeze(0)
+    D = pool.D[i, :m].unsqueeze(0)
+    pen = pool.pen[i, :m:4].unsqueeze(0)
+    v0 = pool.v0[i, :n].unsqueeze(0)
+    goal = pool.goal[i, :n]
+    tau = pool.tau[i, :, :n].unsqueeze(1).clone().requires_grad_(True)
+    v = rollout(M, J, D, pen, v0, tau, h=0.002, max_iter=max_iter, tol=tol)
+    ((v[0] - goal) ** 2).sum().backward()
+    return v[0].detach(), tau.grad[:, 0].detach()
+
+
+def test_engine_matches_per_request_rollout_fp64():
+    _needs_gpu()
+    pool = _pool(24, torch.float64)
+    eng = serve.Engine(slots=5, window=W, max_iter=60, tol=1e-12, dtype=torch.float64)
+    ids = np.arange(24)
+    _serve_all(eng, pool, ids)
+    assert eng.max_active <= 5
+    errs = []
+    for k, i in enumerate(ids):
+        n = int(pool.n[i])
+        out = eng.results[k]
+        v_ref, g_ref = _reference(pool, i, 60, 1e-12)
+        ev = (torch.linalg.norm(out[:n] - v_ref) / torch.linalg.norm(v_ref)).item()
+        eg = (torch.linalg.norm(out[n:] - g_ref.reshape(-1)) / torch.linalg.norm(g_ref)).item()
+        errs.append((max(ev, eg), int(i), n, int(pool.m[i])))
+    errs.sort(reverse=True)
+    print("worst", errs[:3])
+    assert errs[0][0] <= 1e-9, errs[:3]
+
+
+def test_alone_equals_in_mix_fp32():
+    _needs_gpu()
+    pool = _pool(40, torch.float32, seed=11)
+    mix = serve.Engine(slots=16, window=W, max_iter=20, tol=1e-5)
+    _serve_all(mix, pool, np.arange(40))
+    n_bitwise = 0
+    for i in (0, 3, 17, 39):
+        alone = serve.Engine(slots=1, window=W, max_iter=20, tol=1e-5)
+        _serve_all(alone, pool, [i])
+        a, b = alone.results[0], mix.results[i]
+        n_bitwise += int(torch.equal(a, b))
+        e = (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+        assert e <= 1e-6, (i, e)
+    print("bitwise equal", n_bitwise, "of 4")
+
+
+def test_admission_within_budget():
+    _needs_gpu()
+    pool = _pool(12, torch.float32, seed=13)
+    per = serve.slot_bytes(18, 4 * NC_MAX, W, 4)
+    budget = 3 * per + per // 2
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    eng = serve.Engine(budget_bytes=budget, window=W, max_iter=20, tol=1e-5)
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - base
+    assert eng.S == 3
+    # slot arrays plus the allocator's rounding of each tensor
+    assert held <= budget + 64 * 1024, (held, budget)
+    _serve_all(eng, pool, np.arange(12))
+    assert eng.max_active == 3
+    assert len(eng.finished) == 12
+    with pytest.raises(ValueError):
+        serve.Engine(budget_bytes=per - 1, window=W)
+
+
+def test_poisson_stream_reports_latency():
+    _needs_gpu()
+    pool = _pool(64, torch.float32, seed=17)
+    eng = serve.Engine(slots=256, window=W, max_iter=10, tol=1e-5)
+    eng.attach_pool(pool)
+    res = serve.run_stream(eng, rate=2000.0, n_requests=300, warmup=50, seed=1)
+    print(res)
+    assert res["requests"] == 300
+    assert 0 < res["p50_ms"] <= res["p99_ms"] < 1e4
