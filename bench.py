@@ -74,11 +74,117 @@ def cpu_baseline(b32, seconds=10.0):
         done += P.B
         reps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or reps >= 400:
+        if el >= seconds:
             break
     return dict(value=done / el, unit="solves/s", cores=threads, kind="oracle",
                 sample=f"{reps} passes of forward + IFT VJP over one B={B} batch (FP64 oracle on "
                        f"the FP32-rounded inputs, {threads} OpenMP threads, {el:.1f} s)")
+
+
+def k_sweep(bufs, batch, steps=30):
+    """IFT (forward at cap K + VJP) against the unrolled trace at K = 1..10:
+    time per batch and the temporary device memory of each gradient path."""
+    import torch
+    from paper_2607_24959_amd import solver
+    R = len(bufs)
+    tape = torch.empty(batch.tape_bytes(10), dtype=torch.uint8, device="cuda")
+    out = []
+    for K in range(1, 11):
+        row = {"K": K}
+        for mode in ("ift", "unrolled"):
+            def run(i, mode=mode, K=K):
+                t, sol, grads = bufs[i % R]
+                if mode == "ift":
+                    solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=TOL,
+                                   out=sol)
+                    solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                                   out=grads)
+                else:
+                    solver.unrolled_vjp(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                                        K=K, tol=TOL, tape=tape)
+            for i in range(3):
+                run(i)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(steps):
+                run(i)
+            e1.record()
+            torch.cuda.synchronize()
+            row[f"{mode}_ms"] = e0.elapsed_time(e1) / steps
+            # peak temporary memory of one fresh call (outputs allocated by the call)
+            torch.cuda.synchronize()
+            base = torch.cuda.memory_allocated()
+            torch.cuda.reset_peak_memory_stats()
+            t = bufs[0][0]
+            if mode == "ift":
+                sol = solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=TOL)
+                g = solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"])
+            else:
+                g = solver.unrolled_vjp(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                                        K=K, tol=TOL)
+            torch.cuda.synchronize()
+            row[f"{mode}_peak_bytes"] = torch.cuda.max_memory_allocated() - base
+            del g
+        row["state_bytes"] = batch.state_bytes()
+        row["tape_bytes"] = batch.tape_bytes(K)
+        row["ift_over_unrolled"] = row["unrolled_ms"] / row["ift_ms"]
+        out.append(row)
+    return out
+
+
+def uneven(reps=20):
+    """B=8192 packed instances, nv in {3,9,18,36,96}, contacts U{0..256}, FP32:
+    tile classes from the autotuned table, LPT order, forward + IFT VJP of all
+    classes captured in one HIP graph and replayed."""
+    import torch
+    from paper_2607_24959_amd import batching, solver, synth
+    t0 = time.perf_counter()
+    pb = synth.uneven_batch(8192, (3, 9, 18, 36, 96), 256, seed=synth.SEED_BASE + 2).astype(np.float32)
+    gen_s = time.perf_counter() - t0
+    batch = solver.Batch.packed_from(pb.nv, pb.nrows, torch.float32)
+    plan = batching.Plan(batch)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(pb, k))).to("cuda") for k in
+         ("M", "J", "a0", "aref", "D", "abar")}
+    sol, grads = plan.capture(t, max_iter=K_CAP, tol=TOL)
+    for _ in range(2):
+        plan.graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = pb.nv.astype(np.float64)
+    m = pb.nrows.astype(np.float64)
+    byt = float(np.sum([sum(algorithmic_bytes(a, b)) for a, b in zip(n, m)]))
+    st = sol.status.cpu().numpy()
+    return {"workload": "packed B=8192, nv in {3,9,18,36,96}, contacts U{0..256}, FP32, K=10",
+            "ms_per_batch": ms, "solves_per_s": 8192 / (ms / 1e3),
+            "gbps_algorithmic": byt / (ms / 1e3) / 1e9, "bytes_per_batch": byt,
+            "converged_frac": float(np.mean(st & 1)), "classes": plan.summary(),
+            "table": os.path.basename(batching.TABLE_PATH) if os.path.exists(batching.TABLE_PATH) else None,
+            "generation_s": round(gen_s, 1)}
+
+
+def serving(rates=(2000, 5000, 10000, 20000, 50000), n_requests=10000, warmup=1000,
+            budget_bytes=256 * 2 ** 20):
+    """Poisson streams of 6-step MPC windows (nv in {3,9,18}, contacts U{0..64},
+    FP32, Newton cap 10), slots from an HBM budget."""
+    import torch
+    from paper_2607_24959_amd import serve
+    pool = serve.RequestPool(4096, (3, 9, 18), 64, 6, 20260802, 18, 256, torch.float32, "cuda")
+    out = []
+    for rate in rates:
+        eng = serve.Engine(budget_bytes=budget_bytes, window=6, max_iter=K_CAP, tol=TOL)
+        eng.attach_pool(pool)
+        r = serve.run_stream(eng, rate=float(rate), n_requests=n_requests, warmup=warmup, seed=rate)
+        r["budget_MiB"] = budget_bytes / 2 ** 20
+        out.append(r)
+        del eng
+    return out
 
 
 def main():
@@ -88,6 +194,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the K sweep, the uneven batch and the serving streams")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -221,6 +329,10 @@ def main():
         out["unrolled"] = {"value": u_val, "unit": "solves/s", "K": K_CAP, "ms_per_step": u_ms,
                            "ift_over_unrolled": value / u_val}
 
+    if not args.no_extra:
+        out["k_sweep"] = k_sweep(bufs, batch)
+        out["uneven"] = uneven()
+        out["serving"] = serving()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host[0])
     print(json.dumps(out), flush=True)

@@ -1,4 +1,4 @@
-"""ctypes binding of libcs.so: the C ABI of include/cs.h, nothing more.
+"""ctypes binding of libcs.so: the C ABI of include/cs.h and include/cs_serve.h.
 
 Every function here marshals arguments and calls the library; all of the
 method runs in the HIP kernels.  Importing this module loads the library and
@@ -19,7 +19,8 @@ NV_MAX, NROWS_MAX = 128, 4096
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK = 0, 1, 2, 3
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
-            "cs_unrolled_tape_bytes", "cs_strerror", "cs_version")
+            "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
+            "cs_serve_admit", "cs_serve_pre", "cs_serve_post")
 
 
 class CsBatch(C.Structure):
@@ -39,6 +40,23 @@ class CsBatch(C.Structure):
 
 class CsSolverParams(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("flags", C.c_int32), ("tol", C.c_double)]
+
+
+class CsServeTable(C.Structure):
+    _fields_ = [
+        ("dtype", C.c_int32), ("slots", C.c_int32), ("window", C.c_int32),
+        ("n_cap", C.c_int32), ("m_cap", C.c_int32), ("reserved", C.c_int32),
+        ("h", C.c_double), ("b_damp", C.c_double), ("k_spring", C.c_double),
+        ("M", C.c_void_p), ("Minv", C.c_void_p), ("J", C.c_void_p), ("D", C.c_void_p),
+        ("pen", C.c_void_p), ("v", C.c_void_p), ("goal", C.c_void_p), ("tau", C.c_void_p),
+        ("nv", C.c_void_p), ("nrows", C.c_void_p),
+        ("vbar", C.c_void_p), ("taubar", C.c_void_p),
+        ("a0", C.c_void_p), ("abar", C.c_void_p), ("a", C.c_void_p), ("a0bar", C.c_void_p),
+        ("aref", C.c_void_p), ("arefbar", C.c_void_p),
+        ("state", C.c_void_p), ("mask_offset", C.c_uint64),
+        ("arch_a", C.c_void_p), ("arch_a0", C.c_void_p), ("arch_aref", C.c_void_p),
+        ("arch_fac", C.c_void_p), ("arch_mask", C.c_void_p),
+    ]
 
 
 class CsError(RuntimeError):
@@ -73,6 +91,12 @@ def lib():
         L.cs_unrolled_vjp.restype = C.c_int
         L.cs_unrolled_vjp.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                       sz, vp, vp, vp]
+        pt = C.POINTER(CsServeTable)
+        L.cs_serve_admit.restype = C.c_int
+        L.cs_serve_admit.argtypes = [pt, pt, vp, i32, vp]
+        for name in ("cs_serve_pre", "cs_serve_post"):
+            getattr(L, name).restype = C.c_int
+            getattr(L, name).argtypes = [pt, vp, i32, vp]
         _lib = L
     return _lib
 
@@ -115,3 +139,15 @@ def unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, 
     return lib().cs_unrolled_vjp(C.byref(batch), C.byref(params), M, J, a0, aref, D, abar, a_out,
                                  a0bar, arefbar, Jbar, Dbar, Mbar, tape, tape_nbytes, status,
                                  iters, stream)
+
+
+def serve_admit(table, pool, pairs, count, stream):
+    return lib().cs_serve_admit(C.byref(table), C.byref(pool), pairs, int(count), stream)
+
+
+def serve_pre(table, entries, count, stream):
+    return lib().cs_serve_pre(C.byref(table), entries, int(count), stream)
+
+
+def serve_post(table, entries, count, stream):
+    return lib().cs_serve_post(C.byref(table), entries, int(count), stream)

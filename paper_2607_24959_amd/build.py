@@ -23,7 +23,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "cs_api.hip")]
+    srcs = [os.path.join(CSRC, "cs_api.hip"), os.path.join(CSRC, "cs_serve.hip")]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, *srcs]
     if verbose:

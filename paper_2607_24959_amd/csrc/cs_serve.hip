@@ -1,0 +1,250 @@
+// cs_serve.hip -- device steps of the MPC-window serving loop (include/cs_serve.h).
+//
+// One 64-lane workgroup per entry: every entry touches one slot only (a few
+// hundred values), so the launch is latency-bound and a single wave per slot
+// keeps it free of barriers between entries.  All copies and products walk
+// the slot's live sizes with lane-strided, coalesced accesses.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cs.h"
+#include "cs_serve.h"
+
+namespace {
+
+constexpr int WL = 64;   // lanes per entry
+
+struct Geo {
+    int S, W, nc, mc;
+    int64_t ne;          // factor capacity per slot
+};
+
+__device__ inline Geo geo(const cs_serve_table &t) {
+    return Geo{t.slots, t.window, t.n_cap, t.m_cap, (int64_t)t.n_cap * (t.n_cap + 1) / 2};
+}
+
+template <typename T> __device__ inline T *P(void *p) { return static_cast<T *>(p); }
+
+template <typename T>
+__global__ __launch_bounds__(WL) void k_serve_admit(cs_serve_table t, cs_serve_table p,
+                                                    const int32_t *__restrict__ pairs, int count) {
+    const int e = blockIdx.x, l = threadIdx.x;
+    if (e >= count) return;
+    const Geo G = geo(t);
+    const int s = pairs[2 * e], q = pairs[2 * e + 1];
+    if (s < 0 || s >= G.S || q < 0 || q >= p.slots) return;
+    const int n = p.nv[q], m = p.nrows[q];
+    if (n < 1 || n > G.nc || m < 0 || m > G.mc) return;
+    const int64_t nn = (int64_t)G.nc * G.nc, mn = (int64_t)G.mc * G.nc;
+    const T *pM = P<T>(p.M) + q * nn, *pMi = P<T>(p.Minv) + q * nn, *pJ = P<T>(p.J) + q * mn;
+    T *sM = P<T>(t.M) + s * nn, *sMi = P<T>(t.Minv) + s * nn, *sJ = P<T>(t.J) + s * mn;
+    for (int i = l; i < n * n; i += WL) {
+        sM[i] = pM[i];
+        sMi[i] = pMi[i];
+    }
+    for (int64_t i = l; i < (int64_t)m * n; i += WL) sJ[i] = pJ[i];
+    for (int i = l; i < m; i += WL) {
+        P<T>(t.D)[(int64_t)s * G.mc + i] = P<T>(p.D)[(int64_t)q * G.mc + i];
+        P<T>(t.pen)[(int64_t)s * G.mc + i] = P<T>(p.pen)[(int64_t)q * G.mc + i];
+    }
+    for (int i = l; i < G.nc; i += WL) {
+        P<T>(t.v)[(int64_t)s * G.nc + i] = P<T>(p.v)[(int64_t)q * G.nc + i];
+        P<T>(t.goal)[(int64_t)s * G.nc + i] = P<T>(p.goal)[(int64_t)q * G.nc + i];
+        P<T>(t.vbar)[(int64_t)s * G.nc + i] = T(0);
+    }
+    for (int i = l; i < G.W * G.nc; i += WL) {
+        P<T>(t.tau)[(int64_t)s * G.W * G.nc + i] = P<T>(p.tau)[(int64_t)q * G.W * G.nc + i];
+        P<T>(t.taubar)[(int64_t)s * G.W * G.nc + i] = T(0);
+    }
+    if (l == 0) {
+        t.nv[s] = n;
+        t.nrows[s] = m;
+    }
+}
+
+// Entry decode shared by pre and post; false when the entry is out of range.
+__device__ inline bool entry(const cs_serve_table &t, const Geo &G, const int32_t *ent, int e,
+                             int &s, int &step, bool &fwd, int &n, int &m) {
+    s = ent[2 * e];
+    const int ph = ent[2 * e + 1];
+    if (s < 0 || s >= G.S || ph < 0 || ph >= 2 * G.W) return false;
+    fwd = ph < G.W;
+    step = fwd ? ph : 2 * G.W - 1 - ph;
+    n = t.nv[s];
+    m = t.nrows[s];
+    return n >= 1 && n <= G.nc && m >= 0 && m <= G.mc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(WL) void k_serve_pre(cs_serve_table t, const int32_t *__restrict__ ent,
+                                                  int count) {
+    const int e = blockIdx.x, l = threadIdx.x;
+    if (e >= count) return;
+    const Geo G = geo(t);
+    int s, st, n, m;
+    bool fwd;
+    if (!entry(t, G, ent, e, s, st, fwd, n, m)) return;
+    const int64_t on = (int64_t)s * G.nc, om = (int64_t)s * G.mc;
+    if (fwd) {
+        // a0 = M^{-1} tau_t
+        const T *Mi = P<T>(t.Minv) + (int64_t)s * G.nc * G.nc;
+        const T *tau = P<T>(t.tau) + ((int64_t)s * G.W + st) * G.nc;
+        for (int i = l; i < n; i += WL) {
+            T acc = T(0);
+            for (int j = 0; j < n; ++j) acc += Mi[i * n + j] * tau[j];
+            P<T>(t.a0)[on + i] = acc;
+        }
+        // aref = -b J v - k pen
+        const T *J = P<T>(t.J) + (int64_t)s * G.mc * G.nc;
+        const T *v = P<T>(t.v) + on;
+        const T b = T(t.b_damp), k = T(t.k_spring);
+        for (int r = l; r < m; r += WL) {
+            T acc = T(0);
+            for (int j = 0; j < n; ++j) acc += J[(int64_t)r * n + j] * v[j];
+            P<T>(t.aref)[om + r] = -b * acc - k * P<T>(t.pen)[om + r];
+        }
+    } else {
+        const int64_t an = ((int64_t)st * G.S + s) * G.nc, am = ((int64_t)st * G.S + s) * G.mc;
+        for (int i = l; i < n; i += WL) {
+            P<T>(t.a)[on + i] = P<T>(t.arch_a)[an + i];
+            P<T>(t.a0)[on + i] = P<T>(t.arch_a0)[an + i];
+            P<T>(t.abar)[on + i] = T(t.h) * P<T>(t.vbar)[on + i];
+        }
+        for (int r = l; r < m; r += WL) {
+            P<T>(t.aref)[om + r] = P<T>(t.arch_aref)[am + r];
+            t.state[t.mask_offset + om + r] = t.arch_mask[am + r];
+        }
+        const int ne = n * (n + 1) / 2;
+        const T *src = P<T>(t.arch_fac) + ((int64_t)st * G.S + s) * G.ne;
+        T *dst = reinterpret_cast<T *>(t.state) + (int64_t)s * G.ne;
+        for (int i = l; i < ne; i += WL) dst[i] = src[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WL) void k_serve_post(cs_serve_table t, const int32_t *__restrict__ ent,
+                                                   int count) {
+    __shared__ T part[WL];
+    const int e = blockIdx.x, l = threadIdx.x;
+    if (e >= count) return;
+    const Geo G = geo(t);
+    int s, st, n, m;
+    bool fwd;
+    if (!entry(t, G, ent, e, s, st, fwd, n, m)) return;
+    const int64_t on = (int64_t)s * G.nc, om = (int64_t)s * G.mc;
+    if (fwd) {
+        const int64_t an = ((int64_t)st * G.S + s) * G.nc, am = ((int64_t)st * G.S + s) * G.mc;
+        const T h = T(t.h);
+        for (int i = l; i < n; i += WL) {
+            const T a = P<T>(t.a)[on + i];
+            P<T>(t.arch_a)[an + i] = a;
+            P<T>(t.arch_a0)[an + i] = P<T>(t.a0)[on + i];
+            const T vn = P<T>(t.v)[on + i] + h * a;
+            P<T>(t.v)[on + i] = vn;
+            if (st == G.W - 1) P<T>(t.vbar)[on + i] = T(2) * (vn - P<T>(t.goal)[on + i]);
+        }
+        for (int r = l; r < m; r += WL) {
+            P<T>(t.arch_aref)[am + r] = P<T>(t.aref)[om + r];
+            t.arch_mask[am + r] = t.state[t.mask_offset + om + r];
+        }
+        const int ne = n * (n + 1) / 2;
+        const T *src = reinterpret_cast<const T *>(t.state) + (int64_t)s * G.ne;
+        T *dst = P<T>(t.arch_fac) + ((int64_t)st * G.S + s) * G.ne;
+        for (int i = l; i < ne; i += WL) dst[i] = src[i];
+    } else {
+        // taubar_t = M^{-T} a0bar
+        const T *Mi = P<T>(t.Minv) + (int64_t)s * G.nc * G.nc;
+        const T *a0b = P<T>(t.a0bar) + on;
+        for (int i = l; i < n; i += WL) {
+            T acc = T(0);
+            for (int j = 0; j < n; ++j) acc += Mi[j * n + i] * a0b[j];
+            P<T>(t.taubar)[((int64_t)s * G.W + st) * G.nc + i] = acc;
+        }
+        // vbar -= b J^T arefbar: lane (column c, part p) sums rows p, p + np, ...
+        const T *J = P<T>(t.J) + (int64_t)s * G.mc * G.nc;
+        const T *rb = P<T>(t.arefbar) + om;
+        const int np = WL / n;          // n <= n_cap <= 64
+        const int c = l % n, pp = l / n;
+        T acc = T(0);
+        if (pp < np)
+            for (int r = pp; r < m; r += np) acc += J[(int64_t)r * n + c] * rb[r];
+        part[l] = acc;
+        __syncthreads();
+        if (l < n) {
+            T sum = T(0);
+            for (int q = 0; q < np; ++q) sum += part[q * n + l];
+            P<T>(t.vbar)[on + l] -= T(t.b_damp) * sum;
+        }
+    }
+}
+
+int check_table(const cs_serve_table *t, bool slots_table) {
+    if (!t) return CS_EINVAL;
+    if (t->dtype != CS_F32 && t->dtype != CS_F64) return CS_EINVAL;
+    if (t->slots < 1 || t->window < 1 || t->n_cap < 1 || t->n_cap > 64 || t->m_cap < 0 ||
+        t->m_cap > CS_NROWS_MAX)
+        return CS_EINVAL;
+    if (!t->M || !t->Minv || !t->v || !t->goal || !t->tau || !t->nv || !t->nrows) return CS_EINVAL;
+    if (t->m_cap > 0 && (!t->J || !t->D || !t->pen)) return CS_EINVAL;
+    if (slots_table) {
+        if (!t->vbar || !t->taubar || !t->a0 || !t->abar || !t->a || !t->a0bar || !t->state ||
+            !t->arch_a || !t->arch_a0 || !t->arch_fac)
+            return CS_EINVAL;
+        if (t->m_cap > 0 && (!t->aref || !t->arefbar || !t->arch_aref || !t->arch_mask))
+            return CS_EINVAL;
+    }
+    return CS_OK;
+}
+
+template <typename K>
+int launch(K kernel, int count, hipStream_t st, const cs_serve_table &a, const int32_t *list) {
+    hipLaunchKernelGGL(kernel, dim3(count), dim3(WL), 0, st, a, list, count);
+    return hipGetLastError() == hipSuccess ? CS_OK : CS_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cs_serve_admit(const cs_serve_table *table, const cs_serve_table *pool, const int32_t *pairs,
+                   int32_t count, void *stream) {
+    int rc = check_table(table, true);
+    if (rc == CS_OK) rc = check_table(pool, false);
+    if (rc != CS_OK) return rc;
+    if (pool->dtype != table->dtype || pool->n_cap != table->n_cap ||
+        pool->m_cap != table->m_cap || pool->window != table->window)
+        return CS_EINVAL;
+    if (count < 0 || (count > 0 && !pairs)) return CS_EINVAL;
+    if (count == 0) return CS_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (table->dtype == CS_F32)
+        hipLaunchKernelGGL(k_serve_admit<float>, dim3(count), dim3(WL), 0, st, *table, *pool, pairs,
+                           count);
+    else
+        hipLaunchKernelGGL(k_serve_admit<double>, dim3(count), dim3(WL), 0, st, *table, *pool, pairs,
+                           count);
+    return hipGetLastError() == hipSuccess ? CS_OK : CS_EHIP;
+}
+
+int cs_serve_pre(const cs_serve_table *table, const int32_t *entries, int32_t count, void *stream) {
+    const int rc = check_table(table, true);
+    if (rc != CS_OK) return rc;
+    if (count < 0 || (count > 0 && !entries)) return CS_EINVAL;
+    if (count == 0) return CS_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return table->dtype == CS_F32 ? launch(k_serve_pre<float>, count, st, *table, entries)
+                                  : launch(k_serve_pre<double>, count, st, *table, entries);
+}
+
+int cs_serve_post(const cs_serve_table *table, const int32_t *entries, int32_t count, void *stream) {
+    const int rc = check_table(table, true);
+    if (rc != CS_OK) return rc;
+    if (count < 0 || (count > 0 && !entries)) return CS_EINVAL;
+    if (count == 0) return CS_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return table->dtype == CS_F32 ? launch(k_serve_post<float>, count, st, *table, entries)
+                                  : launch(k_serve_post<double>, count, st, *table, entries);
+}
+
+}  // extern "C"

@@ -1,30 +1,29 @@
 """Continuous-batching engine for MPC-window requests.
 
-A request is one W-step window of the semi-implicit rollout (the model of
-rollout.py): W forward contact solves with v_{t+1} = v_t + h a_t, then W IFT
-VJPs in reverse for the gradient of ||v_W - v_goal||^2 w.r.t. the actuation
-tau of every step.
+A request is one W-step window of the semi-implicit rollout that the
+paper's trajectory optimisation and short-horizon residual MPC run (Sec.
+IV-A, Sec. V): W forward contact solves with v_{t+1} = v_t + h a_t, then W
+IFT VJPs in reverse for the gradient of ||v_W - v_goal||^2 w.r.t. the
+actuation tau_t of every step.
 
 The engine keeps a fixed table of S slots in device memory, each with room
 for the largest request shape (n_cap, m_cap); S follows from an HBM budget.
 Every tick it
-  1. admits queued requests into free slots (device-to-device copies),
-  2. runs one batched cs_ift_vjp per kernel family over all slots in a
-     backward phase, after restoring each slot's saved factor of H(A*) for
-     its step from the per-step archive (factorisations stay on device),
-  3. runs one batched cs_forward per kernel family over all slots in a
-     forward phase and archives each slot's solution, factor and active set,
-  4. advances every slot's phase; finished requests free their slot.
-Requests at different phases share launches, and newly admitted work
-overlaps with work already on the device.  An instance's arithmetic does not
-depend on its slot or on the other slots, so a request's result is the same
-alone and in any mix.
-
-Slot layout: matrices are kept twice, tightly packed at the slot's offset
-for the kernels (M: first n^2 of n_cap^2 elements, J: first m n of
-m_cap n_cap) and padded ([n_cap, n_cap] with an identity block, [m_cap,
-n_cap] with zeros) for the dense torch glue; vectors are padded at the end,
-which is both layouts at once.
+  1. admits queued requests into free slots (cs_serve_admit),
+  2. prepares every occupied slot's step (cs_serve_pre): the forward inputs
+     a0 = M^{-1} tau_t, aref = -b J v_t - k pen, or, in the backward phase,
+     the solution, factor and active set of step t restored from the
+     per-step archive, so factorisations stay on the device and are reused,
+  3. runs one cs_ift_vjp per kernel class over the slots in a backward phase
+     and one cs_forward per class over the slots in a forward phase,
+  4. consumes the outputs (cs_serve_post): archive, v += h a, or the
+     gradient recursion, and advances every slot's phase on the host.
+Requests at different phases share launches; admission needs only a free
+slot, so new work overlaps with work already on the device.  The host side
+of a tick is one pinned host-to-device copy of the tick's index lists and a
+fixed number of launches; it never synchronises.  An instance's arithmetic
+does not depend on its slot or on the other slots (kernel classes have fixed
+compile-time sizes), so a request's result is the same alone and in any mix.
 """
 from __future__ import annotations
 
@@ -50,30 +49,41 @@ class Request:
     arrival: float = 0.0          # seconds on the engine clock
     admitted: float = -1.0
     done: float = -1.0
+    done_tick: int = -1
 
 
 def slot_bytes(n_cap, m_cap, window, s=4):
-    """Device bytes one slot holds (inputs, per-step archive, work and outputs)."""
+    """Device bytes one slot holds (payload, request state, work arrays, archive)."""
     ne = n_cap * (n_cap + 1) // 2
-    vals = (3 * n_cap * n_cap + 2 * m_cap * n_cap + 2 * m_cap      # M tight/padded/inverse, J x2, D, pen
-            + 6 * n_cap + 2 * window * n_cap                      # v, goal, vbar, a0, abar, mask, tau, tau-bar
-            + window * (2 * n_cap + m_cap + ne)                   # archived a, a0, aref, factor
-            + 2 * n_cap + 2 * m_cap + ne)                         # work a, grads, aref, factor
-    return vals * s + (window + 1) * m_cap                        # archived and work active sets
+    vals = (2 * n_cap * n_cap + m_cap * n_cap + 2 * m_cap      # M, M^-1, J, D, pen
+            + 7 * n_cap + 2 * window * n_cap                   # v, goal, vbar, a0, abar, a, a0bar; tau, taubar
+            + 2 * m_cap + ne                                   # aref, arefbar; factor
+            + window * (2 * n_cap + m_cap + ne))               # archived a, a0, aref, factor
+    return vals * s + (window + 1) * m_cap + 128               # active sets; sizes, offsets, status, lists
+
+
+def _dt(dtype):
+    return N.CS_F32 if dtype == torch.float32 else N.CS_F64
 
 
 class RequestPool:
-    """Device-resident request payloads (seeded synthetic) in both slot layouts."""
+    """Device-resident request payloads (seeded synthetic), in the slot layout.
+
+    ``Mp``/``Jp`` keep padded copies ([P, n_cap, n_cap] with an identity block,
+    [P, m_cap, n_cap]) for references outside the engine."""
 
     def __init__(self, count, n_choices, nc_max, window, seed, n_cap, m_cap, dtype, device):
         rng = np.random.Generator(np.random.PCG64(seed))
         self.n = rng.choice(np.asarray(n_choices), size=count).astype(np.int32)
         self.nc = rng.integers(0, nc_max + 1, size=count).astype(np.int32)
         self.m = (synth.ROWS_PER_CONTACT * self.nc).astype(np.int32)
+        if self.n.max() > n_cap or self.m.max() > m_cap:
+            raise ValueError("pool shapes exceed the slot capacity")
         P = count
-        Mt = np.zeros((P, n_cap * n_cap)); Jt = np.zeros((P, m_cap * n_cap))
+        Mt = np.zeros((P, n_cap * n_cap))
+        Jt = np.zeros((P, m_cap * n_cap))
         Mp = np.tile(np.eye(n_cap), (P, 1, 1)); Jp = np.zeros((P, m_cap, n_cap))
-        D = np.zeros((P, m_cap)); pen = np.zeros((P, m_cap)); nmask = np.zeros((P, n_cap))
+        D = np.zeros((P, m_cap)); pen = np.zeros((P, m_cap))
         v0 = np.zeros((P, n_cap)); goal = np.zeros((P, n_cap)); tau = np.zeros((P, window, n_cap))
         for i in range(P):
             n, nc, m = int(self.n[i]), int(self.nc[i]), int(self.m[i])
@@ -85,15 +95,29 @@ class RequestPool:
             Jp[i, :m, :n] = d["J"]
             D[i, :m] = d["D"]
             pen[i, :m] = np.repeat(d["pen"], synth.ROWS_PER_CONTACT)
-            nmask[i, :n] = 1.0
             v0[i, :n] = r2.standard_normal(n)
             goal[i, :n] = r2.standard_normal(n)
             tau[i, :, :n] = r2.standard_normal((window, n))
+        self.n_cap, self.m_cap, self.W, self.dtype = n_cap, m_cap, window, dtype
         t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(device, dtype)
         self.Mt, self.Jt, self.Mp, self.Jp = t(Mt), t(Jt), t(Mp), t(Jp)
-        self.Minv = torch.linalg.inv(self.Mp)
-        self.D, self.pen, self.nmask = t(D), t(pen), t(nmask)
+        Minv_p = torch.linalg.inv(self.Mp)          # block diagonal: inv(M) and the identity
+        self.Minv = torch.zeros_like(self.Mt)
+        for i in range(P):
+            n = int(self.n[i])
+            self.Minv[i, :n * n] = Minv_p[i, :n, :n].reshape(-1)
+        self.D, self.pen = t(D), t(pen)
         self.v0, self.goal, self.tau = t(v0), t(goal), t(tau)
+        self.nv = torch.from_numpy(self.n).to(device)
+        self.nrows = torch.from_numpy(self.m).to(device)
+        tb = N.CsServeTable()
+        tb.dtype, tb.slots, tb.window = _dt(dtype), P, window
+        tb.n_cap, tb.m_cap = n_cap, m_cap
+        vp = lambda x: x.data_ptr()
+        tb.M, tb.Minv, tb.J, tb.D, tb.pen = vp(self.Mt), vp(self.Minv), vp(self.Jt), vp(self.D), vp(self.pen)
+        tb.v, tb.goal, tb.tau = vp(self.v0), vp(self.goal), vp(self.tau)
+        tb.nv, tb.nrows = vp(self.nv), vp(self.nrows)
+        self.table = tb
 
 
 class Engine:
@@ -110,21 +134,22 @@ class Engine:
             slots = int(budget_bytes // self.bytes_per_slot)
         if slots < 1:
             raise ValueError("the HBM budget does not hold one request slot")
+        if n_cap > 64:
+            raise ValueError("n_cap is limited to 64")
         self.S = S = int(slots)
         dt = dtype
         z = lambda *shape: torch.zeros(shape, dtype=dt, device=dev)
         ne = n_cap * (n_cap + 1) // 2
-        # kernel layout (tight at the slot offset) and glue layout (padded)
-        self.Mt, self.Jt = z(S, n_cap * n_cap), z(S, m_cap * n_cap)
-        self.Minv, self.Jp = z(S, n_cap, n_cap), z(S, m_cap, n_cap)
-        self.D, self.pen, self.nmask = z(S, m_cap), z(S, m_cap), z(S, n_cap)
+        self.M, self.Minv = z(S, n_cap * n_cap), z(S, n_cap * n_cap)
+        self.J, self.D, self.pen = z(S, m_cap * n_cap), z(S, m_cap), z(S, m_cap)
         self.v, self.goal, self.vbar = z(S, n_cap), z(S, n_cap), z(S, n_cap)
         self.tau, self.taubar = z(S, window, n_cap), z(S, window, n_cap)
-        self.a0, self.aref, self.abar = z(S, n_cap), z(S, m_cap), z(S, n_cap)
+        self.a0, self.abar, self.a0bar = z(S, n_cap), z(S, n_cap), z(S, n_cap)
+        self.aref, self.arefbar = z(S, m_cap), z(S, m_cap)
         self.arch_a, self.arch_a0 = z(window, S, n_cap), z(window, S, n_cap)
         self.arch_aref, self.arch_fac = z(window, S, m_cap), z(window, S, ne)
         self.arch_mask = torch.zeros((window, S, m_cap), dtype=torch.uint8, device=dev)
-        # the slot table as a packed batch with capacity offsets; live sizes per slot
+        # the slot table as a packed batch with capacity offsets and live sizes
         self.nv_host = np.ones(S, dtype=np.int32)
         self.nr_host = np.zeros(S, dtype=np.int32)
         self.batch = solver.Batch.packed_from(np.full(S, n_cap), np.full(S, m_cap), dt, device=dev)
@@ -136,12 +161,32 @@ class Engine:
             a=z(S, n_cap), state=torch.zeros(self.batch.state_bytes(), dtype=torch.uint8, device=dev),
             status=torch.zeros(S, dtype=torch.int32, device=dev),
             iters=torch.zeros(S, dtype=torch.int32, device=dev))
-        fo = self.batch.mask_offset()
-        self.fac_view = self.sol.state[:S * ne * s].view(dt).view(S, ne)
-        self.mask_view = self.sol.state[fo:fo + S * m_cap].view(S, m_cap)
-        self.g_a0, self.g_aref = z(S, n_cap), z(S, m_cap)
+        tb = N.CsServeTable()
+        tb.dtype, tb.slots, tb.window, tb.n_cap, tb.m_cap = _dt(dt), S, window, n_cap, m_cap
+        tb.h, tb.b_damp, tb.k_spring = h, synth.B_DAMP, synth.K_SPRING
+        vp = lambda x: x.data_ptr()
+        tb.M, tb.Minv, tb.J, tb.D, tb.pen = vp(self.M), vp(self.Minv), vp(self.J), vp(self.D), vp(self.pen)
+        tb.v, tb.goal, tb.tau = vp(self.v), vp(self.goal), vp(self.tau)
+        tb.nv, tb.nrows = vp(self.nv_dev), vp(self.nr_dev)
+        tb.vbar, tb.taubar = vp(self.vbar), vp(self.taubar)
+        tb.a0, tb.abar, tb.a, tb.a0bar = vp(self.a0), vp(self.abar), vp(self.sol.a), vp(self.a0bar)
+        tb.aref, tb.arefbar = vp(self.aref), vp(self.arefbar)
+        tb.state, tb.mask_offset = vp(self.sol.state), self.batch.mask_offset()
+        tb.arch_a, tb.arch_a0, tb.arch_aref = vp(self.arch_a), vp(self.arch_a0), vp(self.arch_aref)
+        tb.arch_fac, tb.arch_mask = vp(self.arch_fac), vp(self.arch_mask)
+        self.table = tb
+        # per-tick index lists: admit pairs, step entries, launch orders
+        self.cap_list = 6 * S + 16
+        self.list_dev = torch.zeros(self.cap_list, dtype=torch.int32, device=dev)
+        pin = dev.type == "cuda"
+        self.list_pin = [torch.zeros(self.cap_list, dtype=torch.int32, pin_memory=pin)
+                         for _ in range(2)]
+        self.list_evt = [None, None]
+        self.ring = 0
+        self.params = N.CsSolverParams(int(max_iter), 0, float(tol))
         # host bookkeeping
         self.phase = np.full(S, -1, dtype=np.int64)   # -1 free; 0..W-1 forward; W..2W-1 backward
+        self.cls = np.zeros(S, dtype=np.int64)        # kernel class of the slot's request
         self.req: List[Optional[Request]] = [None] * S
         self.free = deque(range(S))
         self.queue: deque = deque()
@@ -150,10 +195,34 @@ class Engine:
         self.results: Dict[int, torch.Tensor] = {}
         self.keep_results = False
         self.max_active = 0
+        self.ticks = 0
+        self.classes = self._class_table()
+
+    # ------------------------------------------------------------ setup
+    def _class_table(self):
+        """Kernel classes with compile-time sizes fixed per class: small-family
+        classes by padded n with the 64-row layout, chunked classes by
+        workgroup size, each launched with the class's maximum sizes."""
+        out = []
+        s = 4 if self.dtype == torch.float32 else 8
+        for npad in batching.SMALL_NP:
+            if npad <= self.n_cap and ((s == 4 and npad <= 12) or (s == 8 and npad <= 6)):
+                out.append((N.PATH_SMALL, npad, min(64, self.m_cap)))
+        out.append((N.PATH_CHUNK, min(32, self.n_cap), self.m_cap))
+        if self.n_cap > 32:
+            out.append((N.PATH_CHUNK, self.n_cap, self.m_cap))
+        return out
+
+    def class_of(self, n, m):
+        fam = batching.default_family(self.dtype, n, m)
+        for c, (path, nmax, mmax) in enumerate(self.classes):
+            if path == fam and n <= nmax and m <= mmax:
+                return c
+        raise ValueError(f"no kernel class for n={n}, m={m}")
 
     def attach_pool(self, pool: RequestPool):
-        if pool.Mp.shape[1] != self.n_cap or pool.Jp.shape[1] != self.m_cap:
-            raise ValueError("pool capacity differs from the engine's")
+        if (pool.n_cap, pool.m_cap, pool.W, pool.dtype) != (self.n_cap, self.m_cap, self.W, self.dtype):
+            raise ValueError("pool capacity, window or dtype differs from the engine's")
         self.pool = pool
 
     def submit(self, req: Request):
@@ -162,43 +231,14 @@ class Engine:
         self.queue.append(req)
 
     def active(self):
-        return int(np.sum(self.phase >= 0))
-
-    # ------------------------------------------------------------ launches
-    def _launch_groups(self, slots):
-        """Split slots into launch groups (path, order, count, nmax, mmax) by the
-        planner's class rules, so a request runs the same kernel instance
-        whatever else shares its tick."""
-        groups: Dict[tuple, List[int]] = {}
-        for s in slots:
-            n, m = int(self.nv_host[s]), int(self.nr_host[s])
-            fam = batching.default_family(self.dtype, n, m)
-            if fam == N.PATH_SMALL:
-                key = (fam, batching.n_bucket(n), batching.m_bucket(m))
-            else:
-                key = (fam, 0 if n <= 32 else 1, 0)
-            groups.setdefault(key, []).append(s)
-        out = []
-        for key in sorted(groups):
-            idx = np.asarray(groups[key], dtype=np.int32)
-            nmax, mmax = int(self.nv_host[idx].max()), int(self.nr_host[idx].max())
-            if key[0] == N.PATH_SMALL:      # compile-time sizes follow the bucket, not the mix
-                nmax, mmax = max(nmax, min(key[1], self.n_cap)), max(mmax, min(key[2], self.m_cap))
-            out.append((key[0], torch.from_numpy(idx).to(self.device), len(idx), nmax, mmax))
-        return out
-
-    def _desc(self, path, idx_dev, count, nmax, mmax):
-        d = N.CsBatch()
-        C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
-        d.order = idx_dev.data_ptr()
-        d.count = count
-        d.path = path
-        d.nv_max, d.nrows_max = nmax, mmax
-        return d
+        return self.S - len(self.free)
 
     # ------------------------------------------------------------ a tick
-    def _admit(self, now):
-        adm = []
+    def tick(self, now):
+        """Admit, then one batched backward and one batched forward step for
+        every occupied slot.  Returns (solves issued, slots finished)."""
+        W = self.W
+        adm_s, adm_p = [], []
         while self.queue and self.free and self.queue[0].arrival <= now:
             r = self.queue.popleft()
             s = self.free.popleft()
@@ -206,85 +246,72 @@ class Engine:
             self.req[s] = r
             self.phase[s] = 0
             self.nv_host[s], self.nr_host[s] = r.n, r.m
-            adm.append((s, r.pool_index))
-        if adm:
-            slots = np.array([a[0] for a in adm])
-            sl = torch.from_numpy(slots).to(self.device)
-            pi = torch.tensor([a[1] for a in adm], device=self.device)
-            P = self.pool
-            self.Mt[sl], self.Jt[sl] = P.Mt[pi], P.Jt[pi]
-            self.Minv[sl], self.Jp[sl] = P.Minv[pi], P.Jp[pi]
-            self.D[sl], self.pen[sl], self.nmask[sl] = P.D[pi], P.pen[pi], P.nmask[pi]
-            self.v[sl], self.goal[sl], self.tau[sl] = P.v0[pi], P.goal[pi], P.tau[pi]
-            self.vbar[sl] = 0.0
-            self.taubar[sl] = 0.0
-            self.nv_dev[sl] = torch.from_numpy(self.nv_host[slots]).to(self.device)
-            self.nr_dev[sl] = torch.from_numpy(self.nr_host[slots]).to(self.device)
-        self.max_active = max(self.max_active, self.active())
-        return len(adm)
-
-    def tick(self, now):
-        """Admit, then one batched backward and one batched forward step."""
-        self._admit(now)
-        W, h = self.W, self.h
-        vp, st = solver._vp, solver._stream(self.device)
-        bwd = np.flatnonzero(self.phase >= W)
-        fwd = np.flatnonzero((self.phase >= 0) & (self.phase < W))
-        if len(bwd):     # backward step t = 2W - 1 - phase
-            tb = torch.from_numpy(2 * W - 1 - self.phase[bwd]).to(self.device)
-            sb = torch.from_numpy(bwd).to(self.device)
-            self.sol.a[sb] = self.arch_a[tb, sb]
-            self.a0[sb] = self.arch_a0[tb, sb]
-            self.aref[sb] = self.arch_aref[tb, sb]
-            self.fac_view[sb] = self.arch_fac[tb, sb]
-            self.mask_view[sb] = self.arch_mask[tb, sb]
-            self.abar[sb] = h * self.vbar[sb]
-            for path, od, cnt, nmax, mmax in self._launch_groups(bwd):
-                d = self._desc(path, od, cnt, nmax, mmax)
-                rc = N.ift_vjp(d, vp(self.sol.state), self.sol.state.numel(), vp(self.Mt),
-                               vp(self.Jt), vp(self.a0), vp(self.aref), vp(self.D), vp(self.sol.a),
-                               vp(self.abar), vp(self.g_a0), vp(self.g_aref), None, None, None, st)
+            self.cls[s] = self.class_of(r.n, r.m)
+            adm_s.append(s)
+            adm_p.append(r.pool_index)
+        occ = np.flatnonzero(self.phase >= 0)
+        self.max_active = max(self.max_active, len(occ))
+        if len(occ) == 0:
+            return 0, np.zeros(0, dtype=np.int64)
+        ph = self.phase[occ]
+        bwd_mask = ph >= W
+        # list layout: [admit pairs | entries | orders of each launch]
+        parts = [np.stack([np.asarray(adm_s, np.int64), np.asarray(adm_p, np.int64)], 1).ravel(),
+                 np.stack([occ, ph], 1).ravel()]
+        launches = []
+        pos = 2 * len(adm_s) + 2 * len(occ)
+        for kind, sel in (("vjp", occ[bwd_mask]), ("fwd", occ[~bwd_mask])):
+            if len(sel) == 0:
+                continue
+            cs = self.cls[sel]
+            for c in np.unique(cs):
+                idx = sel[cs == c]
+                parts.append(idx)
+                launches.append((kind, int(c), pos, len(idx)))
+                pos += len(idx)
+        flat = np.concatenate(parts).astype(np.int32)
+        buf = self.list_pin[self.ring]
+        if self.list_evt[self.ring] is not None:
+            self.list_evt[self.ring].synchronize()      # its previous copy has been consumed
+        buf[:len(flat)].numpy()[:] = flat
+        stream = torch.cuda.current_stream(self.device)
+        self.list_dev[:len(flat)].copy_(buf[:len(flat)], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        self.list_evt[self.ring] = ev
+        self.ring ^= 1
+        st = C.c_void_p(stream.cuda_stream)
+        base = self.list_dev.data_ptr()
+        at = lambda k: C.c_void_p(base + 4 * k)
+        tb = self.table
+        if adm_s:
+            N.check(N.serve_admit(tb, self.pool.table, at(0), len(adm_s), st), "cs_serve_admit")
+        N.check(N.serve_pre(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_pre")
+        vp = solver._vp
+        sol = self.sol
+        for kind, c, off, cnt in launches:
+            path, nmax, mmax = self.classes[c]
+            d = N.CsBatch()
+            C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
+            d.order, d.count, d.path = base + 4 * off, cnt, path
+            d.nv_max, d.nrows_max = nmax, mmax
+            if kind == "vjp":
+                rc = N.ift_vjp(d, vp(sol.state), sol.state.numel(), vp(self.M), vp(self.J),
+                               vp(self.a0), vp(self.aref), vp(self.D), vp(sol.a), vp(self.abar),
+                               vp(self.a0bar), vp(self.arefbar), None, None, None, st)
                 N.check(rc, "cs_ift_vjp(serve)")
-            nm = self.nmask[sb]
-            a0b = self.g_a0[sb] * nm
-            arefb = self.g_aref[sb] * (self.D[sb] != 0).to(self.dtype)
-            # tau-bar_t = M^-T a0-bar ; v-bar_t = v-bar_{t+1} - b J^T aref-bar
-            self.taubar[sb, tb] = torch.bmm(self.Minv[sb].transpose(1, 2).contiguous(),
-                                            a0b.unsqueeze(-1)).squeeze(-1) * nm
-            self.vbar[sb] = self.vbar[sb] - synth.B_DAMP * torch.bmm(
-                self.Jp[sb].transpose(1, 2).contiguous(), arefb.unsqueeze(-1)).squeeze(-1)
-        if len(fwd):     # forward step t = phase
-            tf = torch.from_numpy(self.phase[fwd]).to(self.device)
-            sf = torch.from_numpy(fwd).to(self.device)
-            self.a0[sf] = torch.bmm(self.Minv[sf], self.tau[sf, tf].unsqueeze(-1)).squeeze(-1) * self.nmask[sf]
-            self.aref[sf] = (-synth.B_DAMP * torch.bmm(self.Jp[sf], self.v[sf].unsqueeze(-1)).squeeze(-1)
-                             - synth.K_SPRING * self.pen[sf])
-            p = N.CsSolverParams(int(self.max_iter), 0, float(self.tol))
-            for path, od, cnt, nmax, mmax in self._launch_groups(fwd):
-                d = self._desc(path, od, cnt, nmax, mmax)
-                rc = N.forward(d, p, vp(self.Mt), vp(self.Jt), vp(self.a0), vp(self.aref),
-                               vp(self.D), None, vp(self.sol.a), vp(self.sol.state),
-                               self.sol.state.numel(), vp(self.sol.status), vp(self.sol.iters), st)
+            else:
+                rc = N.forward(d, self.params, vp(self.M), vp(self.J), vp(self.a0), vp(self.aref),
+                               vp(self.D), None, vp(sol.a), vp(sol.state), sol.state.numel(),
+                               vp(sol.status), vp(sol.iters), st)
                 N.check(rc, "cs_forward(serve)")
-            a = self.sol.a[sf] * self.nmask[sf]
-            self.arch_a[tf, sf] = a
-            self.arch_a0[tf, sf] = self.a0[sf]
-            self.arch_aref[tf, sf] = self.aref[sf]
-            self.arch_fac[tf, sf] = self.fac_view[sf]
-            self.arch_mask[tf, sf] = self.mask_view[sf]
-            self.v[sf] = self.v[sf] + h * a
-        done = np.zeros(0, dtype=np.int64)
-        if len(fwd):
-            self.phase[fwd] += 1
-            last = fwd[self.phase[fwd] == W]
-            if len(last):
-                sl = torch.from_numpy(last).to(self.device)
-                self.vbar[sl] = 2.0 * (self.v[sl] - self.goal[sl])
-        if len(bwd):
-            self.phase[bwd] += 1
-            done = bwd[self.phase[bwd] == 2 * W]
+        N.check(N.serve_post(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_post")
+        self.phase[occ] += 1
+        done = occ[self.phase[occ] == 2 * W]
+        self.ticks += 1
         for s in done:
             r = self.req[s]
+            r.done_tick = self.ticks
             if self.keep_results:
                 n = r.n
                 self.results[r.rid] = torch.cat([self.v[s, :n], self.taubar[s, :, :n].reshape(-1)]).clone()
@@ -292,15 +319,18 @@ class Engine:
             self.phase[s] = -1
             self.free.append(s)
             self.finished.append(r)
-        return len(fwd) + len(bwd), done
+        return len(occ), done
 
 
 def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     """Serve a Poisson stream of ``rate`` requests/s on the wall clock.
 
-    The host synchronises after every tick, so a request completes when the
-    GPU work of its last tick has finished.  Returns latency percentiles (after
-    the warm-up requests), throughput in requests and solves per second."""
+    The host issues ticks without waiting for the GPU (at most two ticks
+    ahead, bounded by the list ring); every tick records an event, and a
+    request completes when the event of its last tick completes on the GPU.
+    Latency is measured from arrival to that completion on one clock.
+    Returns percentiles over the requests after the warm-up ones, and
+    throughput in requests and solves per second."""
     rng = np.random.default_rng(seed)
     total = n_requests + warmup
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=total))
@@ -310,29 +340,35 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
                     arrival=float(arrivals[i])) for i in range(total)]
     pending = deque(reqs)
     engine.finished.clear()
+    stream = torch.cuda.current_stream(engine.device)
     torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
     t0 = time.perf_counter()
-    solves = ticks = 0
+    tick_events = [start]
+    solves = 0
+    t_first = engine.ticks
     while len(engine.finished) < total:
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             engine.submit(pending.popleft())
         if engine.active() == 0 and not engine.queue:
-            if pending:
-                time.sleep(max(0.0, min(pending[0].arrival - now, 0.001)))
-            continue
-        n_work, done = engine.tick(now)
-        torch.cuda.synchronize()
-        tnow = time.perf_counter() - t0
-        for r in engine.finished[len(engine.finished) - len(done):]:
-            r.done = tnow
-        solves += n_work
-        ticks += 1
-    elapsed = time.perf_counter() - t0
+            continue                                    # idle: wait for the next arrival
+        before = engine.ticks
+        n_work, _ = engine.tick(now)
+        if engine.ticks != before:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            tick_events.append(ev)
+            solves += n_work
+    torch.cuda.synchronize()
+    t_end = [start.elapsed_time(e) / 1e3 for e in tick_events]     # seconds since start
+    for r in engine.finished:
+        r.done = t_end[r.done_tick - t_first]
     fin = sorted(engine.finished, key=lambda r: r.rid)[warmup:]
     lat = np.array([r.done - r.arrival for r in fin])
     span = max(r.done for r in fin) - min(r.arrival for r in fin)
     return dict(rate=rate, requests=len(fin), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), requests_per_s=len(fin) / span,
-                solves_per_s=solves / elapsed, ticks=ticks, slots=engine.S,
+                solves_per_s=solves / t_end[-1], ticks=len(tick_events) - 1, slots=engine.S,
                 max_active=engine.max_active)

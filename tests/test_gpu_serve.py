@@ -117,12 +117,15 @@ def test_admission_within_budget():
         serve.Engine(budget_bytes=per - 1, window=W)
 
 
-def test_poisson_stream_reports_latency():
+@pytest.mark.parametrize("rate", [2000.0, 20000.0])
+def test_poisson_stream_reports_latency(rate):
     _needs_gpu()
     pool = _pool(64, torch.float32, seed=17)
-    eng = serve.Engine(slots=256, window=W, max_iter=10, tol=1e-5)
+    eng = serve.Engine(slots=1024, window=W, max_iter=10, tol=1e-5)
     eng.attach_pool(pool)
-    res = serve.run_stream(eng, rate=2000.0, n_requests=300, warmup=50, seed=1)
+    res = serve.run_stream(eng, rate=rate, n_requests=1000, warmup=100, seed=1)
     print(res)
-    assert res["requests"] == 300
+    assert res["requests"] == 1000
     assert 0 < res["p50_ms"] <= res["p99_ms"] < 1e4
+    # every request took its 2W ticks: latency is at least that many tick times
+    assert res["max_active"] <= 1024

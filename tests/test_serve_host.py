@@ -1,9 +1,11 @@
 """Host-side rules of the serving engine (no GPU): slot sizing from an HBM
-budget and request validation."""
+budget, the slot table handed to the library, kernel classes and request
+validation."""
 import numpy as np
 import pytest
 import torch
 
+from paper_2607_24959_amd import _native as N
 from paper_2607_24959_amd import serve
 
 
@@ -18,14 +20,28 @@ def test_slots_follow_budget():
         serve.Engine(device="cpu")
 
 
-def test_slot_layout_views():
-    e = serve.Engine(slots=4, n_cap=9, m_cap=64, device="cpu")
+def test_slot_table_layout():
+    e = serve.Engine(slots=4, n_cap=9, m_cap=64, window=3, device="cpu")
+    t = e.table
+    assert (t.slots, t.window, t.n_cap, t.m_cap) == (4, 3, 9, 64)
+    assert t.state == e.sol.state.data_ptr() and t.a == e.sol.a.data_ptr()
+    # factors of the slot batch end before the active-set bytes, which fit the state
     ne = 9 * 10 // 2
-    assert e.fac_view.shape == (4, ne)
-    assert e.mask_view.shape == (4, 64)
-    # the factor and mask views lie inside the state buffer, disjoint
-    assert e.fac_view.numel() * 4 <= e.batch.mask_offset()
-    assert e.batch.mask_offset() + 4 * 64 <= e.sol.state.numel()
+    assert 4 * 4 * ne <= t.mask_offset
+    assert t.mask_offset + 4 * 64 <= e.sol.state.numel()
+    assert e.arch_fac.shape == (3, 4, ne) and e.arch_mask.shape == (3, 4, 64)
+
+
+def test_kernel_classes():
+    e32 = serve.Engine(slots=2, device="cpu")
+    c = e32.classes
+    assert e32.class_of(3, 0) != e32.class_of(9, 64)
+    assert c[e32.class_of(9, 64)][0] == N.PATH_SMALL
+    assert c[e32.class_of(9, 68)][0] == N.PATH_CHUNK
+    assert c[e32.class_of(18, 8)][0] == N.PATH_CHUNK
+    e64 = serve.Engine(slots=2, dtype=torch.float64, device="cpu")
+    assert e64.classes[e64.class_of(9, 8)][0] == N.PATH_CHUNK
+    assert e64.classes[e64.class_of(6, 8)][0] == N.PATH_SMALL
 
 
 def test_pool_and_request_checks():
@@ -36,10 +52,30 @@ def test_pool_and_request_checks():
         n, m = int(pool.n[i]), int(pool.m[i])
         Mt = pool.Mt[i, :n * n].reshape(n, n)
         assert torch.equal(Mt, pool.Mp[i, :n, :n])
+        assert torch.allclose(pool.Minv[i, :n * n].reshape(n, n) @ Mt, torch.eye(n, dtype=torch.float64))
         assert torch.equal(pool.Jt[i, :m * n].reshape(m, n), pool.Jp[i, :m, :n])
         assert torch.count_nonzero(pool.Mt[i, n * n:]) == 0
-    e = serve.Engine(slots=2, n_cap=9, m_cap=32, window=4, device="cpu")
+    e = serve.Engine(slots=2, n_cap=9, m_cap=32, window=4, dtype=torch.float64, device="cpu")
     with pytest.raises(ValueError):
         e.attach_pool(pool)
     with pytest.raises(ValueError):
         e.submit(serve.Request(rid=0, pool_index=0, n=9, m=64))
+    with pytest.raises(ValueError):
+        serve.RequestPool(4, (12,), 4, 4, 3, 9, 64, torch.float64, "cpu")
+
+
+def test_serve_entry_points_reject_bad_tables():
+    e = serve.Engine(slots=2, n_cap=9, m_cap=64, window=3, device="cpu")
+    bad = N.CsServeTable()
+    assert N.serve_pre(bad, None, 0, None) == N.CS_EINVAL
+    assert N.serve_post(bad, None, 0, None) == N.CS_EINVAL
+    assert N.serve_pre(e.table, None, 1, None) == N.CS_EINVAL       # entries required
+    assert N.serve_pre(e.table, None, -1, None) == N.CS_EINVAL
+    assert N.serve_pre(e.table, None, 0, None) == N.CS_OK            # nothing to do
+    pool = serve.RequestPool(2, (9,), 16, 3, 1, 9, 64, torch.float32, "cpu")
+    assert N.serve_admit(e.table, pool.table, None, 0, None) == N.CS_OK
+    pool64 = serve.RequestPool(2, (9,), 16, 3, 1, 9, 64, torch.float64, "cpu")
+    assert N.serve_admit(e.table, pool64.table, None, 0, None) == N.CS_EINVAL   # dtype differs
+    t = N.CsServeTable.from_buffer_copy(e.table)
+    t.n_cap = 65
+    assert N.serve_pre(t, None, 0, None) == N.CS_EINVAL
