@@ -55,6 +55,32 @@ def forward_flops(n, m, active, iters):
     return iters * step + final
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_uniform_B4096_n9_m64.txt")
+
+
+def measured_traffic(key="forward"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals, srcs = {}, []
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            vals[k] = v
+        elif line.startswith("paper_2607_24959_amd/csrc/"):
+            srcs.append(line)
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if not srcs or vals.get("sources_sha256") != h.hexdigest():
+        return None
+    v = vals.get(f"traffic_bytes.{key}")
+    return int(v) if v is not None else None
+
+
 def make_batches(count, seed0):
     from paper_2607_24959_amd import synth
     return [synth.uniform_batch(B, NV, NC, seed0 + i).astype(np.float32) for i in range(count)]
@@ -299,7 +325,9 @@ def main():
         },
         "roofline": {"kernel": "k_forward_small<float,9,4>", "bound": "alu",
                      "achieved": fwd_flops_rate / 1e12, "peak": FP32_VEC_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": fwd_flops_rate / FP32_VEC_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": fwd_flops_rate / FP32_VEC_PEAK,
+                     "traffic": measured_traffic("forward"),
+                     "algorithmic_bytes_per_launch": B * fwd_b,
                      "flops_per_launch": flops_per_launch},
         "solver": {"converged_frac": float(np.mean(st & 1)), "mean_iters": float(it.mean()),
                    "mean_active_rows": float(act.mean())},

@@ -252,7 +252,8 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 // pass A: r, A, F = M (a - a0) + J^T w and H = M + J^T diag(D o A) J
                 for (int j = tid; j < n; j += NT) {
                     T f = T(0);
-                    for (int l = 0; l < n; ++l) f += M[(int64_t)j * n + l] * (L.a[l] - L.a0[l]);
+#pragma unroll 4
+                    for (int l = 0; l < n; ++l) f += M[(int64_t)l * n + j] * (L.a[l] - L.a0[l]);
                     L.F[j] = f;
                 }
                 acc.zero();
@@ -317,10 +318,11 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 }
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0), md = T(0);
+#pragma unroll 4
                     for (int l = 0; l < n; ++l) {
-                        const T mjl = M[(int64_t)j * n + l];
-                        mp += mjl * L.p[l];
-                        md += mjl * (L.a[l] - L.a0[l]);
+                        const T mlj = M[(int64_t)l * n + j];   // = M[j][l]: M is symmetric
+                        mp += mlj * L.p[l];
+                        md += mlj * (L.a[l] - L.a0[l]);
                     }
                     L.v[j] = mp;
                     L.u[j] = md;
@@ -421,7 +423,8 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
         __syncthreads();
         for (int j = tid; j < n; j += NT) {
             T s = gabar[I.on + j] - L.F[j];
-            for (int l = 0; l < n; ++l) s -= M[(int64_t)j * n + l] * L.u[l];
+#pragma unroll 4
+            for (int l = 0; l < n; ++l) s -= M[(int64_t)l * n + j] * L.u[l];
             L.y[j] = s;
         }
         __syncthreads();

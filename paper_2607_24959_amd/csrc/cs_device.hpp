@@ -144,27 +144,142 @@ __device__ inline void team_sum(T (&v)[NV], T *sred) {
     }
 }
 
-// In-place Cholesky H = L L^T of the n x n row-major matrix in LDS (lower
-// triangle read and overwritten strictly below the diagonal; the diagonal of
-// L goes to diag[]).  Left-looking by columns, one barrier per column.
+// Value of v in lane k of the wave (k wave-uniform), for every lane.
+__device__ inline float lane_bcast(float v, int k) {
+    k = __builtin_amdgcn_readfirstlane(k);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+}
+__device__ inline double lane_bcast(double v, int k) {
+    k = __builtin_amdgcn_readfirstlane(k);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Trailing update of the blocked Cholesky: for c1 <= j <= i < n,
+//   H[i][j] -= sum_{k < 16} H[i][c0 + k] H[j][c0 + k]
+// over 16 x 16 tiles of the lower triangle (tile origin c1).  FP32 runs each
+// tile on the matrix cores (v_mfma_f32_16x16x4f32, four K-slices of 4; lane l
+// feeds row l % 16, slice column l / 16, and receives rows 4 (l / 16) + r);
+// FP64 gives each thread whole entries on the VALU.
+template <int NT>
+__device__ inline void chol_trailing(float *H, int n, int ld, int c0, int c1) {
+    const int nt = (n - c1 + 15) / 16;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wave; t < ntiles; t += NT / 64) {
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const int ra = c1 + 16 * ti + li, rb = c1 + 16 * tj + li;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kc = c0 + 4 * ks + lk;
+            const float a = ra < n ? H[ra * ld + kc] : 0.f;
+            const float b = rb < n ? H[rb * ld + kc] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = c1 + 16 * ti + 4 * lk + r, col = c1 + 16 * tj + li;
+            if (row < n && col <= row) H[row * ld + col] -= acc[r];
+        }
+    }
+}
+
+template <int NT>
+__device__ inline void chol_trailing(double *H, int n, int ld, int c0, int c1) {
+    const int nt = (n - c1 + 15) / 16;
+    const int cnt = nt * (nt + 1) / 2 * 256;
+    for (int e = threadIdx.x; e < cnt; e += NT) {
+        const int t = e >> 8, w = e & 255;
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const int row = c1 + 16 * ti + (w >> 4), col = c1 + 16 * tj + (w & 15);
+        if (row < n && col <= row) {
+            const double *hr = H + row * ld + c0, *hc = H + col * ld + c0;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += hr[k] * hc[k];
+            H[row * ld + col] -= s;
+        }
+    }
+}
+
+// In-place Cholesky H = L L^T of the n x n row-major matrix in LDS (row
+// stride ld): the lower triangle is read, L is written strictly below the
+// diagonal and L_jj goes to diag[j].  Right-looking over 16-column blocks:
+// each wave factors the diagonal block in registers (one row per lane, lane
+// broadcasts; wave 0 stores it), every thread then solves one panel row against it, and the
+// trailing lower triangle takes the block's rank-16 update; three barriers
+// per block.  The caller has synchronised the team after writing H.
 // Returns false (team-uniform) when a pivot is not positive.
-// The matrix has row stride ld (ld = n for a dense n x n block).
 template <int NT, typename T>
 __device__ inline bool team_cholesky(T *H, T *diag, int n, int ld) {
     bool ok = true;
-    for (int j = 0; j < n; ++j) {
-        T s = H[j * ld + j];
-        for (int k = 0; k < j; ++k) s -= H[j * ld + k] * H[j * ld + k];
-        ok = ok && (s > T(0));
-        const T ljj = sqrt(s);
-        const T inv = T(1) / ljj;
-        for (int i = j + 1 + (int)threadIdx.x; i < n; i += NT) {
-            T t = H[i * ld + j];
-            for (int k = 0; k < j; ++k) t -= H[i * ld + k] * H[j * ld + k];
-            H[i * ld + j] = t * inv;
+    for (int c0 = 0; c0 < n; c0 += 16) {
+        const int bs = min(16, n - c0);
+        {   // every wave factors the block (same values); wave 0 stores it
+            const int l = threadIdx.x & 63;
+            const bool w0 = threadIdx.x < 64;
+            T d[16];
+            // clamped (always in-bounds) loads, then select: rows past the
+            // block and the upper triangle are zero
+            const T *hr = H + (c0 + min(l, bs - 1)) * ld + c0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const T x = hr[min(k, bs - 1)];
+                d[k] = (l < bs && k <= l) ? x : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < bs) {
+                    const T ljj = sqrt(lane_bcast(d[j], j));
+                    if (l == j) d[j] = ljj;
+                    else if (l > j) d[j] = d[j] / ljj;
+#pragma unroll
+                    for (int k = j + 1; k < 16; ++k) {
+                        if (k < bs) {
+                            const T lkj = lane_bcast(d[j], k);
+                            if (l >= k) d[k] -= d[j] * lkj;
+                        }
+                    }
+                }
+            }
+            if (w0 && l < bs) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (k < l) H[(c0 + l) * ld + c0 + k] = d[k];
+                diag[c0 + l] = d[l];
+            }
         }
-        if ((int)threadIdx.x == (j % NT)) diag[j] = ljj;
         __syncthreads();
+        for (int j = 0; j < bs; ++j) ok = ok && (diag[c0 + j] > T(0));
+        const int c1 = c0 + bs;
+        if (c1 < n) {
+            // panel rows: x L_D^T = h  (forward substitution against the block)
+            for (int i = c1 + (int)threadIdx.x; i < n; i += NT) {
+                T x[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    T v = H[i * ld + c0 + c];
+#pragma unroll
+                    for (int k = 0; k < c; ++k) v -= x[k] * H[(c0 + c) * ld + c0 + k];
+                    x[c] = v / diag[c0 + c];
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c) H[i * ld + c0 + c] = x[c];
+            }
+            __syncthreads();
+            chol_trailing<NT>(H, n, ld, c0, c1);
+            __syncthreads();
+        }
     }
     return ok;
 }
@@ -172,23 +287,60 @@ template <int NT, typename T>
 __device__ inline bool team_cholesky(T *H, T *diag, int n) { return team_cholesky<NT>(H, diag, n, n); }
 
 // Solve L L^T x = b with the factor from team_cholesky.  b is overwritten;
-// the solution is returned in x.  One barrier per column and direction.
+// the solution is returned in x.  Blocked like the factorisation: wave 0
+// solves each 16 x 16 diagonal block with lane broadcasts, then every thread
+// updates one remaining entry with the block's 16 values; two barriers per
+// block and direction.  The caller has synchronised the team after writing b.
 template <int NT, typename T>
 __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
     // forward: L y = b, y stored in x
-    for (int j = 0; j < n; ++j) {
-        const T yj = b[j] / diag[j];
-        if ((int)threadIdx.x == (j % NT)) x[j] = yj;
-        for (int i = j + 1 + (int)threadIdx.x; i < n; i += NT) b[i] -= L[i * ld + j] * yj;
+    for (int c0 = 0; c0 < n; c0 += 16) {
+        const int bs = min(16, n - c0);
+        if (threadIdx.x < 64) {
+            const int l = threadIdx.x;
+            T y = l < bs ? b[c0 + l] : T(0);
+            for (int c = 0; c < bs; ++c) {
+                if (l == c) y = y / diag[c0 + c];
+                const T yc = lane_bcast(y, c);
+                if (l > c && l < bs) y -= L[(c0 + l) * ld + c0 + c] * yc;
+            }
+            if (l < bs) x[c0 + l] = y;
+        }
         __syncthreads();
+        const int c1 = c0 + bs;
+        if (c1 < n) {
+            for (int i = c1 + (int)threadIdx.x; i < n; i += NT) {
+                T v = b[i];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) v -= L[i * ld + c0 + k] * x[c0 + k];
+                b[i] = v;
+            }
+            __syncthreads();
+        }
     }
     // backward: L^T x = y (in place in x)
-    for (int j = n - 1; j >= 0; --j) {
-        const T xj = x[j] / diag[j];
+    const int nb = (n + 15) / 16;
+    for (int kb = nb - 1; kb >= 0; --kb) {
+        const int c0 = 16 * kb, bs = min(16, n - c0);
+        if (threadIdx.x < 64) {
+            const int l = threadIdx.x;
+            T v = l < bs ? x[c0 + l] : T(0);
+            for (int c = bs - 1; c >= 0; --c) {
+                if (l == c) v = v / diag[c0 + c];
+                const T xc = lane_bcast(v, c);
+                if (l < c) v -= L[(c0 + c) * ld + c0 + l] * xc;
+            }
+            if (l < bs) x[c0 + l] = v;
+        }
         __syncthreads();
-        if ((int)threadIdx.x == (j % NT)) x[j] = xj;
-        for (int i = (int)threadIdx.x; i < j; i += NT) x[i] -= L[j * ld + i] * xj;
-        __syncthreads();
+        if (c0 > 0) {
+            for (int i = threadIdx.x; i < c0; i += NT) {
+                T v = x[i];
+                for (int k = 0; k < bs; ++k) v -= L[(c0 + k) * ld + i] * x[c0 + k];
+                x[i] = v;
+            }
+            __syncthreads();
+        }
     }
 }
 template <int NT, typename T>
