@@ -1,15 +1,20 @@
 // cs_chunk.hpp -- team kernels that stream the rows of J through LDS.
 //
 // One workgroup (NT = 64 for n <= 32, 256 otherwise) solves one instance at
-// a time.  Each Newton pass reads J in chunks of CR rows: a chunk is copied
-// to LDS with coalesced loads, then the residual of its rows (NT / CR lanes
-// per row), the gradient J^T w (lanes over columns) and the Newton-matrix
-// contribution J_c^T diag(D o A) J_c are formed from LDS.  In FP32 the
-// contraction runs on the matrix cores (v_mfma_f32_16x16x4f32 on 16 x 16
-// tiles of the lower triangle, tiles spread over the waves, accumulators in
-// registers); in FP64 lanes accumulate lower-triangle entries on the VALU.
-// A second pass forms q = J p for the line search.  H (row stride npa, the
-// padded n), the row arrays r, q, D, aref and the chunk buffer live in LDS.
+// a time.  Each Newton pass reads J in chunks of CR rows: every thread holds
+// its share of the next chunk in registers (loads issued before the current
+// chunk is processed, so global latency overlaps the work), then the chunk
+// is written to LDS (row stride npa + 1, conflict-free) and its rows give the
+// residuals (NT / CR lanes per row), the gradient J^T w (per-thread partial
+// sums over fixed rows, kept in registers across chunks) and the
+// Newton-matrix contribution J_c^T diag(D o A) J_c.  In FP32 the contraction
+// runs on the matrix cores (v_mfma_f32_16x16x4f32 on 16 x 16 tiles of the
+// lower triangle, tiles spread over the waves and interleaved per K-step,
+// accumulators in registers); in FP64 lanes accumulate lower-triangle
+// entries on the VALU.  A second pass forms q = J p for the line search.
+// H (row stride npa + 1), the row arrays r, q, D, aref and the chunk buffer
+// live in LDS; M stays in global memory (read column-wise, coalesced, as a
+// symmetric matrix).
 #pragma once
 
 #include "cs_device.hpp"
@@ -27,10 +32,12 @@ struct ChLds {
     uint8_t *A;
 };
 
+// H (npa x (npa + 1)), eight n-vectors and the diagonal, reduction scratch,
+// four row arrays, the chunk (CR x (npa + 1)), two chunk-row arrays, A.
 __host__ __device__ inline size_t ch_lds_bytes(int npa, int mmax, int NT, size_t s) {
-    const size_t ldj = (size_t)npa + 1;
-    const size_t nT = (size_t)npa * npa + 9 * (size_t)npa + 16 * (size_t)(NT / 64) +
-                      4 * (size_t)mmax + CR * ldj + 2 * CR;
+    const size_t ld = (size_t)npa + 1;
+    const size_t nT = (size_t)npa * ld + 9 * (size_t)npa + 16 * (size_t)(NT / 64) +
+                      4 * (size_t)mmax + CR * ld + 2 * CR;
     return nT * s + (size_t)mmax + 64;
 }
 
@@ -38,7 +45,7 @@ template <typename T>
 __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int NT) {
     ChLds<T> L;
     T *p = reinterpret_cast<T *>(smem);
-    L.H = p; p += (size_t)npa * npa;
+    L.H = p; p += (size_t)npa * (npa + 1);
     L.diag = p; p += npa;
     L.a = p; p += npa;
     L.a0 = p; p += npa;
@@ -59,34 +66,125 @@ __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int 
     return L;
 }
 
-// Copy rows [c CR, c CR + CR) of J (row-major, n columns) into the chunk
-// buffer (row stride ldj).  Rows past m are left as they are.
+// A thread's share of one chunk (CR rows of a row-major J with n <= 128
+// columns; n <= 32 when NT = 64): elements tid + NT s of the chunk, held in
+// registers between the global load and the LDS store.  Elements past the
+// last row of J read as zero.
 template <int NT, typename T>
-__device__ inline void ch_load(const T *__restrict__ J, int n, int m, int c, int ldj, T *Jc) {
-    const int r0 = c * CR;
-    const int rows = min(CR, m - r0);
-    const int cnt = rows * n;
-    const T *src = J + (int64_t)r0 * n;
-    for (int e = threadIdx.x; e < cnt; e += NT) {
-        const int rho = e / n, j = e - rho * n;
-        Jc[rho * ldj + j] = src[e];
-    }
-}
+struct ChStage {
+    static constexpr int MAXE = CR * (NT == 64 ? 32 : 128) / NT;
+    T v[MAXE];
+    int rho0, j0, drho, dj;
 
-// Dot products of the chunk's rows with the LDS vector x; NT / CR lanes per
-// row, combined with butterflies.  Returns the full dot in every lane of the
-// row's lane group; rho is this lane's chunk row.
+    __device__ inline void plan(int n) {
+        rho0 = (int)threadIdx.x / n;
+        j0 = (int)threadIdx.x - rho0 * n;
+        drho = NT / n;
+        dj = NT - drho * n;
+    }
+    __device__ inline void load(const T *__restrict__ J, int n, int m, int c) {
+        const int r0 = c * CR;
+        const int cnt = min(CR, m - r0) * n;
+        const T *src = J + (int64_t)r0 * n;
+#pragma unroll
+        for (int s = 0; s < MAXE; ++s) {
+            const int e = (int)threadIdx.x + s * NT;
+            v[s] = e < cnt ? src[e] : T(0);
+        }
+    }
+    __device__ inline void store(int n, int ldj, T *Jc) const {
+        int rho = rho0, j = j0;
+#pragma unroll
+        for (int s = 0; s < MAXE; ++s) {
+            if (rho < CR) Jc[rho * ldj + j] = v[s];
+            rho += drho;
+            j += dj;
+            if (j >= n) { j -= n; ++rho; }
+        }
+    }
+};
+
+// Dot products of the chunk's rows with one or two LDS vectors; NT / CR
+// lanes per row, two partial sums per lane, combined with butterflies.
+// Every lane of the row's group gets the full dots; rho is the lane's row.
 template <int NT, typename T>
 __device__ inline T ch_row_dot(int n, int ldj, const T *Jc, const T *x, int &rho, int &part) {
     constexpr int TPR = NT / CR;
     rho = threadIdx.x / TPR;
     part = threadIdx.x % TPR;
-    T s = T(0);
-    for (int j = part; j < n; j += TPR) s += Jc[rho * ldj + j] * x[j];
+    const T *row = Jc + rho * ldj;
+    T s0 = T(0), s1 = T(0);
+    int j = part;
+    for (; j + TPR < n; j += 2 * TPR) {
+        s0 += row[j] * x[j];
+        s1 += row[j + TPR] * x[j + TPR];
+    }
+    if (j < n) s0 += row[j] * x[j];
+    T s = s0 + s1;
 #pragma unroll
     for (int o = 1; o < TPR; o <<= 1) s += __shfl_xor(s, o, 64);
     return s;
 }
+
+template <int NT, typename T>
+__device__ inline void ch_row_dot2(int n, int ldj, const T *Jc, const T *x, const T *y, T &sx,
+                                   T &sy, int &rho, int &part) {
+    constexpr int TPR = NT / CR;
+    rho = threadIdx.x / TPR;
+    part = threadIdx.x % TPR;
+    const T *row = Jc + rho * ldj;
+    T a = T(0), b = T(0);
+    for (int j = part; j < n; j += TPR) {
+        const T jr = row[j];
+        a += jr * x[j];
+        b += jr * y[j];
+    }
+#pragma unroll
+    for (int o = 1; o < TPR; o <<= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    sx = a;
+    sy = b;
+}
+
+// Per-thread partial of J^T x over the chunks: column fj, rows fp, fp + fparts, ...
+template <int NT, typename T>
+struct ChColSum {
+    int fj, fp, fparts;
+    T acc;
+    __device__ inline void plan(int n) {
+        fparts = min(4, NT / n);
+        fp = (int)threadIdx.x / n;
+        fj = (int)threadIdx.x - fp * n;
+        acc = T(0);
+    }
+    __device__ inline void add_chunk(int ldj, const T *Jc, const T *x) {
+        if (fp < fparts) {
+            T s0 = T(0), s1 = T(0);
+            int rr = fp;
+            for (; rr + fparts < CR; rr += 2 * fparts) {
+                s0 += x[rr] * Jc[rr * ldj + fj];
+                s1 += x[rr + fparts] * Jc[(rr + fparts) * ldj + fj];
+            }
+            if (rr < CR) s0 += x[rr] * Jc[rr * ldj + fj];
+            acc += s0 + s1;
+        }
+    }
+    // out[j] = base[j] + sum of the partials; uses scratch (fparts x ldj),
+    // synchronises the team before and after.
+    __device__ inline void finish(int n, int ldj, T *scratch, const T *base, T *out) const {
+        __syncthreads();
+        if (fp < fparts) scratch[fp * ldj + fj] = acc;
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += NT) {
+            T s = base ? base[j] : T(0);
+            for (int q = 0; q < fparts; ++q) s += scratch[q * ldj + j];
+            out[j] = s;
+        }
+        __syncthreads();
+    }
+};
 
 typedef float chf4 __attribute__((ext_vector_type(4)));
 
@@ -121,27 +219,54 @@ template <int NT> struct ChAcc<float, NT> {
 #pragma unroll
         for (int s = 0; s < MAXT; ++s) acc[s] = chf4{0.f, 0.f, 0.f, 0.f};
     }
-    // acc += J_c^T diag(Wc) J_c over the chunk (rows past m carry Wc = 0)
-    __device__ inline void add_chunk(int ldj, const float *Jc, const float *Wc) {
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // acc += J_c^T diag(Wc) J_c over the chunk (rows past m carry Wc = 0).
+    // The wave's tile count is a compile-time constant in each instance of
+    // the body, so a K-step issues all its LDS loads, then all its MFMAs,
+    // with no branches in between.
+    template <int TPW>
+    __device__ inline void add_chunk_t(int ldj, const float *Jc, const float *Wc) {
+        const int lane = threadIdx.x & 63;
         const int kq = lane >> 4, idx = lane & 15;
+        int ca[TPW], cb[TPW];
 #pragma unroll
-        for (int s = 0; s < MAXT; ++s) {
-            if (wave + NW * s < ntiles) {
-                const float *ca = Jc + 16 * ti[s] + idx;
-                const float *cb = Jc + 16 * tj[s] + idx;
-#pragma unroll 4
-                for (int kb = 0; kb < CR / 4; ++kb) {
-                    const int row = kb * 4 + kq;
-                    const float av = ca[row * ldj];
-                    const float bv = Wc[row] * cb[row * ldj];
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[s], 0, 0, 0);
-                }
+        for (int s = 0; s < TPW; ++s) {
+            ca[s] = 16 * ti[s] + idx;
+            cb[s] = 16 * tj[s] + idx;
+        }
+#pragma unroll 2
+        for (int kb = 0; kb < CR / 4; ++kb) {
+            const int row = kb * 4 + kq;
+            const float wr = Wc[row];
+            const float *jr = Jc + row * ldj;
+            float av[TPW], bv[TPW];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                av[s] = jr[ca[s]];
+                bv[s] = jr[cb[s]];
             }
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], wr * bv[s], acc[s], 0, 0, 0);
         }
     }
-    // H (lower, stride npa) = M + acc
-    __device__ inline void store(int n, int npa, const float *__restrict__ M, float *H) const {
+    __device__ inline void add_chunk(int ldj, const float *Jc, const float *Wc) {
+        const int wave = threadIdx.x >> 6;
+        const int ntl = (ntiles - wave + NW - 1) / NW;   // tiles of this wave (wave-uniform)
+        switch (ntl) {
+            case 1: add_chunk_t<1>(ldj, Jc, Wc); break;
+            case 2: add_chunk_t<2>(ldj, Jc, Wc); break;
+            case 3: add_chunk_t<3>(ldj, Jc, Wc); break;
+            case 4: if constexpr (MAXT >= 4) add_chunk_t<4>(ldj, Jc, Wc); break;
+            case 5: if constexpr (MAXT >= 5) add_chunk_t<5>(ldj, Jc, Wc); break;
+            case 6: if constexpr (MAXT >= 6) add_chunk_t<6>(ldj, Jc, Wc); break;
+            case 7: if constexpr (MAXT >= 7) add_chunk_t<7>(ldj, Jc, Wc); break;
+            case 8: if constexpr (MAXT >= 8) add_chunk_t<8>(ldj, Jc, Wc); break;
+            case 9: if constexpr (MAXT >= 9) add_chunk_t<9>(ldj, Jc, Wc); break;
+            default: break;
+        }
+    }
+    // H (lower, stride ldh) = M + acc
+    __device__ inline void store(int n, int ldh, const float *__restrict__ M, float *H) const {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int kq = lane >> 4, idx = lane & 15;
 #pragma unroll
@@ -150,7 +275,7 @@ template <int NT> struct ChAcc<float, NT> {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * ti[s] + 4 * kq + r, col = 16 * tj[s] + idx;
-                    if (row < n && col <= row) H[row * npa + col] = acc[s][r] + M[row * n + col];
+                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + M[row * n + col];
                 }
             }
         }
@@ -165,14 +290,16 @@ template <int NT> struct ChAcc<double, NT> {
 
     __device__ inline void init(int n) {
         ne = n * (n + 1) / 2;
+        // (j, l) of entry tid, then advanced by NT entries at a time
+        int j = 0, l = threadIdx.x;
+        while (l > j) { l -= j + 1; ++j; }
 #pragma unroll
         for (int s = 0; s < MAXE; ++s) {
-            const int e = threadIdx.x + NT * s;
-            int j = 0;
-            while ((j + 1) * (j + 2) / 2 <= e) ++j;
             ej[s] = j;
-            el[s] = e - j * (j + 1) / 2;
+            el[s] = l;
             acc[s] = 0.0;
+            l += NT;
+            while (l > j) { l -= j + 1; ++j; }
         }
     }
     __device__ inline void zero() {
@@ -183,20 +310,53 @@ template <int NT> struct ChAcc<double, NT> {
 #pragma unroll
         for (int s = 0; s < MAXE; ++s) {
             if ((int)threadIdx.x + NT * s < ne) {
-                double h = acc[s];
-                for (int rho = 0; rho < CR; ++rho)
-                    h += Wc[rho] * Jc[rho * ldj + ej[s]] * Jc[rho * ldj + el[s]];
-                acc[s] = h;
+                double h0 = 0.0, h1 = 0.0;
+                const double *cj = Jc + ej[s], *cl = Jc + el[s];
+                for (int rho = 0; rho < CR; rho += 2) {
+                    h0 += Wc[rho] * cj[rho * ldj] * cl[rho * ldj];
+                    h1 += Wc[rho + 1] * cj[(rho + 1) * ldj] * cl[(rho + 1) * ldj];
+                }
+                acc[s] += h0 + h1;
             }
         }
     }
-    __device__ inline void store(int n, int npa, const double *__restrict__ M, double *H) const {
+    __device__ inline void store(int n, int ldh, const double *__restrict__ M, double *H) const {
 #pragma unroll
         for (int s = 0; s < MAXE; ++s)
             if ((int)threadIdx.x + NT * s < ne)
-                H[ej[s] * npa + el[s]] = acc[s] + M[ej[s] * n + el[s]];
+                H[ej[s] * ldh + el[s]] = acc[s] + M[ej[s] * n + el[s]];
     }
 };
+
+// Walk the packed lower triangle (j, l), l <= j, in steps of NT entries
+// starting at entry tid: no division per element.
+struct TriWalk {
+    int j, l;
+    template <int NT> __device__ inline void start() {
+        j = 0;
+        l = threadIdx.x;
+        while (l > j) { l -= j + 1; ++j; }
+    }
+    template <int NT> __device__ inline void next() {
+        l += NT;
+        while (l > j) { l -= j + 1; ++j; }
+    }
+};
+
+template <int NT, typename T>
+__device__ inline T team_max(T v, T *sred) {
+    v = wave_max(v);
+    if constexpr (NT > 64) {
+        constexpr int NW = NT / 64;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+        __syncthreads();
+        v = sred[0];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) v = fmax(v, sred[i]);
+    }
+    return v;
+}
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_forward_chunk(
@@ -208,14 +368,15 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
     extern __shared__ __align__(16) unsigned char smem[];
     const ChLds<T> L = ch_carve<T>(smem, npa, mmax, NT);
     const int tid = threadIdx.x;
-    const int ldj = npa + 1;
-    // stale chunk rows are multiplied by zero weights: keep them finite
-    for (int e = tid; e < CR * ldj; e += NT) L.Jc[e] = T(0);
+    const int ldj = npa + 1, ldh = npa + 1;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
         const int n = I.n, m = I.m;
         const int nch = (m + CR - 1) / CR;
         const T *M = gM + I.onn, *J = gJ + I.omn;
+        ChStage<NT, T> stg;
+        stg.plan(n);
+        ChColSum<NT, T> cs;
         bool bad = false;
         for (int j = tid; j < n; j += NT) {
             const T x = ga0[I.on + j];
@@ -231,36 +392,47 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
             L.A[i] = 0;
             bad |= !finite_val(d) || !finite_val(ar);
         }
-        for (int e = tid; e < n * n; e += NT) {
-            const T x = M[e];
-            L.H[(e / n) * npa + (e % n)] = x;
-            bad |= !finite_val(x);
+        {   // H = M (row stride ldh) for the definiteness check
+            int rr = tid / n, jj = tid - rr * n;
+            const int dr = NT / n, dc = NT - dr * n;
+            for (int e = tid; e < n * n; e += NT) {
+                const T x = M[e];
+                L.H[rr * ldh + jj] = x;
+                bad |= !finite_val(x);
+                rr += dr;
+                jj += dc;
+                if (jj >= n) { jj -= n; ++rr; }
+            }
         }
         for (int e = tid; e < m * n; e += NT) bad |= !finite_val(J[e]);
         const int anybad = __syncthreads_or(bad);
         int st = 0, k = 0;
         if (anybad) st = ST_NONFINITE;
-        else if (!team_cholesky<NT>(L.H, L.diag, n, npa)) st = ST_NOTSPD;
+        else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) st = ST_NOTSPD;
         ChAcc<T, NT> acc;
         acc.init(sizeof(T) == 4 ? npa : n);
         if (st == 0) {
             T trM = T(0);
             for (int j = 0; j < n; ++j) trM += M[(int64_t)j * n + j];
+            // u = M (a - a0), kept up to date across steps
+            for (int j = tid; j < n; j += NT) {
+                T s = T(0);
+#pragma unroll 4
+                for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * (L.a[l] - L.a0[l]);
+                L.u[j] = s;
+            }
             T step_inf = T(-1);
             int lsfail = 0;
             for (k = 0;; ++k) {
                 // pass A: r, A, F = M (a - a0) + J^T w and H = M + J^T diag(D o A) J
-                for (int j = tid; j < n; j += NT) {
-                    T f = T(0);
-#pragma unroll 4
-                    for (int l = 0; l < n; ++l) f += M[(int64_t)l * n + j] * (L.a[l] - L.a0[l]);
-                    L.F[j] = f;
-                }
                 acc.zero();
+                cs.plan(n);
                 bool changed = false;
+                if (nch > 0) stg.load(J, n, m, 0);
                 for (int c = 0; c < nch; ++c) {
                     __syncthreads();
-                    ch_load<NT>(J, n, m, c, ldj, L.Jc);
+                    stg.store(n, ldj, L.Jc);
+                    if (c + 1 < nch) stg.load(J, n, m, c + 1);
                     __syncthreads();
                     int rho, part;
                     const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.a, rho, part);
@@ -281,22 +453,24 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                         }
                     }
                     __syncthreads();
-                    for (int j = tid; j < n; j += NT) {
-                        T f = L.F[j];
-                        for (int rr = 0; rr < CR; ++rr) f += L.Wr[rr] * L.Jc[rr * ldj + j];
-                        L.F[j] = f;
-                    }
+                    cs.add_chunk(ldj, L.Jc, L.Wr);
                     acc.add_chunk(ldj, L.Jc, L.Wc);
                 }
                 const bool same = !__syncthreads_or(changed);
-                acc.store(n, npa, M, L.H);
-                __syncthreads();
-                T g2 = T(0), anorm = T(0);
-                for (int j = 0; j < n; ++j) {
+                acc.store(n, ldh, M, L.H);
+                cs.finish(n, ldj, L.Jc, L.u, L.F);
+                T g2 = T(0), an = T(0);
+                for (int j = tid; j < n; j += NT) {
                     g2 += L.F[j] * L.F[j];
-                    anorm = fmax(anorm, fabs(L.a[j]));
+                    an = fmax(an, fabs(L.a[j]));
                 }
-                if (!team_cholesky<NT>(L.H, L.diag, n, npa)) { st = ST_NOTSPD; break; }
+                {
+                    T v1[1] = {g2};
+                    team_sum<NT>(v1, L.red);
+                    g2 = v1[0];
+                }
+                const T anorm = team_max<NT>(an, L.red);
+                if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) { st = ST_NOTSPD; break; }
                 if (sqrt(g2) <= tol * trM ||
                     (k > 0 && step_inf >= T(0) && same && step_inf <= tol * (T(1) + anorm))) {
                     st = ST_CONVERGED;
@@ -305,44 +479,50 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 if (k == max_iter) { st = ST_MAXITER; break; }
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
-                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, npa);
-                // pass B: q = J p
+                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
+                // pass B: q = J p, and v = M p
+                if (nch > 0) stg.load(J, n, m, 0);
                 for (int c = 0; c < nch; ++c) {
                     __syncthreads();
-                    ch_load<NT>(J, n, m, c, ldj, L.Jc);
+                    stg.store(n, ldj, L.Jc);
+                    if (c + 1 < nch) stg.load(J, n, m, c + 1);
                     __syncthreads();
                     int rho, part;
                     const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.p, rho, part);
                     const int i = c * CR + rho;
                     if (part == 0 && i < m) L.q[i] = s;
                 }
-                for (int j = tid; j < n; j += NT) {
-                    T mp = T(0), md = T(0);
-#pragma unroll 4
-                    for (int l = 0; l < n; ++l) {
-                        const T mlj = M[(int64_t)l * n + j];   // = M[j][l]: M is symmetric
-                        mp += mlj * L.p[l];
-                        md += mlj * (L.a[l] - L.a0[l]);
-                    }
-                    L.v[j] = mp;
-                    L.u[j] = md;
-                }
-                __syncthreads();
                 T c0 = T(0), b0 = T(0);
-                for (int j = 0; j < n; ++j) {
-                    c0 += L.p[j] * L.v[j];
+                for (int j = tid; j < n; j += NT) {
+                    T mp = T(0);
+#pragma unroll 4
+                    for (int l = 0; l < n; ++l) mp += M[(int64_t)l * n + j] * L.p[l];
+                    L.v[j] = mp;
+                    c0 += L.p[j] * mp;
                     b0 += L.p[j] * L.u[j];
                 }
+                {
+                    T v2[2] = {c0, b0};
+                    team_sum<NT>(v2, L.red);   // synchronises: q and v are visible after it
+                    c0 = v2[0];
+                    b0 = v2[1];
+                }
+                __syncthreads();
                 uint32_t bits;
                 T cpiece;
                 int fl;
                 const T alpha = team_line_search<NT>(m, L.r, L.q, L.Dv, c0, b0, L.red, bits,
                                                      cpiece, fl);
                 lsfail |= fl;
-                step_inf = T(0);
-                for (int j = 0; j < n; ++j) step_inf = fmax(step_inf, fabs(alpha * L.p[j]));
-                __syncthreads();
-                for (int j = tid; j < n; j += NT) L.a[j] += alpha * L.p[j];
+                T si = T(0);
+                for (int j = tid; j < n; j += NT) {
+                    const T s = alpha * L.p[j];
+                    si = fmax(si, fabs(s));
+                    L.a[j] += s;
+                    // u = M (a - a0) for the new iterate, from the products of this step
+                    L.u[j] += alpha * L.v[j];
+                }
+                step_inf = team_max<NT>(si, L.red);
                 __syncthreads();
             }
             if (lsfail) st |= ST_LSFAIL;
@@ -351,11 +531,13 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
         const T nanv = T(__builtin_nan(""));
         for (int j = tid; j < n; j += NT) gaout[I.on + j] = ok ? L.a[j] : nanv;
         T *fac = gfac + fac_offset(I);
-        for (int e = tid; e < n * (n + 1) / 2; e += NT) {
-            int j = 0;
-            while ((j + 1) * (j + 2) / 2 <= e) ++j;
-            const int l = e - j * (j + 1) / 2;
-            fac[e] = ok ? (l < j ? L.H[j * npa + l] : L.diag[j]) : nanv;
+        {
+            TriWalk tw;
+            tw.start<NT>();
+            for (int e = tid; e < n * (n + 1) / 2; e += NT) {
+                fac[e] = ok ? (tw.l < tw.j ? L.H[tw.j * ldh + tw.l] : L.diag[tw.j]) : nanv;
+                tw.next<NT>();
+            }
         }
         for (int i = tid; i < m; i += NT) gmask[I.om + i] = ok ? L.A[i] : 0;
         if (tid == 0) {
@@ -377,25 +559,29 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
     extern __shared__ __align__(16) unsigned char smem[];
     const ChLds<T> L = ch_carve<T>(smem, npa, mmax, NT);
     const int tid = threadIdx.x;
-    const int ldj = npa + 1;
+    const int ldj = npa + 1, ldh = npa + 1;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
         const int n = I.n, m = I.m;
         const int nch = (m + CR - 1) / CR;
         const T *M = gM + I.onn, *J = gJ + I.omn;
         const T *fac = gfac + fac_offset(I);
-        for (int e = tid; e < n * (n + 1) / 2; e += NT) {
-            int j = 0;
-            while ((j + 1) * (j + 2) / 2 <= e) ++j;
-            const int l = e - j * (j + 1) / 2;
-            if (l < j) L.H[j * npa + l] = fac[e];
-            else L.diag[j] = fac[e];
+        ChStage<NT, T> stg;
+        stg.plan(n);
+        ChColSum<NT, T> cs;
+        {
+            TriWalk tw;
+            tw.start<NT>();
+            for (int e = tid; e < n * (n + 1) / 2; e += NT) {
+                if (tw.l < tw.j) L.H[tw.j * ldh + tw.l] = fac[e];
+                else L.diag[tw.j] = fac[e];
+                tw.next<NT>();
+            }
         }
         for (int j = tid; j < n; j += NT) {
             L.a[j] = ga[I.on + j];
             L.a0[j] = ga0[I.on + j];
             L.y[j] = gabar[I.on + j];
-            L.F[j] = T(0);
         }
         for (int i = tid; i < m; i += NT) {
             L.Dv[i] = gD[I.om + i];
@@ -404,23 +590,22 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
         }
         __syncthreads();
         // lambda = H^{-1} abar with one refinement step, H v = M v + J^T (D o A* o J v)
-        team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n, npa);
+        team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n, ldh);
+        cs.plan(n);
+        if (nch > 0) stg.load(J, n, m, 0);
         for (int c = 0; c < nch; ++c) {
             __syncthreads();
-            ch_load<NT>(J, n, m, c, ldj, L.Jc);
+            stg.store(n, ldj, L.Jc);
+            if (c + 1 < nch) stg.load(J, n, m, c + 1);
             __syncthreads();
             int rho, part;
             const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.u, rho, part);
             const int i = c * CR + rho;
             if (part == 0) L.Wr[rho] = (i < m && L.A[i]) ? L.Dv[i] * s : T(0);
             __syncthreads();
-            for (int j = tid; j < n; j += NT) {
-                T f = L.F[j];
-                for (int rr = 0; rr < CR; ++rr) f += L.Wr[rr] * L.Jc[rr * ldj + j];
-                L.F[j] = f;
-            }
+            cs.add_chunk(ldj, L.Jc, L.Wr);
         }
-        __syncthreads();
+        cs.finish(n, ldj, L.Jc, nullptr, L.F);
         for (int j = tid; j < n; j += NT) {
             T s = gabar[I.on + j] - L.F[j];
 #pragma unroll 4
@@ -428,17 +613,18 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
             L.y[j] = s;
         }
         __syncthreads();
-        team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, npa);
+        team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
         for (int j = tid; j < n; j += NT) L.u[j] += L.p[j];
-        __syncthreads();
         // per-row cotangents and J-bar, chunk by chunk
+        if (nch > 0) stg.load(J, n, m, 0);
         for (int c = 0; c < nch; ++c) {
             __syncthreads();
-            ch_load<NT>(J, n, m, c, ldj, L.Jc);
+            stg.store(n, ldj, L.Jc);
+            if (c + 1 < nch) stg.load(J, n, m, c + 1);
             __syncthreads();
             int rho, part;
-            const T ja = ch_row_dot<NT>(n, ldj, L.Jc, L.a, rho, part);
-            const T sig = ch_row_dot<NT>(n, ldj, L.Jc, L.u, rho, part);
+            T ja, sig;
+            ch_row_dot2<NT>(n, ldj, L.Jc, L.a, L.u, ja, sig, rho, part);
             const int i = c * CR + rho;
             if (part == 0) {
                 if (i < m) {
@@ -460,23 +646,32 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
                 const int r0 = c * CR;
                 const int cnt = min(CR, m - r0) * n;
                 T *dst = gJbar + I.omn + (int64_t)r0 * n;
+                int rr = tid / n, jj = tid - rr * n;
+                const int dr = NT / n, dc = NT - dr * n;
                 for (int e = tid; e < cnt; e += NT) {
-                    const int rr = e / n, j = e - rr * n;
-                    dst[e] = -(L.Wc[rr] * L.u[j] + L.Wr[rr] * L.a[j]);
+                    dst[e] = -(L.Wc[rr] * L.u[jj] + L.Wr[rr] * L.a[jj]);
+                    rr += dr;
+                    jj += dc;
+                    if (jj >= n) { jj -= n; ++rr; }
                 }
             }
         }
         if (ga0bar) {
             for (int j = tid; j < n; j += NT) {
                 T s = T(0);
+#pragma unroll 4
                 for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * L.u[l];
                 ga0bar[I.on + j] = s;
             }
         }
         if (gMbar) {
+            int jr = tid / n, lc = tid - jr * n;
+            const int dr = NT / n, dc = NT - dr * n;
             for (int e = tid; e < n * n; e += NT) {
-                const int j = e / n, l = e - (e / n) * n;
-                gMbar[I.onn + e] = -L.u[j] * (L.a[l] - L.a0[l]);
+                gMbar[I.onn + e] = -L.u[jr] * (L.a[lc] - L.a0[lc]);
+                jr += dr;
+                lc += dc;
+                if (lc >= n) { lc -= n; ++jr; }
             }
         }
         __syncthreads();

@@ -212,20 +212,86 @@ __device__ inline void chol_trailing(double *H, int n, int ld, int c0, int c1) {
     }
 }
 
+// Panel of the blocked Cholesky: rows i in [c1, n) of the block columns
+// [c0, c0 + 16) become L_ij = sum_k H_ik X_jk with X = L_D^{-1} of the
+// factored diagonal block, given transposed in B (B[k * 17 + j] = X_jk).
+// FP32 on the matrix cores (16-row tiles over the waves; a wave reads its
+// tile before it writes it); FP64 on the VALU in rounds of MAXP entries per
+// thread, computed before any is written.  Ends with a team barrier.
+template <int NT>
+__device__ inline void chol_panel(float *H, int n, int ld, int c0, int c1, const float *B) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (n - c1 + 15) / 16;
+    for (int t = wave; t < nt; t += NT / 64) {
+        const int ra = c1 + 16 * t + li;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lk;
+            const float a = ra < n ? H[ra * ld + c0 + k] : 0.f;
+            const float b = B[k * 17 + li];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = c1 + 16 * t + 4 * lk + r;
+            if (row < n) H[row * ld + c0 + li] = acc[r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__device__ inline void chol_panel(double *H, int n, int ld, int c0, int c1, const double *B) {
+    constexpr int MAXP = 8;
+    const int cnt = (n - c1) * 16;
+    for (int base = 0; base < cnt; base += NT * MAXP) {
+        double out[MAXP];
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q) {
+            const int e = base + (int)threadIdx.x + q * NT;
+            double v = 0.0;
+            if (e < cnt) {
+                const int row = c1 + (e >> 4), j = e & 15;
+                const double *h = H + row * ld + c0;
+                for (int k = 0; k <= j; ++k) v += h[k] * B[k * 17 + j];
+            }
+            out[q] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q) {
+            const int e = base + (int)threadIdx.x + q * NT;
+            if (e < cnt) H[(c1 + (e >> 4)) * ld + c0 + (e & 15)] = out[q];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T> __device__ inline T chol_rsq(T x);
+template <> __device__ inline float chol_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ inline double chol_rsq<double>(double x) { return 1.0 / sqrt(x); }
+
 // In-place Cholesky H = L L^T of the n x n row-major matrix in LDS (row
 // stride ld): the lower triangle is read, L is written strictly below the
 // diagonal and L_jj goes to diag[j].  Right-looking over 16-column blocks:
-// each wave factors the diagonal block in registers (one row per lane, lane
-// broadcasts; wave 0 stores it), every thread then solves one panel row against it, and the
-// trailing lower triangle takes the block's rank-16 update; three barriers
-// per block.  The caller has synchronised the team after writing H.
-// Returns false (team-uniform) when a pivot is not positive.
+// every wave factors the diagonal block in registers (one row per lane,
+// lane broadcasts) and forms its inverse X = L_D^{-1} (one column per
+// lane); wave 0 stores L_D and X^T (to work, 16 x 17 values).  The panel
+// below is H_panel X^T and the trailing lower triangle takes the block's
+// rank-16 update.  n <= 32 for NT = 64, n <= 128 for NT = 256.  The caller
+// has synchronised the team after writing H.  Returns false (team-uniform)
+// when a pivot is not positive.
 template <int NT, typename T>
-__device__ inline bool team_cholesky(T *H, T *diag, int n, int ld) {
+__device__ __attribute__((noinline)) bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
+    // sizes are team-uniform: keep them (and every branch on them) scalar
+    n = __builtin_amdgcn_readfirstlane(n);
+    ld = __builtin_amdgcn_readfirstlane(ld);
     bool ok = true;
     for (int c0 = 0; c0 < n; c0 += 16) {
         const int bs = min(16, n - c0);
-        {   // every wave factors the block (same values); wave 0 stores it
+        {
             const int l = threadIdx.x & 63;
             const bool w0 = threadIdx.x < 64;
             T d[16];
@@ -237,54 +303,58 @@ __device__ inline bool team_cholesky(T *H, T *diag, int n, int ld) {
                 const T x = hr[min(k, bs - 1)];
                 d[k] = (l < bs && k <= l) ? x : T(0);
             }
+            // Branch-free: lanes also update entries above their diagonal
+            // (never stored); every stored entry only reads entries below
+            // or on the diagonal of other rows.
+            T dl = T(1);   // this lane's L_ll
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (j < bs) {
-                    const T ljj = sqrt(lane_bcast(d[j], j));
-                    if (l == j) d[j] = ljj;
-                    else if (l > j) d[j] = d[j] / ljj;
+                    const T piv = lane_bcast(d[j], j);
+                    const T iv = chol_rsq(piv);
+                    const T djs = d[j] * iv;
+                    dl = (l == j) ? piv * iv : dl;
+                    d[j] = (l == j) ? piv * iv : djs;
 #pragma unroll
                     for (int k = j + 1; k < 16; ++k) {
-                        if (k < bs) {
-                            const T lkj = lane_bcast(d[j], k);
-                            if (l >= k) d[k] -= d[j] * lkj;
-                        }
+                        if (k < bs) d[k] -= djs * lane_bcast(djs, k);
                     }
                 }
+            }
+            // column l of X = L_D^{-1}: x_c = 0 (c < l), x_l = 1 / L_ll,
+            // x_c = -(sum_{k<c} L_ck x_k) / L_cc (c > l)
+            T x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                T acc = T(0);
+#pragma unroll
+                for (int k = 0; k < c; ++k) acc += lane_bcast(d[k], c) * x[k];
+                const T rc = T(1) / lane_bcast(d[c], c);
+                const T xc = (c == l) ? rc : -acc * rc;
+                x[c] = (c < l || c >= bs) ? T(0) : xc;
             }
             if (w0 && l < bs) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k)
                     if (k < l) H[(c0 + l) * ld + c0 + k] = d[k];
-                diag[c0 + l] = d[l];
+                diag[c0 + l] = dl;
+            }
+            if (w0 && l < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) work[l * 17 + c] = x[c];
             }
         }
         __syncthreads();
         for (int j = 0; j < bs; ++j) ok = ok && (diag[c0 + j] > T(0));
         const int c1 = c0 + bs;
         if (c1 < n) {
-            // panel rows: x L_D^T = h  (forward substitution against the block)
-            for (int i = c1 + (int)threadIdx.x; i < n; i += NT) {
-                T x[16];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    T v = H[i * ld + c0 + c];
-#pragma unroll
-                    for (int k = 0; k < c; ++k) v -= x[k] * H[(c0 + c) * ld + c0 + k];
-                    x[c] = v / diag[c0 + c];
-                }
-#pragma unroll
-                for (int c = 0; c < 16; ++c) H[i * ld + c0 + c] = x[c];
-            }
-            __syncthreads();
+            chol_panel<NT>(H, n, ld, c0, c1, work);
             chol_trailing<NT>(H, n, ld, c0, c1);
             __syncthreads();
         }
     }
     return ok;
 }
-template <int NT, typename T>
-__device__ inline bool team_cholesky(T *H, T *diag, int n) { return team_cholesky<NT>(H, diag, n, n); }
 
 // Solve L L^T x = b with the factor from team_cholesky.  b is overwritten;
 // the solution is returned in x.  Blocked like the factorisation: wave 0
@@ -292,17 +362,23 @@ __device__ inline bool team_cholesky(T *H, T *diag, int n) { return team_cholesk
 // updates one remaining entry with the block's 16 values; two barriers per
 // block and direction.  The caller has synchronised the team after writing b.
 template <int NT, typename T>
-__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
+__device__ __attribute__((noinline)) void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n,
+                                                         int ld) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    ld = __builtin_amdgcn_readfirstlane(ld);
     // forward: L y = b, y stored in x
     for (int c0 = 0; c0 < n; c0 += 16) {
         const int bs = min(16, n - c0);
         if (threadIdx.x < 64) {
             const int l = threadIdx.x;
-            T y = l < bs ? b[c0 + l] : T(0);
+            const int lr = c0 + min(l, bs - 1);       // clamped row: loads stay in bounds
+            T y = b[lr];
             for (int c = 0; c < bs; ++c) {
-                if (l == c) y = y / diag[c0 + c];
+                const T yd = y / diag[c0 + c];
+                y = (l == c) ? yd : y;
                 const T yc = lane_bcast(y, c);
-                if (l > c && l < bs) y -= L[(c0 + l) * ld + c0 + c] * yc;
+                const T upd = y - L[lr * ld + c0 + c] * yc;
+                y = (l > c) ? upd : y;
             }
             if (l < bs) x[c0 + l] = y;
         }
@@ -324,11 +400,14 @@ __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, in
         const int c0 = 16 * kb, bs = min(16, n - c0);
         if (threadIdx.x < 64) {
             const int l = threadIdx.x;
-            T v = l < bs ? x[c0 + l] : T(0);
+            const int lc = c0 + min(l, bs - 1);       // clamped column: loads stay in bounds
+            T v = x[lc];
             for (int c = bs - 1; c >= 0; --c) {
-                if (l == c) v = v / diag[c0 + c];
+                const T vd = v / diag[c0 + c];
+                v = (l == c) ? vd : v;
                 const T xc = lane_bcast(v, c);
-                if (l < c) v -= L[(c0 + c) * ld + c0 + l] * xc;
+                const T upd = v - L[(c0 + c) * ld + lc] * xc;
+                v = (l < c) ? upd : v;
             }
             if (l < bs) x[c0 + l] = v;
         }

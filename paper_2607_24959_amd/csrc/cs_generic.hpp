@@ -15,13 +15,14 @@ namespace cs {
 // LDS carve-up shared by the generic kernels.
 template <typename T>
 struct GenLds {
-    T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *pb, *ab, *red;
+    T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *pb, *ab, *red, *wk;
     T *r, *q, *Dv, *c1, *c2;
     uint8_t *A, *Ap;
 };
 
 __host__ __device__ inline size_t gen_lds_bytes(int nmax, int mmax, int NT, size_t s) {
-    size_t nT = (size_t)nmax * nmax + 11 * (size_t)nmax + 16 * (size_t)(NT / 64) + 5 * (size_t)mmax;
+    size_t nT = (size_t)nmax * nmax + 11 * (size_t)nmax + 16 * (size_t)(NT / 64) + 16 * 17 +
+                5 * (size_t)mmax;
     return nT * s + 2 * (size_t)mmax + 64;
 }
 
@@ -41,6 +42,7 @@ __device__ inline GenLds<T> gen_carve(unsigned char *smem, int nmax, int mmax, i
     L.pb = p; p += nmax;
     L.ab = p; p += nmax;
     L.red = p; p += 16 * (NT / 64);
+    L.wk = p; p += 16 * 17;
     L.r = p; p += mmax;
     L.q = p; p += mmax;
     L.Dv = p; p += mmax;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
         int st = 0, k = 0;
         if (anybad) {
             st = ST_NONFINITE;
-        } else if (!team_cholesky<NT>(L.H, L.diag, n)) {
+        } else if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) {
             st = ST_NOTSPD;
         }
         if (st == 0) {
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
                 gen_hessian<NT>(n, m, M, J, L);
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n)) { st = ST_NOTSPD; break; }
+                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) { st = ST_NOTSPD; break; }
                 team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n);
                 // q = J p; M p and M (a - a0) for the line search coefficients
                 for (int i = tid; i < m; i += NT) {
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
                 // factor of H at the returned iterate (A from its residual)
                 gen_hessian<NT>(n, m, M, J, L);
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n)) st = ST_NOTSPD;
+                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) st = ST_NOTSPD;
             }
         }
         const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             steps = giters[I.b];
         } else if (anybad) {
             st = ST_NONFINITE;
-        } else if (!team_cholesky<NT>(L.H, L.diag, n)) {
+        } else if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) {
             st = ST_NOTSPD;
         }
 
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 gen_hessian<NT>(n, m, M, J, L);
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n)) { st = ST_NOTSPD; break; }
+                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) { st = ST_NOTSPD; break; }
                 team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n);
                 for (int i = tid; i < m; i += NT) {
                     const T *Ji = J + (size_t)i * n;
