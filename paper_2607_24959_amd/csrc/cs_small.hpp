@@ -162,6 +162,28 @@ __device__ inline bool aligned16(const void *p) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
+// The 16 lanes of a group share one wave: LDS written by one lane of the
+// group is visible to the others after this (in-order LDS within a wave).
+__device__ inline void group_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copy cnt contiguous values into the group's LDS area with coalesced loads
+// (lane g takes elements g, g + 16, ...).
+template <typename T>
+__device__ inline void group_copy_in(const T *__restrict__ src, int cnt, T *dst, int g) {
+    for (int e = g; e < cnt; e += SG) dst[e] = src[e];
+}
+
+// LDS per group for staged inputs/outputs of one instance: M (NP x NP
+// values used n x n), the factor (NE), and two NP-vectors.
+template <int NP> struct GroupShm {
+    static constexpr int NE = NP * (NP + 1) / 2;
+    static constexpr int M0 = 0, F0 = NP * NP, V0 = F0 + NE, W0 = V0 + NP, SIZE = W0 + NP;
+};
+
 // Per-group instance context: one instance's data in registers.
 template <typename T, int NP, int R>
 struct SmallInst {
@@ -173,9 +195,12 @@ struct SmallInst {
     T a0[NP];
     bool bad;
 
+    // msh: the group's LDS area for M (n x n), or null to read M from global
+    // memory in every lane
     __device__ inline void load(const Inst &I, int g, const T *__restrict__ gM,
                                 const T *__restrict__ gJ, const T *__restrict__ ga0,
-                                const T *__restrict__ garef, const T *__restrict__ gD) {
+                                const T *__restrict__ garef, const T *__restrict__ gD,
+                                T *msh = nullptr) {
         n = I.n;
         m = I.m;
         i0 = g * R;
@@ -207,6 +232,11 @@ struct SmallInst {
             for (int j = 0; j < NP; ++j) bad |= !finite_val(J[jj][j]);
         }
         const T *Mb = gM + I.onn;
+        if (msh) {
+            group_copy_in(Mb, n * n, msh, g);
+            group_sync();
+            Mb = msh;
+        }
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
 #pragma unroll
@@ -314,6 +344,15 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
     T step_inf = T(-1);
     int st = 0, lsfail = 0;
     bool have_factor = false;
+    // Md = M (a - a0), carried across steps (Md += alpha M p) so each step
+    // takes one product with M
+    T Md[NP];
+    {
+        T d0[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) d0[j] = a[j] - S.a0[j];
+        sym_mv<T, NP>(S.Ml, d0, Md);
+    }
     for (int k = 0;; ++k) {
         // residual, active set and gradient (eq. 6)
         T d[NP], F[NP], r[R], wD[R];
@@ -331,13 +370,12 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
             act[jj] = an;
             wD[jj] = an ? S.D[jj] : T(0);
         }
-        sym_mv<T, NP>(S.Ml, d, F);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             T s = T(0);
 #pragma unroll
             for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * (wD[jj] * r[jj]);
-            F[j] += gsum16(s);
+            F[j] = Md[j] + gsum16(s);
         }
         const bool same = (k > 0) && gsum16(changed ? T(1) : T(0)) == T(0);
         T g2 = T(0), anorm = T(0);
@@ -436,6 +474,7 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
         for (int j = 0; j < NP; ++j) {
             const T s = alpha * p[j];
             a[j] += s;
+            Md[j] += alpha * Mp[j];
             step_inf = fmax(step_inf, fabs(s));
         }
         iters = k + 1;
@@ -479,9 +518,12 @@ __global__ __launch_bounds__(256) void k_forward_small(
     }
     const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
     const T nanv = T(__builtin_nan(""));
+    {   // lane g < n writes a[g]
+        T ag = a[0];
 #pragma unroll
-    for (int j = 0; j < NP; ++j)
-        if (j == g && j < S.n) gaout[I.on + j] = ok ? a[j] : nanv;
+        for (int j = 1; j < NP; ++j) ag = (g == j) ? a[j] : ag;
+        if (g < S.n) gaout[I.on + g] = ok ? ag : nanv;
+    }
     T *fac = gfac + fac_offset(I);
 #pragma unroll
     for (int j = 0; j < NP; ++j)
@@ -527,10 +569,15 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     if (w >= nb_inst) return;
     const Inst I = inst_at(bv, w);
     const int n = I.n, m = I.m;
+    __shared__ T sh[(256 / SG) * GroupShm<NP>::SIZE];
+    T *gsh = sh + (threadIdx.x / SG) * GroupShm<NP>::SIZE;
     SmallInst<T, NP, R> S;
-    S.load(I, g, gM, gJ, ga0, garef, gD);
+    S.load(I, g, gM, gJ, ga0, garef, gD, gsh + GroupShm<NP>::M0);
     T L[NE], inv[NP], a[NP], ab[NP];
-    const T *fac = gfac + fac_offset(I);
+    // the factor arrives through LDS: coalesced loads, then group broadcasts
+    const T *fac = gsh + GroupShm<NP>::F0;
+    group_copy_in(gfac + fac_offset(I), n * (n + 1) / 2, gsh + GroupShm<NP>::F0, g);
+    group_sync();
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
 #pragma unroll
@@ -612,16 +659,30 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     if (ga0bar) {
         T mt[NP];
         sym_mv<T, NP>(S.Ml, lam, mt);
+        T mg = mt[0];
 #pragma unroll
-        for (int j = 0; j < NP; ++j)
-            if (j == g && j < n) ga0bar[I.on + j] = mt[j];
+        for (int j = 1; j < NP; ++j) mg = (g == j) ? mt[j] : mg;
+        if (g < n) ga0bar[I.on + g] = mg;
     }
     if (gMbar) {
-        T *Mb = gMbar + I.onn;
+        // lambda and a - a0 through LDS; lane g writes entries g, g + 16, ...
+        T *vl = gsh + GroupShm<NP>::V0, *vd = gsh + GroupShm<NP>::W0;
+        if (g == 0) {
 #pragma unroll
-        for (int e = 0; e < NP * NP; ++e) {
-            const int j = e / NP, l = e % NP;
-            if ((e & (SG - 1)) == g && j < n && l < n) Mb[j * n + l] = -lam[j] * (a[l] - S.a0[l]);
+            for (int j = 0; j < NP; ++j) {
+                vl[j] = lam[j];
+                vd[j] = a[j] - S.a0[j];
+            }
+        }
+        group_sync();
+        T *Mb = gMbar + I.onn;
+        int j = g / n, l = g - (g / n) * n;
+        const int dj = SG / n, dl = SG - (SG / n) * n;
+        for (int e = g; e < n * n; e += SG) {
+            Mb[e] = -vl[j] * vd[l];
+            j += dj;
+            l += dl;
+            if (l >= n) { l -= n; ++j; }
         }
     }
 }
