@@ -62,14 +62,18 @@ extern "C" {
  * registers (FP32 n <= 12, FP64 n <= 6, m <= 64).  CHUNK: one workgroup per
  * instance, rows of J streamed through LDS in 64-row chunks, Newton matrix
  * on the matrix cores in FP32 (n <= 128, m <= 2048).  TEAM: one workgroup per
- * instance, any supported shape.  AUTO takes the first that fits in that
- * order (the unrolled VJP has SMALL and TEAM only).  A forced family that
- * does not fit returns CS_EUNSUPPORTED.  Every family writes the same state
- * layout, so any cs_ift_vjp family can read any cs_forward state. */
+ * instance, any supported shape.  WAVE (FP32 forward, n <= 31, m <= 1024):
+ * one wave per instance with J resident in LDS and the Newton matrix and
+ * J^T w from one matrix-core pass per step; its VJP runs on the CHUNK (else
+ * TEAM) family.  AUTO takes the first that fits of SMALL, CHUNK, TEAM (the
+ * unrolled VJP has SMALL and TEAM only).  A forced family that does not fit
+ * returns CS_EUNSUPPORTED.  Every family writes the same state layout, so any
+ * cs_ift_vjp family can read any cs_forward state. */
 #define CS_PATH_AUTO 0
 #define CS_PATH_TEAM 1
 #define CS_PATH_SMALL 2
 #define CS_PATH_CHUNK 3
+#define CS_PATH_WAVE 4
 
 /* Largest sizes the library supports per instance. */
 #define CS_NV_MAX 128
@@ -93,7 +97,7 @@ typedef struct cs_batch {
     int64_t total_mn;       /* packed: off_mn[B] */
     int64_t total_n;        /* packed: off_n[B] */
     int64_t total_m;        /* packed: off_m[B] */
-    int32_t path;           /* kernel family: CS_PATH_AUTO, _TEAM, _SMALL or _CHUNK */
+    int32_t path;           /* kernel family: CS_PATH_AUTO, _TEAM, _SMALL, _CHUNK or _WAVE */
     int32_t count;          /* solve only order[0 .. count-1] (0: all B; > 0 needs order).
                              * nv_max / nrows_max may then describe that subset only */
 } cs_batch;

@@ -16,7 +16,7 @@ CS_OK, CS_EINVAL, CS_ENOSPC, CS_EHIP, CS_EUNSUPPORTED = 0, -1, -2, -3, -4
 CS_F32, CS_F64 = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL = 1, 2, 4, 8, 16
 NV_MAX, NROWS_MAX = 128, 4096
-PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK = 0, 1, 2, 3
+PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",

@@ -23,7 +23,7 @@ import torch
 from . import _native as N
 from . import batching, solver, synth
 
-FAMILIES = (N.PATH_SMALL, N.PATH_CHUNK, N.PATH_TEAM)
+FAMILIES = (N.PATH_SMALL, N.PATH_WAVE, N.PATH_CHUNK, N.PATH_TEAM)
 
 
 def class_keys(nv_choices, nc_max):

@@ -102,6 +102,8 @@ class Plan:
                 gk = (fam, n_bucket(n), m_bucket(m))
             elif fam == N.PATH_CHUNK:
                 gk = (fam, 0 if n <= 32 else 1, 0)   # one launch per workgroup size
+            elif fam == N.PATH_WAVE:
+                gk = (fam, 0 if n <= 15 else 1, 0)   # one launch per padded width
             else:
                 gk = (fam, 0, 0)
             groups.setdefault(gk, []).append(i)

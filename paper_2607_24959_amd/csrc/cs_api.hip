@@ -12,6 +12,7 @@
 #include "cs_chunk.hpp"
 #include "cs_generic.hpp"
 #include "cs_small.hpp"
+#include "cs_wave.hpp"
 
 namespace {
 
@@ -33,7 +34,7 @@ int describe(const cs_batch *b, HostBatch &hb) {
     if (!b) return CS_EINVAL;
     if (b->B < 0) return CS_EINVAL;
     if (b->dtype != CS_F32 && b->dtype != CS_F64) return CS_EINVAL;
-    if (b->path < CS_PATH_AUTO || b->path > CS_PATH_CHUNK) return CS_EINVAL;
+    if (b->path < CS_PATH_AUTO || b->path > CS_PATH_WAVE) return CS_EINVAL;
     if (b->count < 0 || b->count > b->B) return CS_EINVAL;
     if (b->count > 0 && b->count != b->B && !b->order) return CS_EINVAL;
     hb.path = b->path;
@@ -104,7 +105,7 @@ int check_params(const cs_solver_params *p, bool unrolled = false) {
     return CS_OK;
 }
 
-enum { FAM_TEAM = 0, FAM_SMALL = 1, FAM_CHUNK = 2 };
+enum { FAM_TEAM = 0, FAM_SMALL = 1, FAM_CHUNK = 2, FAM_WAVE = 3 };
 
 // Kernel family for this batch (FAM_*) or a negative error code.
 int choose_family(const HostBatch &hb) {
@@ -113,16 +114,26 @@ int choose_family(const HostBatch &hb) {
     switch (hb.path) {
     case CS_PATH_SMALL: return small ? FAM_SMALL : CS_EUNSUPPORTED;
     case CS_PATH_CHUNK: return chunk ? FAM_CHUNK : CS_EUNSUPPORTED;
+    case CS_PATH_WAVE:
+        return cs::wave_supported(hb.nmax, hb.mmax, (int)hb.s) ? FAM_WAVE : CS_EUNSUPPORTED;
     case CS_PATH_TEAM: return FAM_TEAM;
     default: return small ? FAM_SMALL : (chunk ? FAM_CHUNK : FAM_TEAM);
     }
+}
+
+// The VJP family for a batch whose forward ran on `fam`: the WAVE family
+// has no VJP kernel of its own (the state layout is shared).
+int vjp_family(const HostBatch &hb, int fam) {
+    if (fam != FAM_WAVE) return fam;
+    return cs::chunk_supported(hb.nmax, hb.mmax, (int)hb.s) ? FAM_CHUNK : FAM_TEAM;
 }
 
 int choose_family_unrolled(const HostBatch &hb) {
     const bool small = cs::small_unrolled_supported(hb.nmax, hb.mmax, (int)hb.s);
     switch (hb.path) {
     case CS_PATH_SMALL: return small ? FAM_SMALL : CS_EUNSUPPORTED;
-    case CS_PATH_CHUNK: return CS_EUNSUPPORTED;
+    case CS_PATH_CHUNK:
+    case CS_PATH_WAVE: return CS_EUNSUPPORTED;
     case CS_PATH_TEAM: return FAM_TEAM;
     default: return small ? FAM_SMALL : FAM_TEAM;
     }
@@ -153,6 +164,16 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
     uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int fam = choose_family(hb);
     if (fam < 0) return fam;
+    if constexpr (sizeof(T) == 4) {
+        if (fam == FAM_WAVE) {
+            const int rc = cs::launch_wave_forward(hb.bv, hb.bv.B, hb.nmax, hb.mmax, p->max_iter,
+                                                   (float)p->tol, (const float *)M, (const float *)J,
+                                                   (const float *)a0, (const float *)aref,
+                                                   (const float *)D, (const float *)a_init,
+                                                   (float *)a_out, fac, mask, status, iters, stream);
+            return rc == 0 ? CS_OK : CS_EHIP;
+        }
+    }
     if (fam == FAM_CHUNK) {
         const int rc = cs::launch_chunk_forward<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, p->max_iter,
                                                    (T)p->tol, (const T *)M, (const T *)J,
@@ -195,7 +216,7 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
     const T *fac = static_cast<const T *>(state);
     const uint8_t *mask =
         static_cast<const uint8_t *>(state) + align256(hb.s * factor_elems(hb));
-    const int fam = choose_family(hb);
+    const int fam = vjp_family(hb, choose_family(hb));
     if (fam < 0) return fam;
     if (fam == FAM_CHUNK) {
         const int rc = cs::launch_chunk_vjp<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, fac, mask,

@@ -164,3 +164,40 @@ def test_graph_replay_matches_eager():
         # eager work between replays
         plan.forward(t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=3, tol=1e-5)
         torch.cuda.synchronize()
+
+
+def test_wave_family_mixed_fp32():
+    """One-wave family (J resident in LDS): n in {3, 9, 18, 31}, 0..256 contacts."""
+    _needs_gpu()
+    pb = synth.uneven_batch(96, (3, 9, 18, 31), 256, seed=77)
+    p32 = pb.astype(np.float32)
+    p64 = pb.rounded(np.float32)
+    batch = solver.Batch.packed_from(pb.nv, pb.nrows, torch.float32, path=N.PATH_WAVE)
+    t = _dev(p32, torch.float32)
+    sol = solver.forward(batch, *(t[k] for k in KEYS[:5]), max_iter=60, tol=1e-5)
+    grads = solver.ift_vjp(batch, sol, *(t[k] for k in KEYS[:5]), t["abar"])
+    torch.cuda.synchronize()
+    assert np.all(sol.status.cpu().numpy() & (N.ST_NONFINITE | N.ST_NOTSPD) == 0)
+    n_checked, bad, worst = _check_sample(pb, p64, sol, grads, range(pb.B), 60, 1e-4, 1e-3, "wave fp32")
+    assert n_checked >= 70
+    assert len(bad) <= 4, bad
+    # the same instances on the chunked family agree to FP32 rounding
+    b2 = solver.Batch.packed_from(pb.nv, pb.nrows, torch.float32, path=N.PATH_CHUNK)
+    s2 = solver.forward(b2, *(t[k] for k in KEYS[:5]), max_iter=60, tol=1e-5)
+    torch.cuda.synchronize()
+    conv = (sol.status.cpu().numpy() & 1) & (s2.status.cpu().numpy() & 1)
+    a1, a2 = sol.a.cpu().numpy(), s2.a.cpu().numpy()
+    errs = [np.linalg.norm(a1[pb.off_n[i]:pb.off_n[i + 1]] - a2[pb.off_n[i]:pb.off_n[i + 1]]) /
+            max(np.linalg.norm(a2[pb.off_n[i]:pb.off_n[i + 1]]), 1e-30) for i in range(pb.B) if conv[i]]
+    assert np.median(errs) <= 1e-5
+
+
+def test_wave_family_rejects_fp64_and_large_n():
+    _needs_gpu()
+    for dtype, n in ((torch.float64, 9), (torch.float32, 36)):
+        batch = solver.Batch.uniform(4, n, 8, dtype, path=N.PATH_WAVE)
+        z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
+        s = batch.sizes()
+        with pytest.raises(N.CsError) as e:
+            solver.forward(batch, z(s["M"]), z(s["J"]), z(s["a0"]), z(s["aref"]), z(s["D"]))
+        assert e.value.code == N.CS_EUNSUPPORTED
