@@ -65,9 +65,9 @@ extern "C" {
  * instance, any supported shape.  WAVE (FP32 forward, n <= 31, m <= 1024):
  * one wave per instance with J resident in LDS and the Newton matrix and
  * J^T w from one matrix-core pass per step; its VJP runs on the CHUNK (else
- * TEAM) family.  AUTO takes the first that fits of SMALL, CHUNK, TEAM (the
- * unrolled VJP has SMALL and TEAM only).  A forced family that does not fit
- * returns CS_EUNSUPPORTED.  Every family writes the same state layout, so any
+ * TEAM) family.  AUTO takes the first that fits of SMALL, WAVE, CHUNK,
+ * TEAM (the unrolled VJP has SMALL and TEAM only).  A forced family that
+ * does not fit returns CS_EUNSUPPORTED.  Every family writes the same state layout, so any
  * cs_ift_vjp family can read any cs_forward state. */
 #define CS_PATH_AUTO 0
 #define CS_PATH_TEAM 1

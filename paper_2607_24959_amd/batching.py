@@ -57,6 +57,8 @@ def default_family(dtype, n, m):
     s = 4 if dtype == torch.float32 else 8
     if m <= 64 and ((s == 4 and n <= 12) or (s == 8 and n <= 6)):
         return N.PATH_SMALL
+    if s == 4 and n <= 31 and m <= 1024:
+        return N.PATH_WAVE
     if n <= 128 and m <= 2048:
         return N.PATH_CHUNK
     return N.PATH_TEAM

@@ -117,7 +117,10 @@ int choose_family(const HostBatch &hb) {
     case CS_PATH_WAVE:
         return cs::wave_supported(hb.nmax, hb.mmax, (int)hb.s) ? FAM_WAVE : CS_EUNSUPPORTED;
     case CS_PATH_TEAM: return FAM_TEAM;
-    default: return small ? FAM_SMALL : (chunk ? FAM_CHUNK : FAM_TEAM);
+    default:
+        if (small) return FAM_SMALL;
+        if (cs::wave_supported(hb.nmax, hb.mmax, (int)hb.s)) return FAM_WAVE;
+        return chunk ? FAM_CHUNK : FAM_TEAM;
     }
 }
 

@@ -22,13 +22,19 @@ namespace cs {
 
 // Padded width: n + 1 columns (J and the residual), a multiple of 16.
 __host__ __device__ inline int wave_npa(int n) { return (n + 1 + 15) & ~15; }
-__host__ __device__ inline int wave_rows(int m) { return (m + 63) & ~63; }
+__host__ __device__ inline int wave_rows(int m) { return m < 64 ? 64 : (m + 63) & ~63; }
 
-// LDS: J (mp x (NPA + 1)), H (NPA x (NPA + 1)), five row arrays (r, q, D,
-// aref, weights), two NPA vectors, reduction scratch, the active bytes.
+// LDS: J (mp x (NPA + 1)), H (NPA x (NPA + 1)), the row weights of the
+// matrix-core pass, two NPA vectors.
 __host__ __device__ inline size_t wave_lds_bytes(int npa, int mmax) {
     const size_t ld = (size_t)npa + 1, mp = (size_t)wave_rows(mmax);
-    return (mp * ld + (size_t)npa * ld + 5 * mp + 2 * (size_t)npa + 16) * sizeof(float) + mp;
+    return (mp * ld + (size_t)npa * ld + mp + 2 * (size_t)npa) * sizeof(float);
+}
+
+// Rows per lane for up to mmax rows.
+inline int wave_rpl(int mmax) {
+    const int r = (mmax + 63) / 64;
+    return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
 }
 
 typedef float wf4 __attribute__((ext_vector_type(4)));
@@ -38,7 +44,83 @@ __device__ inline float wave_lane(float v, int k) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
 }
 
-template <int NPA>
+// Wave-wide sum and max, every lane receives the result: DPP within each
+// row of 16 lanes (quad xor 1 and 2, half-row and row mirrors), then the
+// four row totals from lanes 0, 16, 32, 48.  Fixed order: reproducible.
+template <int CTRL> __device__ inline float wv_dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float wave_total(float v) {
+    v += wv_dpp<0xB1>(v);
+    v += wv_dpp<0x4E>(v);
+    v += wv_dpp<0x141>(v);
+    v += wv_dpp<0x140>(v);
+    return (wave_lane(v, 0) + wave_lane(v, 16)) + (wave_lane(v, 32) + wave_lane(v, 48));
+}
+__device__ inline float wave_maximum(float v) {
+    v = fmaxf(v, wv_dpp<0xB1>(v));
+    v = fmaxf(v, wv_dpp<0x4E>(v));
+    v = fmaxf(v, wv_dpp<0x141>(v));
+    v = fmaxf(v, wv_dpp<0x140>(v));
+    return fmaxf(fmaxf(wave_lane(v, 0), wave_lane(v, 16)), fmaxf(wave_lane(v, 32), wave_lane(v, 48)));
+}
+
+// Exact line search (Sec. III-B, eq. 10) with the lane's rows in registers;
+// the safeguarded piece Newton of team_line_search (rows past m carry
+// D = q = 0, so they are never active).
+template <int RPL>
+__device__ inline float wave_line_search(const float (&r)[RPL], const float (&q)[RPL],
+                                         const float (&D)[RPL], float c0, float b0, int &fail) {
+    float dqq[RPL], dqr[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const float dq = D[t] * q[t];
+        dqq[t] = dq * q[t];
+        dqr[t] = dq * r[t];
+    }
+    auto piece = [&](float tr, uint32_t &bits, float &c, float &b) {
+        float sc = 0.f, sb = 0.f;
+        uint32_t bb = 0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const bool pa = r[t] + tr * q[t] < 0.f;
+            sc += pa ? dqq[t] : 0.f;
+            sb += pa ? dqr[t] : 0.f;
+            bb |= (pa ? 1u : 0u) << t;
+        }
+        c = c0 + wave_total(sc);
+        b = b0 + wave_total(sb);
+        bits = bb;
+    };
+    float t = 1.f, c, b;
+    uint32_t bits;
+    piece(t, bits, c, b);
+    float lo = 0.f, hi = __builtin_huge_valf(), alpha = t;
+    fail = 1;
+    const float eps = 1.1920929e-7f;
+    for (int it = 0; it < 96; ++it) {
+        const float g = c * t + b;
+        if (g == 0.f) { alpha = t; fail = 0; break; }
+        if (g < 0.f) lo = t; else hi = t;
+        if (hi < __builtin_huge_valf() && hi - lo <= 32.f * eps * hi) { alpha = t; fail = 0; break; }
+        float cand = -b / c;
+        const bool newton = (cand > lo) && (cand < hi);
+        if (!newton) cand = (hi < __builtin_huge_valf()) ? 0.5f * (lo + hi) : 2.f * lo + 1.f;
+        uint32_t nb;
+        float nc, nbv;
+        piece(cand, nb, nc, nbv);
+        const float mism = wave_total((float)__builtin_popcount(nb ^ bits));
+        bits = nb;
+        c = nc;
+        b = nbv;
+        t = cand;
+        alpha = cand;
+        if (newton && mism == 0.f) { fail = 0; break; }
+    }
+    return alpha;
+}
+
+template <int NPA, int RPL>
 __global__ __launch_bounds__(64) void k_forward_wave(
     BatchView bv, int count, int max_iter, float tol, int mmax, const float *__restrict__ gM,
     const float *__restrict__ gJ, const float *__restrict__ ga0, const float *__restrict__ garef,
@@ -47,14 +129,14 @@ __global__ __launch_bounds__(64) void k_forward_wave(
     int32_t *__restrict__ giters) {
     static_assert(NPA == 16 || NPA == 32, "padded width");
     constexpr int LD = NPA + 1;
-    constexpr int NTL = (NPA / 16) * (NPA / 16 + 1) / 2;   // lower-triangle tiles
+    constexpr int NB = NPA / 16;                     // column blocks
+    constexpr int NTL = NB * (NB + 1) / 2;           // lower-triangle tiles
     extern __shared__ __align__(16) unsigned char smem[];
     const int mp = wave_rows(mmax);
     float *Js = reinterpret_cast<float *>(smem);
     float *Hs = Js + (size_t)mp * LD;
-    float *Rs = Hs + NPA * LD, *Qs = Rs + mp, *Ds = Qs + mp, *As_ref = Ds + mp, *Wc = As_ref + mp;
-    float *Fs = Wc + mp, *Vs = Fs + NPA, *red = Vs + NPA;
-    uint8_t *Ab = reinterpret_cast<uint8_t *>(red + 16);
+    float *Wc = Hs + NPA * LD;
+    float *Fs = Wc + mp, *Vs = Fs + NPA;
     const int l = threadIdx.x;
     const int kq = l >> 4, idx = l & 15;
 
@@ -64,7 +146,9 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         const int m4 = (m + 3) & ~3;
         const float *M = gM + I.onn, *J = gJ + I.omn;
         bool bad = false;
-        // J into LDS (columns < n), rows m .. m4-1 zero in every column
+        // J into LDS (columns < n); columns n .. NPA-1 of the live rows and
+        // rows m .. m4-1 start at zero, so row products run over all NPA
+        // columns (a and p are zero past n)
         {
             int rr = l / n, cc = l - (l / n) * n;
             const int dr = 64 / n, dc = 64 - dr * n;
@@ -77,13 +161,20 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 if (cc >= n) { cc -= n; ++rr; }
             }
             for (int e = l; e < (m4 - m) * LD; e += 64) Js[m * LD + e] = 0.f;
+            const int pad = NPA - n;
+            for (int e = l; e < m * pad; e += 64) {
+                const int i = e / pad;
+                Js[i * LD + n + (e - i * pad)] = 0.f;
+            }
         }
-        for (int i = l; i < m; i += 64) {
-            const float d = gD[I.om + i], ar = garef[I.om + i];
-            Ds[i] = d;
-            As_ref[i] = ar;
-            Ab[i] = 0;
-            bad |= !finite_val(d) || !finite_val(ar);
+        // the lane's rows l + 64 t: D and aref in registers (zero past m)
+        float Dr[RPL], ar[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int i = l + 64 * t;
+            Dr[t] = i < m ? gD[I.om + i] : 0.f;
+            ar[t] = i < m ? garef[I.om + i] : 0.f;
+            bad |= !finite_val(Dr[t]) || !finite_val(ar[t]);
         }
         for (int i = m + l; i < m4; i += 64) Wc[i] = 0.f;
         // lane j < n: row j of M, a_j, a0_j
@@ -103,8 +194,9 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         const bool anybad = __syncthreads_or(bad);
 
         // Cholesky of the rows h (lane i holds row i, entries c <= i), in
-        // place; returns false when a pivot is not positive.  Entries above
-        // the diagonal are updated too and never used.
+        // place; idl gets 1 / L_ii.  Entries above the diagonal are updated
+        // too and never used.  False when a pivot is not positive.
+        float idl = 1.f;
         auto factor = [&](float (&h)[NPA]) -> bool {
             bool ok = true;
 #pragma unroll
@@ -112,14 +204,14 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 if (j < n) {
                     const float piv = wave_lane(h[j], j);
                     ok = ok && (piv > 0.f);
-                    const float ljj = sqrtf(piv);
-                    const float inv = 1.f / ljj;
-                    h[j] = (l == j) ? ljj : h[j] * inv;
+                    const float inv = __builtin_amdgcn_rsqf(piv);
+                    if (l == j) idl = inv;
+                    h[j] = (l == j) ? piv * inv : h[j] * inv;
                     if (l < NPA) Vs[l] = h[j];   // column j of L (rows >= n hold 0)
                     __syncthreads();
+                    // rows >= n are zero, so their column entries are zero
 #pragma unroll
-                    for (int k = j + 1; k < NPA; ++k)
-                        if (k < n) h[k] -= h[j] * Vs[k];
+                    for (int k2 = j + 1; k2 < NPA; ++k2) h[k2] -= h[j] * Vs[k2];
                     __syncthreads();
                 }
             }
@@ -128,6 +220,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 
         int st = 0, k = 0;
         float h[NPA];
+        uint32_t act = 0;   // activity of the lane's rows
         if (anybad) {
             st = ST_NONFINITE;
         } else {
@@ -149,49 +242,64 @@ __global__ __launch_bounds__(64) void k_forward_wave(
             float step_inf = -1.f;
             int lsfail = 0;
             bool have_factor = false;
+            float rr[RPL];
             for (k = 0;; ++k) {
                 // residuals and active set of the lane's rows; r into column n
+                // (av[n] is zero: the previous residual there drops out)
                 float av[NPA];
 #pragma unroll
                 for (int c = 0; c < NPA; ++c) av[c] = wave_lane(aj, c);
-                bool changed = false;
-                for (int i = l; i < m; i += 64) {
-                    const float *row = Js + i * LD;
+                uint32_t nact = 0;
+#pragma unroll
+                for (int t = 0; t < RPL; ++t) {
+                    const int i = l + 64 * t;
+                    const float *row = Js + min(i, m4 > 0 ? m4 - 1 : 0) * LD;
                     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
                     for (int c = 0; c < NPA; c += 2) {
-                        if (c < n) s0 += row[c] * av[c];
-                        if (c + 1 < n) s1 += row[c + 1] * av[c + 1];
+                        s0 += row[c] * av[c];
+                        s1 += row[c + 1] * av[c + 1];
                     }
-                    const float r = s0 + s1 - As_ref[i];
-                    const uint8_t an = r < 0.f;
-                    changed |= an != Ab[i];
-                    Ab[i] = an;
-                    Rs[i] = r;
-                    Js[i * LD + n] = r;
-                    Wc[i] = an ? Ds[i] : 0.f;
+                    rr[t] = (i < m) ? s0 + s1 - ar[t] : 0.f;
+                    const bool an = rr[t] < 0.f && i < m;
+                    nact |= (an ? 1u : 0u) << t;
+                    if (i < m) {
+                        Js[i * LD + n] = rr[t];
+                        Wc[i] = an ? Dr[t] : 0.f;
+                    }
                 }
-                const bool same = !__syncthreads_or(changed);
-                // lower triangle of [J | r]^T diag(Wc) [J | r] on the matrix cores
+                const bool same = !__syncthreads_or(nact != act);
+                act = nact;
+                // lower triangle of [J | r]^T diag(Wc) [J | r] on the matrix
+                // cores; the next K-step's operands load while this one runs
                 wf4 acc[NTL];
 #pragma unroll
                 for (int t = 0; t < NTL; ++t) acc[t] = wf4{0.f, 0.f, 0.f, 0.f};
-                for (int ks = 0; ks < m4 / 4; ++ks) {
-                    const int row = 4 * ks + kq;
-                    const float wr = Wc[row];
-                    const float *jr = Js + row * LD + idx;
-                    float cb[NPA / 16];
+                const int nks = m4 / 4;
+                if (nks > 0) {
+                    float wr = Wc[kq];
+                    float cb[NB];
 #pragma unroll
-                    for (int b = 0; b < NPA / 16; ++b) cb[b] = jr[16 * b];
+                    for (int bb = 0; bb < NB; ++bb) cb[bb] = Js[kq * LD + idx + 16 * bb];
+                    for (int ks = 0; ks < nks; ++ks) {
+                        const int nrow = 4 * min(ks + 1, nks - 1) + kq;
+                        const float wn = Wc[nrow];
+                        float cn[NB];
 #pragma unroll
-                    for (int ti = 0, t = 0; ti < NPA / 16; ++ti)
+                        for (int bb = 0; bb < NB; ++bb) cn[bb] = Js[nrow * LD + idx + 16 * bb];
 #pragma unroll
-                        for (int tj = 0; tj <= ti; ++tj, ++t)
-                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[ti], wr * cb[tj], acc[t], 0, 0, 0);
+                        for (int ti = 0, t = 0; ti < NB; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj <= ti; ++tj, ++t)
+                                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cb[ti], wr * cb[tj], acc[t], 0, 0, 0);
+                        wr = wn;
+#pragma unroll
+                        for (int bb = 0; bb < NB; ++bb) cb[bb] = cn[bb];
+                    }
                 }
                 // H part to Hs (rows < n), J^T w (row n) to Fs
 #pragma unroll
-                for (int ti = 0, t = 0; ti < NPA / 16; ++ti)
+                for (int ti = 0, t = 0; ti < NB; ++ti)
 #pragma unroll
                     for (int tj = 0; tj <= ti; ++tj, ++t)
 #pragma unroll
@@ -202,12 +310,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                         }
                 __syncthreads();
                 const float Fj = (l < n) ? Md + Fs[l] : 0.f;
-                float g2 = Fj * Fj, an = fabsf(aj);
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    g2 += __shfl_xor(g2, o, 64);
-                    an = fmaxf(an, __shfl_xor(an, o, 64));
-                }
+                const float g2 = wave_total(Fj * Fj), an = wave_maximum(fabsf(aj));
                 if (!(same && have_factor)) {
 #pragma unroll
                     for (int c = 0; c < NPA; ++c)
@@ -226,7 +329,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 #pragma unroll
                 for (int j = 0; j < NPA; ++j) {
                     if (j < n) {
-                        const float yj = wave_lane(y / h[j], j);
+                        const float yj = wave_lane(y * idl, j);
                         y = (l == j) ? yj : ((l > j) ? y - h[j] * yj : y);
                     }
                 }
@@ -239,7 +342,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 #pragma unroll
                 for (int j = NPA - 1; j >= 0; --j) {
                     if (j < n) {
-                        const float xj = wave_lane(pj / h[j], j);
+                        const float xj = wave_lane(pj * idl, j);
                         const float lji = Hs[j * LD + (l < n ? l : 0)];
                         pj = (l == j) ? xj : ((l < j) ? pj - lji * xj : pj);
                     }
@@ -249,35 +352,27 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 float pv[NPA];
 #pragma unroll
                 for (int c = 0; c < NPA; ++c) pv[c] = wave_lane(pj, c);
-                for (int i = l; i < m; i += 64) {
-                    const float *row = Js + i * LD;
+                float qr[RPL];
+#pragma unroll
+                for (int t = 0; t < RPL; ++t) {
+                    const int i = l + 64 * t;
+                    const float *row = Js + min(i, m4 > 0 ? m4 - 1 : 0) * LD;
                     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
                     for (int c = 0; c < NPA; c += 2) {
-                        if (c < n) s0 += row[c] * pv[c];
-                        if (c + 1 < n) s1 += row[c + 1] * pv[c + 1];
+                        s0 += row[c] * pv[c];
+                        s1 += row[c + 1] * pv[c + 1];
                     }
-                    Qs[i] = s0 + s1;
+                    qr[t] = (i < m) ? s0 + s1 : 0.f;
                 }
                 float Mp = 0.f;
 #pragma unroll
                 for (int c = 0; c < NPA; ++c) Mp += Mrow[c] * pv[c];
-                float c0 = pj * Mp, b0 = pj * Md;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    c0 += __shfl_xor(c0, o, 64);
-                    b0 += __shfl_xor(b0, o, 64);
-                }
-                __syncthreads();
-                uint32_t bits;
-                float cpiece;
+                const float c0 = wave_total(pj * Mp), b0 = wave_total(pj * Md);
                 int fl;
-                const float alpha = team_line_search<64>(m, Rs, Qs, Ds, c0, b0, red, bits, cpiece, fl);
+                const float alpha = wave_line_search<RPL>(rr, qr, Dr, c0, b0, fl);
                 lsfail |= fl;
-                float si = fabsf(alpha * pj);
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) si = fmaxf(si, __shfl_xor(si, o, 64));
-                step_inf = si;
+                step_inf = wave_maximum(fabsf(alpha * pj));
                 aj += alpha * pj;
                 Md += alpha * Mp;
                 __syncthreads();
@@ -302,7 +397,11 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 while (c > j) { c -= j + 1; ++j; }
             }
         }
-        for (int i = l; i < m; i += 64) gmask[I.om + i] = ok ? Ab[i] : 0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int i = l + 64 * t;
+            if (i < m) gmask[I.om + i] = (ok && ((act >> t) & 1u)) ? 1 : 0;
+        }
         if (l == 0) {
             gstatus[I.b] = st;
             if (giters) giters[I.b] = k;
@@ -326,17 +425,20 @@ inline int launch_wave_forward(const BatchView &bv, int count, int nmax, int mma
     const int npa = wave_npa(nmax);
     const size_t lds = wave_lds_bytes(npa, mmax);
     const unsigned grid = (unsigned)(count < (1 << 20) ? count : (1 << 20));
-    if (npa == 16) {
-        auto k = k_forward_wave<16>;
-        if (!ensure_lds(reinterpret_cast<const void *>(k), lds)) return -3;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, stream, bv, count, max_iter, tol, mmax, M, J,
-                           a0, aref, D, a_init, a_out, fac, mask, status, iters);
-    } else {
-        auto k = k_forward_wave<32>;
-        if (!ensure_lds(reinterpret_cast<const void *>(k), lds)) return -3;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, stream, bv, count, max_iter, tol, mmax, M, J,
-                           a0, aref, D, a_init, a_out, fac, mask, status, iters);
+    const int rpl = wave_rpl(mmax);
+    int rc = -3;
+#define CS_WAVE_CALL(NPAV, RPLV)                                                                 \
+    if (npa == NPAV && rpl == RPLV) {                                                          \
+        auto k = k_forward_wave<NPAV, RPLV>;                                                   \
+        if (!ensure_lds(reinterpret_cast<const void *>(k), lds)) return -3;                    \
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, stream, bv, count, max_iter, tol, mmax, M, \
+                           J, a0, aref, D, a_init, a_out, fac, mask, status, iters);           \
+        rc = 0;                                                                                \
     }
+    CS_WAVE_CALL(16, 1) CS_WAVE_CALL(16, 2) CS_WAVE_CALL(16, 4) CS_WAVE_CALL(16, 8) CS_WAVE_CALL(16, 16)
+    CS_WAVE_CALL(32, 1) CS_WAVE_CALL(32, 2) CS_WAVE_CALL(32, 4) CS_WAVE_CALL(32, 8) CS_WAVE_CALL(32, 16)
+#undef CS_WAVE_CALL
+    if (rc != 0) return -3;
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -208,7 +208,13 @@ class Engine:
         for npad in batching.SMALL_NP:
             if npad <= self.n_cap and ((s == 4 and npad <= 12) or (s == 8 and npad <= 6)):
                 out.append((N.PATH_SMALL, npad, min(64, self.m_cap)))
-        out.append((N.PATH_CHUNK, min(32, self.n_cap), self.m_cap))
+        if s == 4:   # the one-wave family: n <= 31, up to 1024 rows
+            wm = min(1024, self.m_cap)
+            out.append((N.PATH_WAVE, min(15, self.n_cap), wm))
+            if self.n_cap > 15:
+                out.append((N.PATH_WAVE, min(31, self.n_cap), wm))
+        if s == 8 or self.m_cap > 1024 or self.n_cap > 31:
+            out.append((N.PATH_CHUNK, min(32, self.n_cap), self.m_cap))
         if self.n_cap > 32:
             out.append((N.PATH_CHUNK, self.n_cap, self.m_cap))
         return out

@@ -174,9 +174,11 @@ def test_backward_memory_flat_in_K_for_ift_linear_for_unrolled():
     ift = {K: _peak_backward_bytes(P, "ift", K) for K in (1, 5, 10)}
     unr = {K: _peak_backward_bytes(P, "unrolled", K) for K in (1, 5, 10)}
     print("peak bytes IFT", ift, "unrolled", unr)
-    # IFT keeps one K-independent state per step: its peak must not grow with K
-    # (the caching allocator's block splitting moves it by up to ~10% either way)
-    assert ift[10] <= 1.02 * ift[1] and ift[5] <= 1.02 * ift[1]
+    # IFT keeps one K-independent state per step: its peak must not grow with K.
+    # Library temporaries (batched products in the rollout) move the measured
+    # peak by up to ~12% from call to call, with no trend in K; the unrolled
+    # trace instead grows by one saved iterate set per Newton iteration.
     assert max(ift.values()) <= 1.2 * min(ift.values())
+    assert abs(ift[10] - ift[1]) <= 0.05 * (unr[10] - unr[1])
     assert unr[10] > 3 * unr[1]
     assert unr[10] > 5 * ift[10]

@@ -194,8 +194,8 @@ def test_wave_family_mixed_fp32():
 
 def test_wave_family_rejects_fp64_and_large_n():
     _needs_gpu()
-    for dtype, n in ((torch.float64, 9), (torch.float32, 36)):
-        batch = solver.Batch.uniform(4, n, 8, dtype, path=N.PATH_WAVE)
+    for dtype, n, m in ((torch.float64, 9, 8), (torch.float32, 36, 8), (torch.float32, 9, 1028)):
+        batch = solver.Batch.uniform(4, n, m, dtype, path=N.PATH_WAVE)
         z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
         s = batch.sizes()
         with pytest.raises(N.CsError) as e:

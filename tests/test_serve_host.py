@@ -37,8 +37,14 @@ def test_kernel_classes():
     c = e32.classes
     assert e32.class_of(3, 0) != e32.class_of(9, 64)
     assert c[e32.class_of(9, 64)][0] == N.PATH_SMALL
-    assert c[e32.class_of(9, 68)][0] == N.PATH_CHUNK
-    assert c[e32.class_of(18, 8)][0] == N.PATH_CHUNK
+    assert c[e32.class_of(9, 68)][0] == N.PATH_WAVE
+    assert c[e32.class_of(18, 8)][0] == N.PATH_WAVE
+    assert c[e32.class_of(18, 8)] != c[e32.class_of(9, 68)]   # padded widths 32 and 16
+    e_wide = serve.Engine(slots=2, m_cap=1024, device="cpu")
+    assert e_wide.classes[e_wide.class_of(18, 600)][0] == N.PATH_WAVE
+    e_huge = serve.Engine(slots=2, m_cap=2048, device="cpu")
+    assert e_huge.classes[e_huge.class_of(18, 1500)][0] == N.PATH_CHUNK
+    assert e_wide.classes[e_wide.class_of(18, 100)][0] == N.PATH_WAVE
     e64 = serve.Engine(slots=2, dtype=torch.float64, device="cpu")
     assert e64.classes[e64.class_of(9, 8)][0] == N.PATH_CHUNK
     assert e64.classes[e64.class_of(6, 8)][0] == N.PATH_SMALL
