@@ -195,17 +195,55 @@ struct SmallInst {
     T a0[NP];
     bool bad;
 
-    // msh: the group's LDS area for M (n x n), or null to read M from global
-    // memory in every lane
-    __device__ inline void load(const Inst &I, int g, const T *__restrict__ gM,
-                                const T *__restrict__ gJ, const T *__restrict__ ga0,
-                                const T *__restrict__ garef, const T *__restrict__ gD,
-                                T *msh = nullptr) {
+    // True for the whole wave when every lane's block is R full rows of
+    // width NP at 16-byte aligned addresses (where vector loads are used):
+    // then load_fast() issues every load of the instance before any use.
+    __device__ static inline bool fast_ok(const Inst &I, int g, const T *__restrict__ gJ,
+                                          const T *__restrict__ garef, const T *__restrict__ gD) {
+        constexpr int V = Vec16<T>::V;
+        const int i0 = g * R;
+        const bool fl = (I.n == NP) && (i0 + R <= I.m);
+        const bool vj = (R * NP) % V != 0 || aligned16(gJ + I.omn + (int64_t)i0 * NP);
+        const bool vr = R % V != 0 || (aligned16(garef + I.om + i0) && aligned16(gD + I.om + i0));
+        return __builtin_amdgcn_ballot_w64(!(fl && vj && vr)) == 0;
+    }
+
+    // Loads of a full block (fast_ok): no predicates, so the compiler keeps
+    // every load in flight together.
+    __device__ inline void load_fast(const Inst &I, int g, const T *__restrict__ gM,
+                                     const T *__restrict__ gJ, const T *__restrict__ ga0,
+                                     const T *__restrict__ garef, const T *__restrict__ gD) {
+        n = NP;
+        m = I.m;
+        i0 = g * R;
+        full = true;
+        T flat[R * NP];
+        load_run<T, R * NP>(gJ + I.omn + (int64_t)i0 * NP, true, R * NP, flat);
+        load_run<T, R>(garef + I.om + i0, true, R, aref);
+        load_run<T, R>(gD + I.om + i0, true, R, D);
+        const T *Mb = gM + I.onn;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+#pragma unroll
+            for (int l = 0; l <= j; ++l) Ml[Tri<NP>::idx(j, l)] = Mb[j * NP + l];
+            a0[j] = ga0[I.on + j];
+        }
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) J[jj][j] = flat[jj * NP + j];
+    }
+
+    // General loads (ragged blocks, n < NP).  msh: the group's LDS area for
+    // M (n x n), or null to read M from global memory in every lane.
+    __device__ inline void load_general(const Inst &I, int g, const T *__restrict__ gM,
+                                        const T *__restrict__ gJ, const T *__restrict__ ga0,
+                                        const T *__restrict__ garef, const T *__restrict__ gD,
+                                        T *msh) {
         n = I.n;
         m = I.m;
         i0 = g * R;
         full = (n == NP) && (i0 + R <= m);
-        bad = false;
         const T *Jb = gJ + I.omn + (int64_t)i0 * n;
         if (full) {
             T flat[R * NP];
@@ -225,12 +263,6 @@ struct SmallInst {
         const T *ar = garef + I.om + i0, *dd = gD + I.om + i0;
         load_run<T, R>(ar, live >= R && aligned16(ar), live, aref);
         load_run<T, R>(dd, live >= R && aligned16(dd), live, D);
-#pragma unroll
-        for (int jj = 0; jj < R; ++jj) {
-            bad |= !finite_val(aref[jj]) || !finite_val(D[jj]);
-#pragma unroll
-            for (int j = 0; j < NP; ++j) bad |= !finite_val(J[jj][j]);
-        }
         const T *Mb = gM + I.onn;
         if (msh) {
             group_copy_in(Mb, n * n, msh, g);
@@ -240,15 +272,37 @@ struct SmallInst {
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
 #pragma unroll
-            for (int l = 0; l <= j; ++l) {
-                const T x = (j < n) ? Mb[j * n + l] : (j == l ? T(1) : T(0));
-                bad |= !finite_val(x);
-                Ml[Tri<NP>::idx(j, l)] = x;
-            }
+            for (int l = 0; l <= j; ++l)
+                Ml[Tri<NP>::idx(j, l)] = (j < n) ? Mb[j * n + l] : (j == l ? T(1) : T(0));
             a0[j] = j < n ? ga0[I.on + j] : T(0);
-            bad |= !finite_val(a0[j]);
         }
-        bad = gsum16(bad ? T(1) : T(0)) != T(0);
+    }
+
+    // The instance has a non-finite input (group-uniform).
+    __device__ inline void check() {
+        bool b = false;
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            b |= !finite_val(aref[jj]) || !finite_val(D[jj]);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) b |= !finite_val(J[jj][j]);
+        }
+#pragma unroll
+        for (int e = 0; e < Tri<NP>::NE; ++e) b |= !finite_val(Ml[e]);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) b |= !finite_val(a0[j]);
+        bad = gsum16(b ? T(1) : T(0)) != T(0);
+    }
+
+    __device__ inline void load(const Inst &I, int g, const T *__restrict__ gM,
+                                const T *__restrict__ gJ, const T *__restrict__ ga0,
+                                const T *__restrict__ garef, const T *__restrict__ gD,
+                                T *msh = nullptr) {
+        if (fast_ok(I, g, gJ, garef, gD))
+            load_fast(I, g, gM, gJ, ga0, garef, gD);
+        else
+            load_general(I, g, gM, gJ, ga0, garef, gD, msh);
+        check();
     }
 };
 
@@ -572,28 +626,47 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     __shared__ T sh[(256 / SG) * GroupShm<NP>::SIZE];
     T *gsh = sh + (threadIdx.x / SG) * GroupShm<NP>::SIZE;
     SmallInst<T, NP, R> S;
-    S.load(I, g, gM, gJ, ga0, garef, gD, gsh + GroupShm<NP>::M0);
     T L[NE], inv[NP], a[NP], ab[NP];
-    // the factor arrives through LDS: coalesced loads, then group broadcasts
-    const T *fac = gsh + GroupShm<NP>::F0;
-    group_copy_in(gfac + fac_offset(I), n * (n + 1) / 2, gsh + GroupShm<NP>::F0, g);
-    group_sync();
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-#pragma unroll
-        for (int l = 0; l <= j; ++l)
-            L[Tri<NP>::idx(j, l)] = (j < n) ? fac[Tri<NP>::idx(j, l)] : (j == l ? T(1) : T(0));
-        inv[j] = fast_rcp(L[Tri<NP>::idx(j, j)]);
-        a[j] = j < n ? ga[I.on + j] : T(0);
-        ab[j] = j < n ? gabar[I.on + j] : T(0);
-    }
-    const int live = m - S.i0;
     bool act[R];
-    {
+    if (S.fast_ok(I, g, gJ, garef, gD)) {
+        // every load of the instance issued before any use
+        const T *fp = gfac + fac_offset(I);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) L[e] = fp[e];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            a[j] = ga[I.on + j];
+            ab[j] = gabar[I.on + j];
+        }
+        const uint8_t *mk = gmask + I.om + g * R;
+        uint8_t mb[R];
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) mb[jj] = mk[jj];
+        S.load_fast(I, g, gM, gJ, ga0, garef, gD);
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) act[jj] = mb[jj] != 0;
+    } else {
+        S.load_general(I, g, gM, gJ, ga0, garef, gD, gsh + GroupShm<NP>::M0);
+        // the factor arrives through LDS: coalesced loads, then group broadcasts
+        const T *fac = gsh + GroupShm<NP>::F0;
+        group_copy_in(gfac + fac_offset(I), n * (n + 1) / 2, gsh + GroupShm<NP>::F0, g);
+        group_sync();
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+#pragma unroll
+            for (int l = 0; l <= j; ++l)
+                L[Tri<NP>::idx(j, l)] = (j < n) ? fac[Tri<NP>::idx(j, l)] : (j == l ? T(1) : T(0));
+            a[j] = j < n ? ga[I.on + j] : T(0);
+            ab[j] = j < n ? gabar[I.on + j] : T(0);
+        }
+        const int lv = m - S.i0;
         const uint8_t *mk = gmask + I.om + S.i0;
 #pragma unroll
-        for (int jj = 0; jj < R; ++jj) act[jj] = jj < live && mk[jj] != 0;
+        for (int jj = 0; jj < R; ++jj) act[jj] = jj < lv && mk[jj] != 0;
     }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) inv[j] = fast_rcp(L[Tri<NP>::idx(j, j)]);
+    const int live = m - S.i0;
     // lambda = H^{-1} abar, then one step of iterative refinement with
     // H v = M v + J^T (D o A* o J v)
     T lam[NP];
