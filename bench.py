@@ -8,7 +8,8 @@ synthetic inputs) that their working set exceeds twice the 256 MB last-level
 (MALL) cache.  Prints one JSON line.
 
 Also measured (reported inside the same line): the unrolled-trace gradient
-at the same K on the same GPU, the state/tape memory, the dominant kernel's
+at the same K on the same GPU (the library's fused trace kernels, and plain
+reverse-mode AD of the same solve by PyTorch autograd), the state/tape memory, the dominant kernel's
 roofline position from HIP events bracketing every launch in the timed
 region, and the FP64 oracle timed on the host cores on a bounded sample.
 """
@@ -157,6 +158,41 @@ def k_sweep(bufs, batch, steps=30):
         row["ift_over_unrolled"] = row["unrolled_ms"] / row["ift_ms"]
         out.append(row)
     return out
+
+
+def unrolled_ad(bufs, R, ift_value, reps=3):
+    """Plain unrolled reverse-mode AD of the same K-step solve: PyTorch autograd
+    through the batched tensor program (eager), on the same batches.  Time per
+    gradient of the whole batch, and the peak memory it holds at K=1 and K=10."""
+    import torch
+    from paper_2607_24959_amd import ad_unrolled
+
+    def call(t, K=K_CAP):
+        return ad_unrolled.vjp(t["M"].reshape(B, NV, NV), t["J"].reshape(B, M_ROWS, NV),
+                               t["a0"].reshape(B, NV), t["aref"].reshape(B, M_ROWS),
+                               t["D"].reshape(B, M_ROWS), t["abar"].reshape(B, NV), K=K, tol=TOL)
+
+    peaks = {}
+    for K in (1, K_CAP):
+        call(bufs[0][0], K)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        call(bufs[0][0], K)
+        torch.cuda.synchronize()
+        peaks[K] = torch.cuda.max_memory_allocated() - base
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        call(bufs[i % R][0])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    val = B / (ms / 1e3)
+    return {"what": "PyTorch autograd through the same batched K-step solve (eager tensor ops)",
+            "value": val, "unit": "solves/s", "K": K_CAP, "ms_per_step": ms,
+            "ift_over_unrolled_ad": ift_value / val,
+            "peak_bytes_K1": peaks[1], f"peak_bytes_K{K_CAP}": peaks[K_CAP]}
 
 
 def uneven(reps=20):
@@ -356,6 +392,7 @@ def main():
         u_val = B / (u_ms / 1e3)
         out["unrolled"] = {"value": u_val, "unit": "solves/s", "K": K_CAP, "ms_per_step": u_ms,
                            "ift_over_unrolled": value / u_val}
+        out["unrolled_ad"] = unrolled_ad(bufs, R, value)
 
     if not args.no_extra:
         out["k_sweep"] = k_sweep(bufs, batch)
