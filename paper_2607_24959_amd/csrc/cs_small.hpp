@@ -57,48 +57,49 @@ template <int NP> struct Tri {
 };
 
 // Cholesky of the packed lower triangle in registers; returns false when a
-// pivot is not positive.  inv[] receives 1 / L_jj.
+// pivot is not positive.  inv[] receives 1 / L_jj.  Right-looking: once
+// column j is scaled, every trailing entry takes its update independently, so
+// the dependency chain per column is pivot -> rsq -> scale -> next pivot.
 template <typename T, int NP>
 __device__ inline bool reg_cholesky(T (&H)[Tri<NP>::NE], T (&inv)[NP]) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        T s = H[Tri<NP>::idx(j, j)];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= H[Tri<NP>::idx(j, k)] * H[Tri<NP>::idx(j, k)];
+        const T s = H[Tri<NP>::idx(j, j)];
         ok = ok && (s > T(0));
         const T iv = fast_rsq(s);
         H[Tri<NP>::idx(j, j)] = s * iv;
         inv[j] = iv;
 #pragma unroll
-        for (int i = j + 1; i < NP; ++i) {
-            T t = H[Tri<NP>::idx(i, j)];
+        for (int i = j + 1; i < NP; ++i) H[Tri<NP>::idx(i, j)] *= iv;
 #pragma unroll
-            for (int k = 0; k < j; ++k) t -= H[Tri<NP>::idx(i, k)] * H[Tri<NP>::idx(j, k)];
-            H[Tri<NP>::idx(i, j)] = t * iv;
-        }
+        for (int i = j + 1; i < NP; ++i)
+#pragma unroll
+            for (int k = j + 1; k <= i; ++k)
+                H[Tri<NP>::idx(i, k)] -= H[Tri<NP>::idx(i, j)] * H[Tri<NP>::idx(k, j)];
     }
     return ok;
 }
 
-// x = (L L^T)^{-1} b
+// x = (L L^T)^{-1} b, both substitutions column-oriented: after each solved
+// component the remaining right-hand side entries update independently.
 template <typename T, int NP>
 __device__ inline void reg_chol_solve(const T (&L)[Tri<NP>::NE], const T (&inv)[NP], const T (&b)[NP],
                                       T (&x)[NP]) {
     T y[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        T s = b[j];
+    for (int j = 0; j < NP; ++j) y[j] = b[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s -= L[Tri<NP>::idx(j, k)] * y[k];
-        y[j] = s * inv[j];
+    for (int j = 0; j < NP; ++j) {
+        y[j] *= inv[j];
+#pragma unroll
+        for (int i = j + 1; i < NP; ++i) y[i] -= L[Tri<NP>::idx(i, j)] * y[j];
     }
 #pragma unroll
     for (int j = NP - 1; j >= 0; --j) {
-        T s = y[j];
+        x[j] = y[j] * inv[j];
 #pragma unroll
-        for (int k = j + 1; k < NP; ++k) s -= L[Tri<NP>::idx(k, j)] * x[k];
-        x[j] = s * inv[j];
+        for (int i = 0; i < j; ++i) y[i] -= L[Tri<NP>::idx(j, i)] * x[j];
     }
 }
 
@@ -316,8 +317,15 @@ struct StepTape {
 
 // Exact line search along p in registers (Sec. III-B, eq. 10); the method is
 // the safeguarded piece Newton of team_line_search in cs_device.hpp.  Returns
-// alpha; the accepted piece's rows (bits) and slope c are returned for the tape.
-template <typename T, int R>
+// alpha; when BITS, the accepted piece's rows (bits) and slope c are returned
+// for the tape.
+//
+// A Newton point is accepted when it lies on the piece that produced it.
+// With BITS that is checked row by row (one more group sum per round);
+// without, by the piece sums (c, b) coming out bitwise equal: equal row sets
+// give equal sums (same partials, same reduction order), and a different set
+// with equal sums has the same linear phi' there, whose root is the point.
+template <bool BITS, typename T, int R>
 __device__ inline T small_line_search(const T (&r)[R], const T (&q)[R], const T (&D)[R], T c0, T b0,
                                       uint32_t &bits_out, T &c_out, int &fail) {
     T dqq[R], dqr[R];
@@ -335,7 +343,7 @@ __device__ inline T small_line_search(const T (&r)[R], const T (&q)[R], const T 
             const bool pa = r[jj] + t * q[jj] < T(0);
             sc += pa ? dqq[jj] : T(0);
             sb += pa ? dqr[jj] : T(0);
-            bb |= (pa ? 1u : 0u) << jj;
+            if constexpr (BITS) bb |= (pa ? 1u : 0u) << jj;
         }
         c = c0 + gsum16(sc);
         b = b0 + gsum16(sb);
@@ -345,31 +353,31 @@ __device__ inline T small_line_search(const T (&r)[R], const T (&q)[R], const T 
     uint32_t bits;
     piece(t, bits, c, b);
     T lo = T(0), hi = inf_val<T>();
-    T alpha = t;
     fail = 1;
     const T eps = T(sizeof(T) == 4 ? 1.1920929e-7 : 2.220446049250313e-16);
     for (int it = 0; it < 96; ++it) {
         const T gp = c * t + b;
-        if (gp == T(0)) { alpha = t; fail = 0; break; }
+        if (gp == T(0)) { fail = 0; break; }
         if (gp < T(0)) lo = t; else hi = t;
-        if (hi < inf_val<T>() && hi - lo <= T(32) * eps * hi) { alpha = t; fail = 0; break; }
+        if (hi < inf_val<T>() && hi - lo <= T(32) * eps * hi) { fail = 0; break; }
         T cand = -b * fast_rcp(c);
         const bool newton = (cand > lo) && (cand < hi);
         if (!newton) cand = (hi < inf_val<T>()) ? T(0.5) * (lo + hi) : T(2) * lo + T(1);
         uint32_t nb;
         T nc, nbv;
         piece(cand, nb, nc, nbv);
-        const T mism = gsum16(T(__builtin_popcount(nb ^ bits)));
+        bool same;
+        if constexpr (BITS) same = gsum16(T(__builtin_popcount(nb ^ bits))) == T(0);
+        else same = (nc == c) && (nbv == b);
         bits = nb;
         c = nc;
         b = nbv;
         t = cand;
-        alpha = cand;
-        if (newton && mism == T(0)) { fail = 0; break; }
+        if (newton && same) { fail = 0; break; }
     }
     bits_out = bits;
     c_out = c;
-    return alpha;
+    return t;
 }
 
 // One Newton solve of the group's instance.  On return a holds the iterate,
@@ -459,7 +467,8 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
             if (!reg_cholesky<T, NP>(H, inv)) { st = ST_NOTSPD; break; }
             have_factor = true;
         }
-        if (sqrt(g2) <= tol * trM ||
+        const T gtol = tol * trM;
+        if (g2 <= gtol * gtol ||
             (step_inf >= T(0) && same && step_inf <= tol * (T(1) + anorm))) {
             st = ST_CONVERGED;
             break;
@@ -488,7 +497,7 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
         uint32_t bits;
         T cpiece;
         int fail;
-        const T alpha = small_line_search<T, R>(r, q, S.D, c0, b0, bits, cpiece, fail);
+        const T alpha = small_line_search<TAPE, T, R>(r, q, S.D, c0, b0, bits, cpiece, fail);
         lsfail |= fail;
         if constexpr (TAPE) {
             T *rec = tp.tT + (int64_t)k * tp.recT;
