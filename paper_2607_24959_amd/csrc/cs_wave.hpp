@@ -78,23 +78,19 @@ __device__ inline float wave_line_search(const float (&r)[RPL], const float (&q)
         dqq[t] = dq * q[t];
         dqr[t] = dq * r[t];
     }
-    auto piece = [&](float tr, uint32_t &bits, float &c, float &b) {
+    auto piece = [&](float tr, float &c, float &b) {
         float sc = 0.f, sb = 0.f;
-        uint32_t bb = 0;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const bool pa = r[t] + tr * q[t] < 0.f;
             sc += pa ? dqq[t] : 0.f;
             sb += pa ? dqr[t] : 0.f;
-            bb |= (pa ? 1u : 0u) << t;
         }
         c = c0 + wave_total(sc);
         b = b0 + wave_total(sb);
-        bits = bb;
     };
     float t = 1.f, c, b;
-    uint32_t bits;
-    piece(t, bits, c, b);
+    piece(t, c, b);
     float lo = 0.f, hi = __builtin_huge_valf(), alpha = t;
     fail = 1;
     const float eps = 1.1920929e-7f;
@@ -106,16 +102,17 @@ __device__ inline float wave_line_search(const float (&r)[RPL], const float (&q)
         float cand = -b / c;
         const bool newton = (cand > lo) && (cand < hi);
         if (!newton) cand = (hi < __builtin_huge_valf()) ? 0.5f * (lo + hi) : 2.f * lo + 1.f;
-        uint32_t nb;
         float nc, nbv;
-        piece(cand, nb, nc, nbv);
-        const float mism = wave_total((float)__builtin_popcount(nb ^ bits));
-        bits = nb;
+        piece(cand, nc, nbv);
+        // the piece is unchanged when its sums come out bitwise equal (same
+        // rows, same partials, same reduction order); a different row set
+        // with equal sums has the same linear phi' there, whose root is cand
+        const bool same = (nc == c) && (nbv == b);
         c = nc;
         b = nbv;
         t = cand;
         alpha = cand;
-        if (newton && mism == 0.f) { fail = 0; break; }
+        if (newton && same) { fail = 0; break; }
     }
     return alpha;
 }
@@ -194,8 +191,14 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         const bool anybad = __syncthreads_or(bad);
 
         // Cholesky of the rows h (lane i holds row i, entries c <= i), in
-        // place; idl gets 1 / L_ii.  Entries above the diagonal are updated
-        // too and never used.  False when a pivot is not positive.
+        // place; idl gets 1 / L_ii.  Right-looking with register broadcasts:
+        // after column j is scaled, its entries L_kj (lane k's h[j]) are read
+        // into scalar registers and every lane updates its row, so no LDS
+        // round trip or barrier sits on the per-column chain.  Columns are
+        // visited in blocks of 8 so a block wholly past n is skipped (a
+        // uniform branch); rows >= n are zero and stay zero.  Entries above
+        // the diagonal are updated too and never used.  False when a pivot
+        // is not positive.
         float idl = 1.f;
         auto factor = [&](float (&h)[NPA]) -> bool {
             bool ok = true;
@@ -207,12 +210,14 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                     const float inv = __builtin_amdgcn_rsqf(piv);
                     if (l == j) idl = inv;
                     h[j] = (l == j) ? piv * inv : h[j] * inv;
-                    if (l < NPA) Vs[l] = h[j];   // column j of L (rows >= n hold 0)
-                    __syncthreads();
-                    // rows >= n are zero, so their column entries are zero
 #pragma unroll
-                    for (int k2 = j + 1; k2 < NPA; ++k2) h[k2] -= h[j] * Vs[k2];
-                    __syncthreads();
+                    for (int kb = (j + 1) / 8; kb < NPA / 8; ++kb) {
+                        if (8 * kb < n) {
+#pragma unroll
+                            for (int k2 = 8 * kb; k2 < 8 * kb + 8; ++k2)
+                                if (k2 > j) h[k2] -= h[j] * wave_lane(h[j], k2);
+                        }
+                    }
                 }
             }
             return ok;

@@ -183,6 +183,12 @@ class Engine:
                          for _ in range(2)]
         self.list_evt = [None, None]
         self.ring = 0
+        # the kernel launches of one tick touch disjoint slots, so they run
+        # concurrently on side streams (default priority) between the
+        # tick's pre and post kernels on the caller's stream
+        self.side = [torch.cuda.Stream(device=dev) for _ in range(3)] if pin else []
+        self.ev_pre = torch.cuda.Event() if pin else None
+        self.ev_side = [torch.cuda.Event() for _ in self.side]
         self.params = N.CsSolverParams(int(max_iter), 0, float(tol))
         # host bookkeeping
         self.phase = np.full(S, -1, dtype=np.int64)   # -1 free; 0..W-1 forward; W..2W-1 backward
@@ -295,22 +301,36 @@ class Engine:
         N.check(N.serve_pre(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_pre")
         vp = solver._vp
         sol = self.sol
-        for kind, c, off, cnt in launches:
+        # longest launches first (forwards before VJPs, wider classes first),
+        # dealt round-robin over the caller's stream and the side streams
+        launches.sort(key=lambda L: (L[0] == "fwd", self.classes[L[1]][1], self.classes[L[1]][2]),
+                      reverse=True)
+        lanes = [stream] + (self.side if len(launches) > 1 else [])
+        lanes = lanes[:len(launches)]
+        if len(lanes) > 1:
+            self.ev_pre.record(stream)
+            for sd in lanes[1:]:
+                sd.wait_event(self.ev_pre)
+        for j, (kind, c, off, cnt) in enumerate(launches):
             path, nmax, mmax = self.classes[c]
             d = N.CsBatch()
             C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
             d.order, d.count, d.path = base + 4 * off, cnt, path
             d.nv_max, d.nrows_max = nmax, mmax
+            ls = C.c_void_p(lanes[j % len(lanes)].cuda_stream) if lanes else st
             if kind == "vjp":
                 rc = N.ift_vjp(d, vp(sol.state), sol.state.numel(), vp(self.M), vp(self.J),
                                vp(self.a0), vp(self.aref), vp(self.D), vp(sol.a), vp(self.abar),
-                               vp(self.a0bar), vp(self.arefbar), None, None, None, st)
+                               vp(self.a0bar), vp(self.arefbar), None, None, None, ls)
                 N.check(rc, "cs_ift_vjp(serve)")
             else:
                 rc = N.forward(d, self.params, vp(self.M), vp(self.J), vp(self.a0), vp(self.aref),
                                vp(self.D), None, vp(sol.a), vp(sol.state), sol.state.numel(),
-                               vp(sol.status), vp(sol.iters), st)
+                               vp(sol.status), vp(sol.iters), ls)
                 N.check(rc, "cs_forward(serve)")
+        for sd, ev in zip(lanes[1:], self.ev_side):
+            ev.record(sd)
+            stream.wait_event(ev)
         N.check(N.serve_post(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_post")
         self.phase[occ] += 1
         done = occ[self.phase[occ] == 2 * W]
