@@ -410,7 +410,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
         if (anybad) st = ST_NONFINITE;
         else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) st = ST_NOTSPD;
         ChAcc<T, NT> acc;
-        acc.init(sizeof(T) == 4 ? npa : n);
+        acc.init(sizeof(T) == 4 ? round16(n) : n);   // this instance's tiles, not the class's
         if (st == 0) {
             T trM = T(0);
             for (int j = 0; j < n; ++j) trM += M[(int64_t)j * n + j];

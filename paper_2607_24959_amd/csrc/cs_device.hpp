@@ -269,6 +269,21 @@ __device__ inline void chol_panel(double *H, int n, int ld, int c0, int c1, cons
     }
 }
 
+// The out-of-line team routines below work on the launching kernel's
+// dynamic LDS (every caller carves its LDS from that one region).  They take
+// element offsets into it rather than pointers: a pointer crossing a call
+// boundary loses its address space and every access would become a flat
+// access waiting on both memory counters; an offset rebuilt against the LDS
+// symbol keeps them ds_* instructions.
+template <typename T> __device__ inline T *lds_at(int off) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    return reinterpret_cast<T *>(smem) + off;
+}
+template <typename T> __device__ inline int lds_off(const T *p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    return (int)(p - reinterpret_cast<const T *>(smem));
+}
+
 template <typename T> __device__ inline T chol_rsq(T x);
 template <> __device__ inline float chol_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ inline double chol_rsq<double>(double x) { return 1.0 / sqrt(x); }
@@ -284,10 +299,13 @@ template <> __device__ inline double chol_rsq<double>(double x) { return 1.0 / s
 // has synchronised the team after writing H.  Returns false (team-uniform)
 // when a pivot is not positive.
 template <int NT, typename T>
-__device__ __attribute__((noinline)) bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
+__device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int n, int ld, int wko) {
     // sizes are team-uniform: keep them (and every branch on them) scalar
     n = __builtin_amdgcn_readfirstlane(n);
     ld = __builtin_amdgcn_readfirstlane(ld);
+    T *H = lds_at<T>(__builtin_amdgcn_readfirstlane(ho));
+    T *diag = lds_at<T>(__builtin_amdgcn_readfirstlane(dgo));
+    T *work = lds_at<T>(__builtin_amdgcn_readfirstlane(wko));
     bool ok = true;
     for (int c0 = 0; c0 < n; c0 += 16) {
         const int bs = min(16, n - c0);
@@ -362,10 +380,14 @@ __device__ __attribute__((noinline)) bool team_cholesky(T *H, T *diag, int n, in
 // updates one remaining entry with the block's 16 values; two barriers per
 // block and direction.  The caller has synchronised the team after writing b.
 template <int NT, typename T>
-__device__ __attribute__((noinline)) void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n,
-                                                         int ld) {
+__device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, int bo, int xo, int n,
+                                                             int ld) {
     n = __builtin_amdgcn_readfirstlane(n);
     ld = __builtin_amdgcn_readfirstlane(ld);
+    const T *L = lds_at<T>(__builtin_amdgcn_readfirstlane(lo));
+    const T *diag = lds_at<T>(__builtin_amdgcn_readfirstlane(dgo));
+    T *b = lds_at<T>(__builtin_amdgcn_readfirstlane(bo));
+    T *x = lds_at<T>(__builtin_amdgcn_readfirstlane(xo));
     // forward: L y = b, y stored in x
     for (int c0 = 0; c0 < n; c0 += 16) {
         const int bs = min(16, n - c0);
@@ -421,6 +443,15 @@ __device__ __attribute__((noinline)) void team_chol_solve(const T *L, const T *d
             __syncthreads();
         }
     }
+}
+// Pointer forms for the callers (all arguments point into the dynamic LDS).
+template <int NT, typename T>
+__device__ inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
+    return team_cholesky_lds<NT, T>(lds_off(H), lds_off(diag), n, ld, lds_off(work));
+}
+template <int NT, typename T>
+__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
+    team_chol_solve_lds<NT, T>(lds_off(L), lds_off(diag), lds_off(b), lds_off(x), n, ld);
 }
 template <int NT, typename T>
 __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
