@@ -256,11 +256,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--no-ad", action="store_true", help="skip the plain unrolled-AD comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the K sweep, the uneven batch and the serving streams")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
+    ap.add_argument("--section", choices=("uneven", "serving"),
+                    help="only run this workload (for profiling) and print its JSON")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
+    rates = tuple(int(x) for x in args.serve_rates.split(","))
+    if args.section == "uneven":
+        print(json.dumps(uneven(reps=5)), flush=True)
+        return
+    if args.section == "serving":
+        print(json.dumps(serving(rates, n_requests=args.serve_requests,
+                                 warmup=max(1, args.serve_requests // 10))), flush=True)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * 2 ** 20 // 4
@@ -392,12 +405,14 @@ def main():
         u_val = B / (u_ms / 1e3)
         out["unrolled"] = {"value": u_val, "unit": "solves/s", "K": K_CAP, "ms_per_step": u_ms,
                            "ift_over_unrolled": value / u_val}
-        out["unrolled_ad"] = unrolled_ad(bufs, R, value)
+        if not args.no_ad:
+            out["unrolled_ad"] = unrolled_ad(bufs, R, value)
 
     if not args.no_extra:
         out["k_sweep"] = k_sweep(bufs, batch)
         out["uneven"] = uneven()
-        out["serving"] = serving()
+        out["serving"] = serving(rates, n_requests=args.serve_requests,
+                                 warmup=max(1, args.serve_requests // 10))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host[0])
     print(json.dumps(out), flush=True)
