@@ -356,6 +356,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "timing": {"wall_ms": wall * 1e3, "gpu_ms": gpu_ms,
+                   "kernel_sum_ms": float(np.sum(t_fwd) + np.sum(t_vjp))},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

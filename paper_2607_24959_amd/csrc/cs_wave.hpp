@@ -16,6 +16,8 @@
 // team one with 64 threads (rows from LDS, wave reductions only).
 #pragma once
 
+#include <type_traits>
+
 #include "cs_device.hpp"
 
 namespace cs {
@@ -24,11 +26,11 @@ namespace cs {
 __host__ __device__ inline int wave_npa(int n) { return (n + 1 + 15) & ~15; }
 __host__ __device__ inline int wave_rows(int m) { return m < 64 ? 64 : (m + 63) & ~63; }
 
-// LDS: J (mp x (NPA + 1)), H (NPA x (NPA + 1)), the row weights of the
-// matrix-core pass, two NPA vectors.
+// LDS: J (mp x (NPA + 1)), H (NPA x (NPA + 1)), the weights of the active
+// rows (compacted), two NPA vectors, the indices of the active rows.
 __host__ __device__ inline size_t wave_lds_bytes(int npa, int mmax) {
     const size_t ld = (size_t)npa + 1, mp = (size_t)wave_rows(mmax);
-    return (mp * ld + (size_t)npa * ld + mp + 2 * (size_t)npa) * sizeof(float);
+    return (mp * ld + (size_t)npa * ld + mp + 2 * (size_t)npa + mp) * sizeof(float);
 }
 
 // Rows per lane for up to mmax rows.
@@ -38,6 +40,15 @@ inline int wave_rpl(int mmax) {
 }
 
 typedef float wf4 __attribute__((ext_vector_type(4)));
+
+// The lane index as a value the compiler cannot treat as loop-invariant.
+// Lane masks such as (l == j) for every compile-time j would otherwise be
+// hoisted out of the Newton loop and held in scalar register pairs, more of
+// them than the scalar file holds (they then spill through vector lanes).
+__device__ inline int opaque_lane(int l) {
+    asm volatile("" : "+v"(l));
+    return l;
+}
 
 // Value of v in lane k (k a compile-time or wave-uniform index).
 __device__ inline float wave_lane(float v, int k) {
@@ -134,6 +145,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
     float *Hs = Js + (size_t)mp * LD;
     float *Wc = Hs + NPA * LD;
     float *Fs = Wc + mp, *Vs = Fs + NPA;
+    int *Lr = reinterpret_cast<int *>(Vs + NPA);    // active rows, compacted
     const int l = threadIdx.x;
     const int kq = l >> 4, idx = l & 15;
 
@@ -194,33 +206,40 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         // place; idl gets 1 / L_ii.  Right-looking with register broadcasts:
         // after column j is scaled, its entries L_kj (lane k's h[j]) are read
         // into scalar registers and every lane updates its row, so no LDS
-        // round trip or barrier sits on the per-column chain.  Columns are
-        // visited in blocks of 8 so a block wholly past n is skipped (a
-        // uniform branch); rows >= n are zero and stay zero.  Entries above
-        // the diagonal are updated too and never used.  False when a pivot
-        // is not positive.
+        // round trip or barrier sits on the per-column chain.  Branch-free
+        // over all NPA columns (a branch that changes h[] makes the compiler
+        // copy the whole row at its join): columns past n get pivot 1 and,
+        // their rows and columns being zero, factor as the identity.  Entries
+        // above the diagonal are updated too and never used or broadcast.
+        // False when a pivot of the first n columns is not positive.
+        // The column count NC >= n is a compile-time 16, 24 or 32, chosen
+        // per instance, so an n = 18 instance does not pay for 32 columns.
         float idl = 1.f;
-        auto factor = [&](float (&h)[NPA]) -> bool {
+        auto factor_nc = [&](auto ncc, float (&h)[NPA]) -> bool {
+            constexpr int NC = decltype(ncc)::value;
             bool ok = true;
 #pragma unroll
-            for (int j = 0; j < NPA; ++j) {
-                if (j < n) {
-                    const float piv = wave_lane(h[j], j);
-                    ok = ok && (piv > 0.f);
-                    const float inv = __builtin_amdgcn_rsqf(piv);
-                    if (l == j) idl = inv;
-                    h[j] = (l == j) ? piv * inv : h[j] * inv;
+            for (int j = 0; j < NC; ++j) {
+                const bool live = j < n;
+                const float piv = live ? wave_lane(h[j], j) : 1.f;
+                ok = ok && (!live || piv > 0.f);
+                const float inv = __builtin_amdgcn_rsqf(piv);
+                // lane j's h[j] is the pivot itself, so this gives L_jj there
+                idl = (opaque_lane(l) == j) ? inv : idl;
+                h[j] *= inv;
 #pragma unroll
-                    for (int kb = (j + 1) / 8; kb < NPA / 8; ++kb) {
-                        if (8 * kb < n) {
-#pragma unroll
-                            for (int k2 = 8 * kb; k2 < 8 * kb + 8; ++k2)
-                                if (k2 > j) h[k2] -= h[j] * wave_lane(h[j], k2);
-                        }
-                    }
-                }
+                for (int k2 = j + 1; k2 < NC; ++k2) h[k2] -= h[j] * wave_lane(h[j], k2);
             }
             return ok;
+        };
+        auto factor = [&](float (&h)[NPA]) -> bool {
+            if constexpr (NPA == 16) {
+                return factor_nc(std::integral_constant<int, 16>{}, h);
+            } else {
+                if (n <= 16) return factor_nc(std::integral_constant<int, 16>{}, h);
+                if (n <= 24) return factor_nc(std::integral_constant<int, 24>{}, h);
+                return factor_nc(std::integral_constant<int, 32>{}, h);
+            }
         };
 
         int st = 0, k = 0;
@@ -255,6 +274,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 #pragma unroll
                 for (int c = 0; c < NPA; ++c) av[c] = wave_lane(aj, c);
                 uint32_t nact = 0;
+                int cnt = 0;    // active rows so far (wave-uniform)
 #pragma unroll
                 for (int t = 0; t < RPL; ++t) {
                     const int i = l + 64 * t;
@@ -268,30 +288,47 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                     rr[t] = (i < m) ? s0 + s1 - ar[t] : 0.f;
                     const bool an = rr[t] < 0.f && i < m;
                     nact |= (an ? 1u : 0u) << t;
-                    if (i < m) {
-                        Js[i * LD + n] = rr[t];
-                        Wc[i] = an ? Dr[t] : 0.f;
+                    if (i < m) Js[i * LD + n] = rr[t];
+                    // the active rows and their weights, compacted in row order
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64(an);
+                    if (an) {
+                        const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        Lr[pos] = i;
+                        Wc[pos] = Dr[t];
                     }
+                    cnt += (int)__builtin_popcountll(bal);
+                }
+                // pad the list to whole K-steps with zero weights on row 0
+                const int cnt4 = (cnt + 3) & ~3;
+                if (l < cnt4 - cnt) {
+                    Lr[cnt + l] = 0;
+                    Wc[cnt + l] = 0.f;
                 }
                 const bool same = !__syncthreads_or(nact != act);
                 act = nact;
-                // lower triangle of [J | r]^T diag(Wc) [J | r] on the matrix
-                // cores; the next K-step's operands load while this one runs
+                // lower triangle of [J | r]^T diag(D o A) [J | r] over the
+                // active rows on the matrix cores; the next K-step's operands
+                // (and the row index after it) load while this one runs
                 wf4 acc[NTL];
 #pragma unroll
                 for (int t = 0; t < NTL; ++t) acc[t] = wf4{0.f, 0.f, 0.f, 0.f};
-                const int nks = m4 / 4;
+                const int nks = cnt4 / 4;
                 if (nks > 0) {
                     float wr = Wc[kq];
                     float cb[NB];
+                    {
+                        const int r0 = Lr[kq];
 #pragma unroll
-                    for (int bb = 0; bb < NB; ++bb) cb[bb] = Js[kq * LD + idx + 16 * bb];
+                        for (int bb = 0; bb < NB; ++bb) cb[bb] = Js[r0 * LD + idx + 16 * bb];
+                    }
+                    int rnext = Lr[4 * min(1, nks - 1) + kq];
                     for (int ks = 0; ks < nks; ++ks) {
-                        const int nrow = 4 * min(ks + 1, nks - 1) + kq;
-                        const float wn = Wc[nrow];
+                        const float wn = Wc[4 * min(ks + 1, nks - 1) + kq];
                         float cn[NB];
 #pragma unroll
-                        for (int bb = 0; bb < NB; ++bb) cn[bb] = Js[nrow * LD + idx + 16 * bb];
+                        for (int bb = 0; bb < NB; ++bb) cn[bb] = Js[rnext * LD + idx + 16 * bb];
+                        rnext = Lr[4 * min(ks + 2, nks - 1) + kq];
 #pragma unroll
                         for (int ti = 0, t = 0; ti < NB; ++ti)
 #pragma unroll
@@ -319,7 +356,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 if (!(same && have_factor)) {
 #pragma unroll
                     for (int c = 0; c < NPA; ++c)
-                        h[c] = (l < n && c <= l) ? Hs[l * LD + c] + Mrow[c] : 0.f;
+                        h[c] = Hs[min(l, NPA - 1) * LD + c] + Mrow[c];
                     if (!factor(h)) { st = ST_NOTSPD; break; }
                     have_factor = true;
                 }
@@ -335,13 +372,14 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 for (int j = 0; j < NPA; ++j) {
                     if (j < n) {
                         const float yj = wave_lane(y * idl, j);
-                        y = (l == j) ? yj : ((l > j) ? y - h[j] * yj : y);
+                        const int lo = opaque_lane(l);
+                        y = (lo == j) ? yj : ((lo > j) ? y - h[j] * yj : y);
                     }
                 }
                 // L rows to LDS for the transposed solve
 #pragma unroll
                 for (int c = 0; c < NPA; ++c)
-                    if (l < n && c <= l) Hs[l * LD + c] = h[c];
+                    if (l < NPA) Hs[l * LD + c] = h[c];
                 __syncthreads();
                 float pj = y;
 #pragma unroll
@@ -349,7 +387,8 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                     if (j < n) {
                         const float xj = wave_lane(pj * idl, j);
                         const float lji = Hs[j * LD + (l < n ? l : 0)];
-                        pj = (l == j) ? xj : ((l < j) ? pj - lji * xj : pj);
+                        const int lo = opaque_lane(l);
+                        pj = (lo == j) ? xj : ((lo < j) ? pj - lji * xj : pj);
                     }
                 }
                 if (l >= n) pj = 0.f;
@@ -390,7 +429,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         // factor: lane i's row of L (diagonal included) through LDS
 #pragma unroll
         for (int c = 0; c < NPA; ++c)
-            if (l < n && c <= l) Hs[l * LD + c] = h[c];
+            if (l < NPA) Hs[l * LD + c] = h[c];
         __syncthreads();
         {
             float *fac = gfac + fac_offset(I);
