@@ -159,22 +159,29 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         // rows m .. m4-1 start at zero, so row products run over all NPA
         // columns (a and p are zero past n)
         {
+            // eight coalesced loads in flight per lane (clamped indices, no
+            // predicates), then the LDS stores along the (row, column) walk
+            const int tot = m * n;
             int rr = l / n, cc = l - (l / n) * n;
             const int dr = 64 / n, dc = 64 - dr * n;
-            for (int e = l; e < m * n; e += 64) {
-                const float x = J[e];
-                Js[rr * LD + cc] = x;
-                bad |= !finite_val(x);
-                rr += dr;
-                cc += dc;
-                if (cc >= n) { cc -= n; ++rr; }
+            for (int e0 = 0; e0 < tot; e0 += 64 * 8) {
+                float x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = J[min(e0 + l + 64 * u, tot - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (e0 + l + 64 * u < tot) {
+                        Js[rr * LD + cc] = x[u];
+                        bad |= !finite_val(x[u]);
+                    }
+                    rr += dr;
+                    cc += dc;
+                    if (cc >= n) { cc -= n; ++rr; }
+                }
             }
             for (int e = l; e < (m4 - m) * LD; e += 64) Js[m * LD + e] = 0.f;
-            const int pad = NPA - n;
-            for (int e = l; e < m * pad; e += 64) {
-                const int i = e / pad;
-                Js[i * LD + n + (e - i * pad)] = 0.f;
-            }
+            for (int i = l; i < m; i += 64)
+                for (int c = n; c < NPA; ++c) Js[i * LD + c] = 0.f;
         }
         // the lane's rows l + 64 t: D and aref in registers (zero past m)
         float Dr[RPL], ar[RPL];
@@ -202,19 +209,19 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         }
         const bool anybad = __syncthreads_or(bad);
 
-        // Cholesky of the rows h (lane i holds row i, entries c <= i), in
-        // place; idl gets 1 / L_ii.  Right-looking with register broadcasts:
-        // after column j is scaled, its entries L_kj (lane k's h[j]) are read
-        // into scalar registers and every lane updates its row, so no LDS
-        // round trip or barrier sits on the per-column chain.  Branch-free
-        // over all NPA columns (a branch that changes h[] makes the compiler
-        // copy the whole row at its join): columns past n get pivot 1 and,
-        // their rows and columns being zero, factor as the identity.  Entries
-        // above the diagonal are updated too and never used or broadcast.
-        // False when a pivot of the first n columns is not positive.
-        // The column count NC >= n is a compile-time 16, 24 or 32, chosen
-        // per instance, so an n = 18 instance does not pay for 32 columns.
-        float idl = 1.f;
+        // Cholesky of the rows h (lane i holds row i), in place, ending
+        // strictly lower: the diagonal L_ii goes to dl and 1 / L_ii to idl,
+        // and the diagonal and everything right of it are cleared at the
+        // end.  Right-looking with register broadcasts: after
+        // column j is scaled, its entries L_kj (lane k's h[j]) are read into
+        // scalar registers and every lane updates its row, with no LDS round
+        // trip or barrier on the per-column chain.  Branch-free over NC
+        // columns (a branch that changes h[] makes the compiler copy the
+        // whole row at its join); NC >= n is a compile-time 16, 24 or 32
+        // chosen per instance, and columns n .. NC-1 (zero rows and columns)
+        // take pivot 1.  False when a pivot of the first n columns is not
+        // positive.
+        float idl = 1.f, dl = 1.f;
         auto factor_nc = [&](auto ncc, float (&h)[NPA]) -> bool {
             constexpr int NC = decltype(ncc)::value;
             bool ok = true;
@@ -224,22 +231,40 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 const float piv = live ? wave_lane(h[j], j) : 1.f;
                 ok = ok && (!live || piv > 0.f);
                 const float inv = __builtin_amdgcn_rsqf(piv);
-                // lane j's h[j] is the pivot itself, so this gives L_jj there
-                idl = (opaque_lane(l) == j) ? inv : idl;
-                h[j] *= inv;
+                const bool me = opaque_lane(l) == j;
+                idl = me ? inv : idl;
+                dl = me ? piv * inv : dl;
+                h[j] *= inv;    // lane j: the pivot times 1 / sqrt(pivot)
 #pragma unroll
                 for (int k2 = j + 1; k2 < NC; ++k2) h[k2] -= h[j] * wave_lane(h[j], k2);
             }
+            // the updates also reach entries right of each lane's diagonal
+            // (never read above); clear them and the diagonal, once
+            const int lo = opaque_lane(l);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) h[c] = (c < lo) ? h[c] : 0.f;
             return ok;
         };
-        auto factor = [&](float (&h)[NPA]) -> bool {
+        // Calls f with the compile-time column count for this instance.
+        auto with_nc = [&](auto f) {
             if constexpr (NPA == 16) {
-                return factor_nc(std::integral_constant<int, 16>{}, h);
+                return f(std::integral_constant<int, 16>{});
             } else {
-                if (n <= 16) return factor_nc(std::integral_constant<int, 16>{}, h);
-                if (n <= 24) return factor_nc(std::integral_constant<int, 24>{}, h);
-                return factor_nc(std::integral_constant<int, 32>{}, h);
+                if (n <= 16) return f(std::integral_constant<int, 16>{});
+                if (n <= 24) return f(std::integral_constant<int, 24>{});
+                return f(std::integral_constant<int, 32>{});
             }
+        };
+        auto factor = [&](float (&h)[NPA]) -> bool {
+            return with_nc([&](auto ncc) { return factor_nc(ncc, h); });
+        };
+        // the lane's row of `src`, lower triangle and diagonal (zero elsewhere
+        // and in lanes >= n), as the starting h of a factorisation
+        auto lower_row = [&](float (&h)[NPA], auto &&src) {
+            const int lo = opaque_lane(l);
+            const bool rowok = lo < n;
+#pragma unroll
+            for (int c = 0; c < NPA; ++c) h[c] = (rowok && c <= lo) ? src(c) : 0.f;
         };
 
         int st = 0, k = 0;
@@ -248,8 +273,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         if (anybad) {
             st = ST_NONFINITE;
         } else {
-#pragma unroll
-            for (int c = 0; c < NPA; ++c) h[c] = Mrow[c];
+            lower_row(h, [&](int c) { return Mrow[c]; });
             if (!factor(h)) st = ST_NOTSPD;
         }
         if (st == 0) {
@@ -354,9 +378,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 const float Fj = (l < n) ? Md + Fs[l] : 0.f;
                 const float g2 = wave_total(Fj * Fj), an = wave_maximum(fabsf(aj));
                 if (!(same && have_factor)) {
-#pragma unroll
-                    for (int c = 0; c < NPA; ++c)
-                        h[c] = Hs[min(l, NPA - 1) * LD + c] + Mrow[c];
+                    lower_row(h, [&](int c) { return Hs[min(l, NPA - 1) * LD + c] + Mrow[c]; });
                     if (!factor(h)) { st = ST_NOTSPD; break; }
                     have_factor = true;
                 }
@@ -367,31 +389,32 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 }
                 if (k == max_iter) { st = ST_MAXITER; break; }
                 // p = -H^{-1} F: forward L y = -F (y in lane j), then L^T p = y
-                float y = -Fj;
+                // (h strictly lower, diagonal in dl / idl: every lane applies
+                // every column update, no selects; lane j's value is final
+                // once column j is reached and is scaled by 1 / L_jj at the end)
+                float y = -Fj;          // zero in lanes >= n
+                with_nc([&](auto ncc) {
+                    constexpr int NC = decltype(ncc)::value;
 #pragma unroll
-                for (int j = 0; j < NPA; ++j) {
-                    if (j < n) {
-                        const float yj = wave_lane(y * idl, j);
-                        const int lo = opaque_lane(l);
-                        y = (lo == j) ? yj : ((lo > j) ? y - h[j] * yj : y);
-                    }
+                    for (int j = 0; j < NC; ++j) y -= h[j] * wave_lane(y * idl, j);
+                    return 0;
+                });
+                y *= idl;
+                // strictly lower rows of L to LDS for the transposed solve
+                if (l < NPA) {
+#pragma unroll
+                    for (int c = 0; c < NPA; ++c) Hs[l * LD + c] = h[c];
                 }
-                // L rows to LDS for the transposed solve
-#pragma unroll
-                for (int c = 0; c < NPA; ++c)
-                    if (l < NPA) Hs[l * LD + c] = h[c];
                 __syncthreads();
                 float pj = y;
+                with_nc([&](auto ncc) {
+                    constexpr int NC = decltype(ncc)::value;
+                    const float *col = Hs + min(l, NPA - 1);    // L_jl at col[j * LD]
 #pragma unroll
-                for (int j = NPA - 1; j >= 0; --j) {
-                    if (j < n) {
-                        const float xj = wave_lane(pj * idl, j);
-                        const float lji = Hs[j * LD + (l < n ? l : 0)];
-                        const int lo = opaque_lane(l);
-                        pj = (lo == j) ? xj : ((lo < j) ? pj - lji * xj : pj);
-                    }
-                }
-                if (l >= n) pj = 0.f;
+                    for (int j = NC - 1; j >= 0; --j) pj -= col[j * LD] * wave_lane(pj * idl, j);
+                    return 0;
+                });
+                pj = (l < n) ? pj * idl : 0.f;
                 // q = J p for the lane's rows; M p and the line-search coefficients
                 float pv[NPA];
 #pragma unroll
@@ -426,10 +449,13 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
         const float nanv = __builtin_nanf("");
         if (l < n) gaout[I.on + l] = ok ? aj : nanv;
-        // factor: lane i's row of L (diagonal included) through LDS
+        // factor: lane i's row of L (strictly lower part, then the diagonal)
+        // through LDS
+        if (l < NPA) {
 #pragma unroll
-        for (int c = 0; c < NPA; ++c)
-            if (l < NPA) Hs[l * LD + c] = h[c];
+            for (int c = 0; c < NPA; ++c) Hs[l * LD + c] = h[c];
+            Hs[l * LD + l] = dl;
+        }
         __syncthreads();
         {
             float *fac = gfac + fac_offset(I);
