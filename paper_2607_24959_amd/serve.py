@@ -28,6 +28,7 @@ compile-time sizes), so a request's result is the same alone and in any mix.
 from __future__ import annotations
 
 import ctypes as C
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass
@@ -367,6 +368,11 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     pending = deque(reqs)
     engine.finished.clear()
     stream = torch.cuda.current_stream(engine.device)
+    # the loop allocates an event per tick; a cyclic-GC pass over the
+    # growing heap would stall the host for milliseconds mid-stream
+    gc_was_enabled = gc.isenabled()
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     start.record(stream)
@@ -388,6 +394,8 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
             tick_events.append(ev)
             solves += n_work
     torch.cuda.synchronize()
+    if gc_was_enabled:
+        gc.enable()
     t_end = [start.elapsed_time(e) / 1e3 for e in tick_events]     # seconds since start
     for r in engine.finished:
         r.done = t_end[r.done_tick - t_first]
