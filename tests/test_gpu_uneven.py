@@ -192,6 +192,27 @@ def test_wave_family_mixed_fp32():
     assert np.median(errs) <= 1e-5
 
 
+def test_wave_family_size_boundaries_fp32():
+    """One-wave family at the edges of its compile-time sizes: n in {1, 2, 15,
+    16, 17, 23, 24, 25, 30, 31} (Cholesky column counts 16 / 24 / 32, padded
+    widths 16 / 32) with 0, 1, 16, 17 and 256 contacts (0, 4, 64, 68, 1024 rows:
+    empty, one K-step, exactly one and just over one row group, the maximum)."""
+    _needs_gpu()
+    shapes = [(n, nc) for n in (1, 2, 15, 16, 17, 23, 24, 25, 30, 31) for nc in (0, 1, 16, 17, 256)]
+    pb = synth.pack([synth.instance(4242, i, n, nc) for i, (n, nc) in enumerate(shapes)])
+    p32, p64 = pb.astype(np.float32), pb.rounded(np.float32)
+    batch = solver.Batch.packed_from(pb.nv, pb.nrows, torch.float32, path=N.PATH_WAVE)
+    t = _dev(p32, torch.float32)
+    sol = solver.forward(batch, *(t[k] for k in KEYS[:5]), max_iter=60, tol=1e-5)
+    grads = solver.ift_vjp(batch, sol, *(t[k] for k in KEYS[:5]), t["abar"])
+    torch.cuda.synchronize()
+    assert np.all(sol.status.cpu().numpy() & (N.ST_NONFINITE | N.ST_NOTSPD) == 0)
+    n_checked, bad, worst = _check_sample(pb, p64, sol, grads, range(pb.B), 60, 1e-4, 1e-3,
+                                          "wave boundaries fp32")
+    assert n_checked >= 0.8 * pb.B
+    assert len(bad) <= 2, bad
+
+
 def test_wave_family_rejects_fp64_and_large_n():
     _needs_gpu()
     for dtype, n, m in ((torch.float64, 9, 8), (torch.float32, 36, 8), (torch.float32, 9, 1028)):
