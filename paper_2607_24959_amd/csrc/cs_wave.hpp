@@ -230,19 +230,24 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 const bool live = j < n;
                 const float piv = live ? wave_lane(h[j], j) : 1.f;
                 ok = ok && (!live || piv > 0.f);
-                const float inv = __builtin_amdgcn_rsqf(piv);
-                const bool me = opaque_lane(l) == j;
-                idl = me ? inv : idl;
-                dl = me ? piv * inv : dl;
-                h[j] *= inv;    // lane j: the pivot times 1 / sqrt(pivot)
+                // lane j: the pivot times 1 / sqrt(pivot) = L_jj, final from here
+                h[j] *= __builtin_amdgcn_rsqf(piv);
 #pragma unroll
                 for (int k2 = j + 1; k2 < NC; ++k2) h[k2] -= h[j] * wave_lane(h[j], k2);
             }
-            // the updates also reach entries right of each lane's diagonal
-            // (never read above); clear them and the diagonal, once
+            // lane l's diagonal is h[l]; the updates also reached entries right
+            // of it (never read above).  One pass picks the diagonal and clears
+            // the diagonal and everything right of it (no per-column lane
+            // masks, so the column loop is one scheduling region).
             const int lo = opaque_lane(l);
+            float d = 1.f;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) h[c] = (c < lo) ? h[c] : 0.f;
+            for (int c = 0; c < NC; ++c) {
+                d = (c == lo) ? h[c] : d;
+                h[c] = (c < lo) ? h[c] : 0.f;
+            }
+            dl = (lo < n) ? d : 1.f;    // rows past n are zero: identity there
+            idl = __builtin_amdgcn_rcpf(dl);
             return ok;
         };
         // Calls f with the compile-time column count for this instance.
