@@ -417,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
             // u = M (a - a0), kept up to date across steps
             for (int j = tid; j < n; j += NT) {
                 T s = T(0);
-#pragma unroll 4
+#pragma unroll 16
                 for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * (L.a[l] - L.a0[l]);
                 L.u[j] = s;
             }
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 T c0 = T(0), b0 = T(0);
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0);
-#pragma unroll 4
+#pragma unroll 16
                     for (int l = 0; l < n; ++l) mp += M[(int64_t)l * n + j] * L.p[l];
                     L.v[j] = mp;
                     c0 += L.p[j] * mp;
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
         cs.finish(n, ldj, L.Jc, nullptr, L.F);
         for (int j = tid; j < n; j += NT) {
             T s = gabar[I.on + j] - L.F[j];
-#pragma unroll 4
+#pragma unroll 16
             for (int l = 0; l < n; ++l) s -= M[(int64_t)l * n + j] * L.u[l];
             L.y[j] = s;
         }
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
         if (ga0bar) {
             for (int j = tid; j < n; j += NT) {
                 T s = T(0);
-#pragma unroll 4
+#pragma unroll 16
                 for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * L.u[l];
                 ga0bar[I.on + j] = s;
             }

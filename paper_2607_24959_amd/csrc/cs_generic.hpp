@@ -81,7 +81,7 @@ __device__ inline void gen_gradient(int n, int m, const T *__restrict__ M, const
                                     const GenLds<T> &L) {
     for (int j = threadIdx.x; j < n; j += NT) {
         T f = T(0);
-#pragma unroll 4
+#pragma unroll 16
         for (int l = 0; l < n; ++l) f += M[(size_t)l * n + j] * (L.a[l] - L.a0[l]);
         for (int i = 0; i < m; ++i)
             if (L.A[i]) f += J[(size_t)i * n + j] * (L.Dv[i] * L.r[i]);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
                 }
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0), md = T(0);
-#pragma unroll 4
+#pragma unroll 16
                     for (int l = 0; l < n; ++l) {
                         const T mlj = M[(size_t)l * n + j];   // = M[j][l]: M is symmetric
                         mp += mlj * L.p[l];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
         __syncthreads();
         for (int j = tid; j < n; j += NT) {
             T s = gabar[I.on + j];
-#pragma unroll 4
+#pragma unroll 16
             for (int l = 0; l < n; ++l) s -= M[(size_t)l * n + j] * L.u[l];
             for (int i = 0; i < m; ++i) s -= J[(size_t)i * n + j] * L.q[i];
             L.y[j] = s;
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 }
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0), md = T(0);
-#pragma unroll 4
+#pragma unroll 16
                     for (int l = 0; l < n; ++l) {
                         const T mlj = M[(size_t)l * n + j];   // = M[j][l]: M is symmetric
                         mp += mlj * L.p[l];
