@@ -287,6 +287,18 @@ template <typename T> __device__ inline int lds_off(const T *p) {
 template <typename T> __device__ inline T chol_rsq(T x);
 template <> __device__ inline float chol_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ inline double chol_rsq<double>(double x) { return 1.0 / sqrt(x); }
+template <typename T> __device__ inline T chol_rcp(T x);
+template <> __device__ inline float chol_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double chol_rcp<double>(double x) { return 1.0 / x; }
+
+// The lane index as a value the compiler cannot treat as loop-invariant.
+// Lane masks such as (l == j) for every compile-time j would otherwise be
+// hoisted out of loops and held in scalar register pairs, more of them than
+// the scalar file holds (they then spill through vector lanes).
+__device__ inline int opaque_lane(int l) {
+    asm volatile("" : "+v"(l));
+    return l;
+}
 
 // In-place Cholesky H = L L^T of the n x n row-major matrix in LDS (row
 // stride ld): the lower triangle is read, L is written strictly below the
@@ -321,23 +333,24 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
                 const T x = hr[min(k, bs - 1)];
                 d[k] = (l < bs && k <= l) ? x : T(0);
             }
-            // Branch-free: lanes also update entries above their diagonal
-            // (never stored); every stored entry only reads entries below
-            // or on the diagonal of other rows.
-            T dl = T(1);   // this lane's L_ll
+            // Branch-free over the 16 columns: lanes also update entries
+            // above their diagonal (never stored; every stored entry only
+            // reads entries below or on the diagonal of other rows), and
+            // columns past bs (zero rows and columns) take pivot 1.  A branch
+            // that changes d[] would make the compiler copy the row at its
+            // join.  Lane j's own d[j] is the pivot, so scaling gives L_jj.
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                if (j < bs) {
-                    const T piv = lane_bcast(d[j], j);
-                    const T iv = chol_rsq(piv);
-                    const T djs = d[j] * iv;
-                    dl = (l == j) ? piv * iv : dl;
-                    d[j] = (l == j) ? piv * iv : djs;
+                const T piv = (j < bs) ? lane_bcast(d[j], j) : T(1);
+                d[j] *= chol_rsq(piv);
 #pragma unroll
-                    for (int k = j + 1; k < 16; ++k) {
-                        if (k < bs) d[k] -= djs * lane_bcast(djs, k);
-                    }
-                }
+                for (int k = j + 1; k < 16; ++k) d[k] -= d[j] * lane_bcast(d[j], k);
+            }
+            T dl = d[0];   // this lane's L_ll, picked in one pass
+            {
+                const int lo = opaque_lane(l);
+#pragma unroll
+                for (int k = 1; k < 16; ++k) dl = (k == lo) ? d[k] : dl;
             }
             // column l of X = L_D^{-1}: x_c = 0 (c < l), x_l = 1 / L_ll,
             // x_c = -(sum_{k<c} L_ck x_k) / L_cc (c > l)
@@ -347,7 +360,7 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
                 T acc = T(0);
 #pragma unroll
                 for (int k = 0; k < c; ++k) acc += lane_bcast(d[k], c) * x[k];
-                const T rc = T(1) / lane_bcast(d[c], c);
+                const T rc = chol_rcp(lane_bcast(d[c], c));
                 const T xc = (c == l) ? rc : -acc * rc;
                 x[c] = (c < l || c >= bs) ? T(0) : xc;
             }

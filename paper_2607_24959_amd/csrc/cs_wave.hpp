@@ -41,14 +41,6 @@ inline int wave_rpl(int mmax) {
 
 typedef float wf4 __attribute__((ext_vector_type(4)));
 
-// The lane index as a value the compiler cannot treat as loop-invariant.
-// Lane masks such as (l == j) for every compile-time j would otherwise be
-// hoisted out of the Newton loop and held in scalar register pairs, more of
-// them than the scalar file holds (they then spill through vector lanes).
-__device__ inline int opaque_lane(int l) {
-    asm volatile("" : "+v"(l));
-    return l;
-}
 
 // Value of v in lane k (k a compile-time or wave-uniform index).
 __device__ inline float wave_lane(float v, int k) {
