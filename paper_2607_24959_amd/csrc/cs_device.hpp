@@ -408,12 +408,20 @@ __device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, i
             const int l = threadIdx.x;
             const int lr = c0 + min(l, bs - 1);       // clamped row: loads stay in bounds
             T y = b[lr];
-            for (int c = 0; c < bs; ++c) {
-                const T yd = y / diag[c0 + c];
-                y = (l == c) ? yd : y;
-                const T yc = lane_bcast(y, c);
-                const T upd = y - L[lr * ld + c0 + c] * yc;
-                y = (l > c) ? upd : y;
+            // the lane's row of the block and the diagonal reciprocals up
+            // front (clamped columns), then 16 unrolled steps; lanes past the
+            // block never store and only feed broadcasts read by such lanes
+            T lrow[16], rd[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int cc = c0 + min(c, bs - 1);
+                lrow[c] = L[lr * ld + cc];
+                rd[c] = chol_rcp(diag[cc]);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const T yc = lane_bcast(y, c) * rd[c];   // y_c = (lane c's value) / L_cc
+                y = (l == c) ? yc : ((l > c) ? y - lrow[c] * yc : y);
             }
             if (l < bs) x[c0 + l] = y;
         }
@@ -437,12 +445,19 @@ __device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, i
             const int l = threadIdx.x;
             const int lc = c0 + min(l, bs - 1);       // clamped column: loads stay in bounds
             T v = x[lc];
-            for (int c = bs - 1; c >= 0; --c) {
-                const T vd = v / diag[c0 + c];
-                v = (l == c) ? vd : v;
-                const T xc = lane_bcast(v, c);
-                const T upd = v - L[(c0 + c) * ld + lc] * xc;
-                v = (l < c) ? upd : v;
+            T lcol[16], rd[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int cc = c0 + min(c, bs - 1);
+                lcol[c] = L[cc * ld + lc];
+                rd[c] = chol_rcp(diag[cc]);
+            }
+            // columns past the block update nobody (c < bs), so the lanes of
+            // the block see exactly the bs steps
+#pragma unroll
+            for (int c = 15; c >= 0; --c) {
+                const T xc = lane_bcast(v, c) * rd[c];
+                v = (l == c) ? xc : ((l < c && c < bs) ? v - lcol[c] * xc : v);
             }
             if (l < bs) x[c0 + l] = v;
         }
