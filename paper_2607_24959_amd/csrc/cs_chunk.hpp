@@ -29,6 +29,8 @@ template <typename T>
 struct ChLds {
     T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *red;
     T *r, *q, *Dv, *ar, *Jc, *Wc, *Wr;
+    T *Lw;          // weights of the chunk's active rows, compacted per wave
+    int *Lr, *Lc;   // their chunk rows, and the padded count per wave
     uint8_t *A;
 };
 
@@ -37,7 +39,7 @@ struct ChLds {
 __host__ __device__ inline size_t ch_lds_bytes(int npa, int mmax, int NT, size_t s) {
     const size_t ld = (size_t)npa + 1;
     const size_t nT = (size_t)npa * ld + 9 * (size_t)npa + 16 * (size_t)(NT / 64) +
-                      4 * (size_t)mmax + CR * ld + 2 * CR;
+                      4 * (size_t)mmax + CR * ld + 4 * CR + 8;
     return nT * s + (size_t)mmax + 64;
 }
 
@@ -62,6 +64,9 @@ __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int 
     L.Jc = p; p += (size_t)CR * (npa + 1);
     L.Wc = p; p += CR;
     L.Wr = p; p += CR;
+    L.Lw = p; p += CR;
+    L.Lr = reinterpret_cast<int *>(p); p += CR;
+    L.Lc = reinterpret_cast<int *>(p); p += 8;
     L.A = reinterpret_cast<uint8_t *>(p);
     return L;
 }
@@ -219,12 +224,16 @@ template <int NT> struct ChAcc<float, NT> {
 #pragma unroll
         for (int s = 0; s < MAXT; ++s) acc[s] = chf4{0.f, 0.f, 0.f, 0.f};
     }
-    // acc += J_c^T diag(Wc) J_c over the chunk (rows past m carry Wc = 0).
-    // The wave's tile count is a compile-time constant in each instance of
-    // the body, so a K-step issues all its LDS loads, then all its MFMAs,
-    // with no branches in between.
+    // acc += J_c^T diag(D o A) J_c over the chunk's active rows: every wave
+    // owns a segment of CR / NW consecutive chunk rows, whose active rows
+    // (and weights) were compacted into Lr / Lw with the count padded to
+    // whole K-steps (pad rows carry weight 0).  The wave's tile count is a
+    // compile-time constant in each instance of the body, so a K-step issues
+    // all its LDS loads, then all its MFMAs, with no branches in between.
     template <int TPW>
-    __device__ inline void add_chunk_t(int ldj, const float *Jc, const float *Wc) {
+    __device__ inline void add_chunk_t(int ldj, const float *Jc, const int *Lr, const float *Lw,
+                                       const int *Lc) {
+        constexpr int SEG = CR / NW;
         const int lane = threadIdx.x & 63;
         const int kq = lane >> 4, idx = lane & 15;
         int ca[TPW], cb[TPW];
@@ -233,35 +242,39 @@ template <int NT> struct ChAcc<float, NT> {
             ca[s] = 16 * ti[s] + idx;
             cb[s] = 16 * tj[s] + idx;
         }
+        for (int sg = 0; sg < NW; ++sg) {
+            const int nk = __builtin_amdgcn_readfirstlane(Lc[sg]) >> 2;
 #pragma unroll 2
-        for (int kb = 0; kb < CR / 4; ++kb) {
-            const int row = kb * 4 + kq;
-            const float wr = Wc[row];
-            const float *jr = Jc + row * ldj;
-            float av[TPW], bv[TPW];
+            for (int kb = 0; kb < nk; ++kb) {
+                const int e = sg * SEG + 4 * kb + kq;
+                const float wr = Lw[e];
+                const float *jr = Jc + Lr[e] * ldj;
+                float av[TPW], bv[TPW];
 #pragma unroll
-            for (int s = 0; s < TPW; ++s) {
-                av[s] = jr[ca[s]];
-                bv[s] = jr[cb[s]];
+                for (int s = 0; s < TPW; ++s) {
+                    av[s] = jr[ca[s]];
+                    bv[s] = jr[cb[s]];
+                }
+#pragma unroll
+                for (int s = 0; s < TPW; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], wr * bv[s], acc[s], 0, 0, 0);
             }
-#pragma unroll
-            for (int s = 0; s < TPW; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], wr * bv[s], acc[s], 0, 0, 0);
         }
     }
-    __device__ inline void add_chunk(int ldj, const float *Jc, const float *Wc) {
+    __device__ inline void add_chunk(int ldj, const float *Jc, const float *, const int *Lr,
+                                     const float *Lw, const int *Lc) {
         const int wave = threadIdx.x >> 6;
         const int ntl = (ntiles - wave + NW - 1) / NW;   // tiles of this wave (wave-uniform)
         switch (ntl) {
-            case 1: add_chunk_t<1>(ldj, Jc, Wc); break;
-            case 2: add_chunk_t<2>(ldj, Jc, Wc); break;
-            case 3: add_chunk_t<3>(ldj, Jc, Wc); break;
-            case 4: if constexpr (MAXT >= 4) add_chunk_t<4>(ldj, Jc, Wc); break;
-            case 5: if constexpr (MAXT >= 5) add_chunk_t<5>(ldj, Jc, Wc); break;
-            case 6: if constexpr (MAXT >= 6) add_chunk_t<6>(ldj, Jc, Wc); break;
-            case 7: if constexpr (MAXT >= 7) add_chunk_t<7>(ldj, Jc, Wc); break;
-            case 8: if constexpr (MAXT >= 8) add_chunk_t<8>(ldj, Jc, Wc); break;
-            case 9: if constexpr (MAXT >= 9) add_chunk_t<9>(ldj, Jc, Wc); break;
+            case 1: add_chunk_t<1>(ldj, Jc, Lr, Lw, Lc); break;
+            case 2: add_chunk_t<2>(ldj, Jc, Lr, Lw, Lc); break;
+            case 3: add_chunk_t<3>(ldj, Jc, Lr, Lw, Lc); break;
+            case 4: if constexpr (MAXT >= 4) add_chunk_t<4>(ldj, Jc, Lr, Lw, Lc); break;
+            case 5: if constexpr (MAXT >= 5) add_chunk_t<5>(ldj, Jc, Lr, Lw, Lc); break;
+            case 6: if constexpr (MAXT >= 6) add_chunk_t<6>(ldj, Jc, Lr, Lw, Lc); break;
+            case 7: if constexpr (MAXT >= 7) add_chunk_t<7>(ldj, Jc, Lr, Lw, Lc); break;
+            case 8: if constexpr (MAXT >= 8) add_chunk_t<8>(ldj, Jc, Lr, Lw, Lc); break;
+            case 9: if constexpr (MAXT >= 9) add_chunk_t<9>(ldj, Jc, Lr, Lw, Lc); break;
             default: break;
         }
     }
@@ -306,7 +319,8 @@ template <int NT> struct ChAcc<double, NT> {
 #pragma unroll
         for (int s = 0; s < MAXE; ++s) acc[s] = 0.0;
     }
-    __device__ inline void add_chunk(int ldj, const double *Jc, const double *Wc) {
+    __device__ inline void add_chunk(int ldj, const double *Jc, const double *Wc, const int *,
+                                     const double *, const int *) {
 #pragma unroll
         for (int s = 0; s < MAXE; ++s) {
             if ((int)threadIdx.x + NT * s < ne) {
@@ -436,6 +450,8 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     __syncthreads();
                     int rho, part;
                     const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.a, rho, part);
+                    bool actf = false;
+                    T wdv = T(0);
                     if (part == 0) {
                         const int i = c * CR + rho;
                         if (i < m) {
@@ -447,14 +463,36 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                             const T wd = an ? L.Dv[i] : T(0);
                             L.Wc[rho] = wd;
                             L.Wr[rho] = wd * r;
+                            actf = an;
+                            wdv = wd;
                         } else {
                             L.Wc[rho] = T(0);
                             L.Wr[rho] = T(0);
                         }
                     }
+                    if constexpr (sizeof(T) == 4) {
+                        // the wave's active rows compacted in row order into its
+                        // segment, the count padded to whole K-steps
+                        constexpr int SEG = CR / (NT / 64);
+                        const int sg = tid >> 6, lane = tid & 63;
+                        const uint64_t bal = __builtin_amdgcn_ballot_w64(actf);
+                        if (actf) {
+                            const int pos = (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                            L.Lr[sg * SEG + pos] = rho;
+                            L.Lw[sg * SEG + pos] = wdv;
+                        }
+                        const int cnt = (int)__builtin_popcountll(bal);
+                        const int cnt4 = (cnt + 3) & ~3;
+                        if (lane < cnt4 - cnt) {
+                            L.Lr[sg * SEG + cnt + lane] = sg * SEG;   // a row of the chunk, weight 0
+                            L.Lw[sg * SEG + cnt + lane] = T(0);
+                        }
+                        if (lane == 0) L.Lc[sg] = cnt4;
+                    }
                     __syncthreads();
                     cs.add_chunk(ldj, L.Jc, L.Wr);
-                    acc.add_chunk(ldj, L.Jc, L.Wc);
+                    acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Lw, L.Lc);
                 }
                 const bool same = !__syncthreads_or(changed);
                 acc.store(n, ldh, M, L.H);
