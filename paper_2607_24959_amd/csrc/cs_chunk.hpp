@@ -293,6 +293,30 @@ template <int NT> struct ChAcc<float, NT> {
             }
         }
     }
+    // As store, when the chunk's column n held the residual: row n of the
+    // product is J^T diag(D o A) r = J^T w, so F = u + that row.
+    __device__ inline void store_hf(int n, int ldh, const float *__restrict__ M, float *H,
+                                    const float *u, float *F) const {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int kq = lane >> 4, idx = lane & 15;
+#pragma unroll
+        for (int s = 0; s < MAXT; ++s) {
+            if (wave + NW * s < ntiles) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * ti[s] + 4 * kq + r, col = 16 * tj[s] + idx;
+                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + M[row * n + col];
+                    if (row == n && col < n) F[col] = acc[s][r] + u[col];
+                }
+            }
+        }
+    }
+    // The residual rides along as column n when the padded width n + 1 still
+    // fits the workgroup's tile budget.
+    __device__ static inline bool fits_residual(int n) {
+        const int nt = round16(n + 1) / 16;
+        return nt * (nt + 1) / 2 <= NW * MAXT;
+    }
 };
 
 // FP64: lower-triangle entries e = tid + NT s on the VALU.
@@ -423,8 +447,13 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
         int st = 0, k = 0;
         if (anybad) st = ST_NONFINITE;
         else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) st = ST_NOTSPD;
+        // FP32: the residual rides in column n of the staged chunk (which
+        // the row stride npa + 1 always has), so one matrix-core pass gives
+        // H and J^T w; tiles of this instance's own width, not the class's
+        bool fused = false;
+        if constexpr (sizeof(T) == 4) fused = ChAcc<T, NT>::fits_residual(n);
         ChAcc<T, NT> acc;
-        acc.init(sizeof(T) == 4 ? round16(n) : n);   // this instance's tiles, not the class's
+        acc.init(sizeof(T) == 4 ? round16(fused ? n + 1 : n) : n);
         if (st == 0) {
             T trM = T(0);
             for (int j = 0; j < n; ++j) trM += M[(int64_t)j * n + j];
@@ -465,9 +494,11 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                             L.Wr[rho] = wd * r;
                             actf = an;
                             wdv = wd;
+                            if (fused) L.Jc[rho * ldj + n] = r;
                         } else {
                             L.Wc[rho] = T(0);
                             L.Wr[rho] = T(0);
+                            if (fused) L.Jc[rho * ldj + n] = T(0);
                         }
                     }
                     if constexpr (sizeof(T) == 4) {
@@ -491,12 +522,22 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                         if (lane == 0) L.Lc[sg] = cnt4;
                     }
                     __syncthreads();
-                    cs.add_chunk(ldj, L.Jc, L.Wr);
+                    if (!fused) cs.add_chunk(ldj, L.Jc, L.Wr);
                     acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Lw, L.Lc);
                 }
                 const bool same = !__syncthreads_or(changed);
-                acc.store(n, ldh, M, L.H);
-                cs.finish(n, ldj, L.Jc, L.u, L.F);
+                if constexpr (sizeof(T) == 4) {
+                    if (fused) {
+                        acc.store_hf(n, ldh, M, L.H, L.u, L.F);
+                        __syncthreads();
+                    } else {
+                        acc.store(n, ldh, M, L.H);
+                        cs.finish(n, ldj, L.Jc, L.u, L.F);
+                    }
+                } else {
+                    acc.store(n, ldh, M, L.H);
+                    cs.finish(n, ldj, L.Jc, L.u, L.F);
+                }
                 T g2 = T(0), an = T(0);
                 for (int j = tid; j < n; j += NT) {
                     g2 += L.F[j] * L.F[j];
