@@ -1,20 +1,23 @@
-// cs_chunk.hpp -- team kernels that stream the rows of J through LDS.
+// cs_chunk.hpp -- team kernels for instances whose J does not stay in LDS.
 //
 // One workgroup (NT = 64 for n <= 32, 256 otherwise) solves one instance at
-// a time.  Each Newton pass reads J in chunks of CR rows: every thread holds
-// its share of the next chunk in registers (loads issued before the current
-// chunk is processed, so global latency overlaps the work), then the chunk
-// is written to LDS (row stride npa + 1, conflict-free) and its rows give the
-// residuals (NT / CR lanes per row), the gradient J^T w (per-thread partial
-// sums over fixed rows, kept in registers across chunks) and the
-// Newton-matrix contribution J_c^T diag(D o A) J_c.  In FP32 the contraction
-// runs on the matrix cores (v_mfma_f32_16x16x4f32 on 16 x 16 tiles of the
-// lower triangle, tiles spread over the waves and interleaved per K-step,
-// accumulators in registers); in FP64 lanes accumulate lower-triangle
-// entries on the VALU.  A second pass forms q = J p for the line search.
-// H (row stride npa + 1), the row arrays r, q, D, aref and the chunk buffer
-// live in LDS; M stays in global memory (read column-wise, coalesced, as a
-// symmetric matrix).
+// a time.  Forward, per Newton step: the residuals r = J a - aref come
+// straight from global memory (eight lanes per row, many rows' loads in
+// flight, no staging), each wave listing its active rows (r < 0) in row
+// order; the listed rows are then gathered into LDS in chunks of CR rows
+// (row stride npa + 1, conflict-free) for the Newton-matrix contribution
+// J_A^T diag(D_A) J_A and the gradient J_A^T w -- inactive rows add nothing
+// to either.  In FP32 the contraction runs on the matrix cores
+// (v_mfma_f32_16x16x4f32 on 16 x 16 tiles of the lower triangle, tiles spread
+// over the waves and interleaved per K-step, accumulators in registers), and
+// when n is not a multiple of 16 the residual rides in column n so the same
+// pass yields J^T w; in FP64 lanes accumulate lower-triangle entries on the
+// VALU.  A second direct pass forms q = J p for the line search.  The VJP
+// streams J through LDS in CR-row chunks (each thread holds its share of the
+// next chunk in registers while the current one is used).  H (row stride
+// npa + 1), the row arrays r, q, D, aref and the chunk buffer live in LDS; M
+// stays in global memory (read column-wise, coalesced, as a symmetric
+// matrix).
 #pragma once
 
 #include "cs_device.hpp"
@@ -31,16 +34,26 @@ struct ChLds {
     T *r, *q, *Dv, *ar, *Jc, *Wc, *Wr;
     T *Lw;          // weights of the chunk's active rows, compacted per wave
     int *Lr, *Lc;   // their chunk rows, and the padded count per wave
+    int *Li, *Ln;   // forward: each wave's active rows (row order), and their counts
     uint8_t *A;
 };
 
+// Capacity of one wave's active-row list: the rows dotted by a wave's lanes
+// in ch_rows_dot are 8 of every NT / 8.
+__host__ __device__ inline int ch_list_cap(int mmax, int NT) {
+    const int rpb = NT / 8;
+    return 8 * ((mmax + rpb - 1) / rpb);
+}
+
 // H (npa x (npa + 1)), eight n-vectors and the diagonal, reduction scratch,
-// four row arrays, the chunk (CR x (npa + 1)), two chunk-row arrays, A.
+// four row arrays, the chunk (CR x (npa + 1)), two chunk-row arrays, the
+// per-wave active-row lists, A.
 __host__ __device__ inline size_t ch_lds_bytes(int npa, int mmax, int NT, size_t s) {
     const size_t ld = (size_t)npa + 1;
     const size_t nT = (size_t)npa * ld + 9 * (size_t)npa + 16 * (size_t)(NT / 64) +
                       4 * (size_t)mmax + CR * ld + 4 * CR + 8;
-    return nT * s + (size_t)mmax + 64;
+    const size_t lists = 4 * ((size_t)(NT / 64) * ch_list_cap(mmax, NT) + 8);
+    return nT * s + lists + (size_t)mmax + 64;
 }
 
 template <typename T>
@@ -67,7 +80,10 @@ __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int 
     L.Lw = p; p += CR;
     L.Lr = reinterpret_cast<int *>(p); p += CR;
     L.Lc = reinterpret_cast<int *>(p); p += 8;
-    L.A = reinterpret_cast<uint8_t *>(p);
+    int *ip = reinterpret_cast<int *>(p);
+    L.Li = ip; ip += (NT / 64) * ch_list_cap(mmax, NT);
+    L.Ln = ip; ip += 8;
+    L.A = reinterpret_cast<uint8_t *>(ip);
     return L;
 }
 
@@ -151,6 +167,76 @@ __device__ inline void ch_row_dot2(int n, int ldj, const T *Jc, const T *x, cons
     }
     sx = a;
     sy = b;
+}
+
+// Sum over the 8 lanes of an aligned lane octet, every lane gets the sum.
+template <typename T> __device__ inline T osum8(T v);
+template <> __device__ inline float osum8<float>(float v) {
+    // quad xor 1, quad xor 2, half-row mirror
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+    return v;
+}
+template <> __device__ inline double osum8<double>(double v) {
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) v += __shfl_xor(v, o, 8);
+    return v;
+}
+
+// Dot products of every row of the instance's row-major J (m x n, global
+// memory) with an LDS vector x.  Eight lanes per row; lane `part` of an
+// octet always takes columns part, part + 8, ... (CPL of them), so x is read
+// from LDS once per pass.  Rows go in blocks of NT / 8 (octet o of the
+// workgroup takes row o of each block), two blocks' loads issued before any
+// use; addresses are clamped so every load is unconditional.  fn(i, s) runs
+// on every lane of every octet with the row's dot s (rows i >= m included,
+// so calls stay wave-convergent).
+template <int NT, int CPL, typename T, typename Fn>
+__device__ inline void ch_rows_dot_t(const T *__restrict__ J, int n, int m, const T *x, Fn &fn) {
+    constexpr int RPB = NT / 8, UN = 2;
+    const int part = threadIdx.x & 7, oct = threadIdx.x >> 3;
+    T xv[CPL];
+    int cl[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int c = part + 8 * k;
+        xv[k] = c < n ? x[c] : T(0);
+        cl[k] = min(c, n - 1);
+    }
+    for (int b0 = 0; b0 < m; b0 += UN * RPB) {
+        T v[UN][CPL];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const T *row = J + (int64_t)min(b0 + u * RPB + oct, m - 1) * n;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) v[u][k] = row[cl[k]];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            T s0 = T(0), s1 = T(0);
+#pragma unroll
+            for (int k = 0; k + 1 < CPL; k += 2) {
+                s0 += v[u][k] * xv[k];
+                s1 += v[u][k + 1] * xv[k + 1];
+            }
+            fn(b0 + u * RPB + oct, osum8(s0 + s1));
+        }
+    }
+}
+
+// The same with the columns per lane chosen from n (ceil(n / 8) rounded up
+// to a multiple of 4; n <= 32 when NT = 64, n <= 128 otherwise).
+template <int NT, typename T, typename Fn>
+__device__ inline void ch_rows_dot(const T *__restrict__ J, int n, int m, const T *x, Fn &&fn) {
+    if constexpr (NT == 64) {
+        ch_rows_dot_t<NT, 4>(J, n, m, x, fn);
+    } else {
+        if (n <= 32) ch_rows_dot_t<NT, 4>(J, n, m, x, fn);
+        else if (n <= 64) ch_rows_dot_t<NT, 8>(J, n, m, x, fn);
+        else if (n <= 96) ch_rows_dot_t<NT, 12>(J, n, m, x, fn);
+        else ch_rows_dot_t<NT, 16>(J, n, m, x, fn);
+    }
 }
 
 // Per-thread partial of J^T x over the chunks: column fj, rows fp, fp + fparts, ...
@@ -396,6 +482,77 @@ __device__ inline T team_max(T v, T *sred) {
     return v;
 }
 
+// Chunk c of the active-row list (entries c CR .. c CR + CR - 1 of the
+// per-wave lists taken wave after wave) into LDS: slot s of Jc gets the
+// row of J, Wc[s] its weight D_i, Wr[s] = D_i r_i and, when fused, Jc[s][n]
+// = r_i; slots past the list's end are zero rows of weight zero.  Lc gets
+// each wave segment's slot count padded to whole K-steps.  Synchronises the
+// team before the LDS stores and after them.
+template <int NT, int CPL, typename T>
+__device__ inline void ch_gather_t(const T *__restrict__ J, int n, int ldj, int c, int total,
+                                   const int (&off)[NT / 64], int cap, bool fused,
+                                   const ChLds<T> &L) {
+    constexpr int RPB = NT / 8, GP = CR / RPB, NW = NT / 64;
+    const int part = threadIdx.x & 7, oct = threadIdx.x >> 3;
+    T v[GP][CPL];
+    int rows[GP];
+#pragma unroll
+    for (int g = 0; g < GP; ++g) {
+        const int pos = c * CR + g * RPB + oct;
+        int row = -1;
+        if (pos < total) {
+            int w = 0, o = 0;
+#pragma unroll
+            for (int q = 1; q < NW; ++q)
+                if (pos >= off[q]) { w = q; o = off[q]; }
+            row = L.Li[w * cap + pos - o];
+        }
+        rows[g] = row;
+        const T *src = J + (int64_t)max(row, 0) * n;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const T x = src[min(part + 8 * k, n - 1)];
+            v[g][k] = row >= 0 ? x : T(0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < GP; ++g) {
+        const int slot = g * RPB + oct;
+        T *dst = L.Jc + slot * ldj;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            if (part + 8 * k < n) dst[part + 8 * k] = v[g][k];
+        if (part == 0) {
+            const int row = rows[g];
+            const T r = row >= 0 ? L.r[row] : T(0);
+            const T wd = row >= 0 ? L.Dv[row] : T(0);
+            L.Wc[slot] = wd;
+            L.Wr[slot] = wd * r;
+            if (fused) dst[n] = r;
+        }
+    }
+    if ((int)threadIdx.x < NW) {
+        const int left = min(CR, total - c * CR) - (CR / NW) * (int)threadIdx.x;
+        L.Lc[threadIdx.x] = min(CR / NW, (max(left, 0) + 3) & ~3);
+    }
+    __syncthreads();
+}
+
+template <int NT, typename T>
+__device__ inline void ch_gather(const T *__restrict__ J, int n, int ldj, int c, int total,
+                                 const int (&off)[NT / 64], int cap, bool fused,
+                                 const ChLds<T> &L) {
+    if constexpr (NT == 64) {
+        ch_gather_t<NT, 4>(J, n, ldj, c, total, off, cap, fused, L);
+    } else {
+        if (n <= 32) ch_gather_t<NT, 4>(J, n, ldj, c, total, off, cap, fused, L);
+        else if (n <= 64) ch_gather_t<NT, 8>(J, n, ldj, c, total, off, cap, fused, L);
+        else if (n <= 96) ch_gather_t<NT, 12>(J, n, ldj, c, total, off, cap, fused, L);
+        else ch_gather_t<NT, 16>(J, n, ldj, c, total, off, cap, fused, L);
+    }
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_forward_chunk(
     BatchView bv, int count, int max_iter, T tol, int npa, int mmax, const T *__restrict__ gM,
@@ -407,13 +564,12 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
     const ChLds<T> L = ch_carve<T>(smem, npa, mmax, NT);
     const int tid = threadIdx.x;
     const int ldj = npa + 1, ldh = npa + 1;
+    const int cap = ch_list_cap(mmax, NT);
+    for (int e = tid; e < CR; e += NT) L.Lr[e] = e;   // gathered chunks: slot e is row e
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
         const int n = I.n, m = I.m;
-        const int nch = (m + CR - 1) / CR;
         const T *M = gM + I.onn, *J = gJ + I.omn;
-        ChStage<NT, T> stg;
-        stg.plan(n);
         ChColSum<NT, T> cs;
         bool bad = false;
         for (int j = tid; j < n; j += NT) {
@@ -467,63 +623,49 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
             T step_inf = T(-1);
             int lsfail = 0;
             for (k = 0;; ++k) {
-                // pass A: r, A, F = M (a - a0) + J^T w and H = M + J^T diag(D o A) J
+                // pass A: r, A, F = M (a - a0) + J^T w and H = M + J^T diag(D o A) J.
+                // Residuals straight from global memory; each wave lists its
+                // active rows in row order; the listed rows are then gathered
+                // into LDS chunks for the contraction and J^T w (inactive
+                // rows add nothing to either).
                 acc.zero();
                 cs.plan(n);
                 bool changed = false;
-                if (nch > 0) stg.load(J, n, m, 0);
-                for (int c = 0; c < nch; ++c) {
-                    __syncthreads();
-                    stg.store(n, ldj, L.Jc);
-                    if (c + 1 < nch) stg.load(J, n, m, c + 1);
-                    __syncthreads();
-                    int rho, part;
-                    const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.a, rho, part);
-                    bool actf = false;
-                    T wdv = T(0);
-                    if (part == 0) {
-                        const int i = c * CR + rho;
-                        if (i < m) {
+                {
+                    int cntw = 0;   // wave-uniform
+                    int *lw = L.Li + (tid >> 6) * cap;
+                    ch_rows_dot<NT>(J, n, m, L.a, [&](int i, T s) {
+                        bool an = false;
+                        if ((tid & 7) == 0 && i < m) {
                             const T r = s - L.ar[i];
-                            const uint8_t an = r < T(0);
-                            changed |= an != L.A[i];
+                            an = r < T(0);
+                            changed |= an != (L.A[i] != 0);
                             L.A[i] = an;
                             L.r[i] = r;
-                            const T wd = an ? L.Dv[i] : T(0);
-                            L.Wc[rho] = wd;
-                            L.Wr[rho] = wd * r;
-                            actf = an;
-                            wdv = wd;
-                            if (fused) L.Jc[rho * ldj + n] = r;
-                        } else {
-                            L.Wc[rho] = T(0);
-                            L.Wr[rho] = T(0);
-                            if (fused) L.Jc[rho * ldj + n] = T(0);
                         }
+                        const uint64_t bal = __builtin_amdgcn_ballot_w64(an);
+                        if (an)
+                            lw[cntw + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(bal >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = i;
+                        cntw += (int)__builtin_popcountll(bal);
+                    });
+                    if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
+                }
+                __syncthreads();
+                {
+                    int off[NT / 64], total = 0;
+#pragma unroll
+                    for (int w = 0; w < NT / 64; ++w) {
+                        off[w] = total;
+                        total += L.Ln[w];
                     }
-                    if constexpr (sizeof(T) == 4) {
-                        // the wave's active rows compacted in row order into its
-                        // segment, the count padded to whole K-steps
-                        constexpr int SEG = CR / (NT / 64);
-                        const int sg = tid >> 6, lane = tid & 63;
-                        const uint64_t bal = __builtin_amdgcn_ballot_w64(actf);
-                        if (actf) {
-                            const int pos = (int)__builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                            L.Lr[sg * SEG + pos] = rho;
-                            L.Lw[sg * SEG + pos] = wdv;
-                        }
-                        const int cnt = (int)__builtin_popcountll(bal);
-                        const int cnt4 = (cnt + 3) & ~3;
-                        if (lane < cnt4 - cnt) {
-                            L.Lr[sg * SEG + cnt + lane] = sg * SEG;   // a row of the chunk, weight 0
-                            L.Lw[sg * SEG + cnt + lane] = T(0);
-                        }
-                        if (lane == 0) L.Lc[sg] = cnt4;
+                    const int ncha = (total + CR - 1) / CR;
+                    for (int c = 0; c < ncha; ++c) {
+                        ch_gather<NT>(J, n, ldj, c, total, off, cap, fused, L);
+                        if (!fused) cs.add_chunk(ldj, L.Jc, L.Wr);
+                        acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Wc, L.Lc);
                     }
-                    __syncthreads();
-                    if (!fused) cs.add_chunk(ldj, L.Jc, L.Wr);
-                    acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Lw, L.Lc);
                 }
                 const bool same = !__syncthreads_or(changed);
                 if constexpr (sizeof(T) == 4) {
@@ -559,18 +701,10 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
                 team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
-                // pass B: q = J p, and v = M p
-                if (nch > 0) stg.load(J, n, m, 0);
-                for (int c = 0; c < nch; ++c) {
-                    __syncthreads();
-                    stg.store(n, ldj, L.Jc);
-                    if (c + 1 < nch) stg.load(J, n, m, c + 1);
-                    __syncthreads();
-                    int rho, part;
-                    const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.p, rho, part);
-                    const int i = c * CR + rho;
-                    if (part == 0 && i < m) L.q[i] = s;
-                }
+                // pass B: q = J p (straight from global memory), and v = M p
+                ch_rows_dot<NT>(J, n, m, L.p, [&](int i, T s) {
+                    if ((tid & 7) == 0 && i < m) L.q[i] = s;
+                });
                 T c0 = T(0), b0 = T(0);
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0);
