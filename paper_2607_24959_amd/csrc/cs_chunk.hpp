@@ -56,6 +56,15 @@ __host__ __device__ inline size_t ch_lds_bytes(int npa, int mmax, int NT, size_t
     return nT * s + lists + (size_t)mmax + 64;
 }
 
+// Forward with M resident in LDS (FP32, when it fits): the n x n copy sits
+// 16-byte aligned after everything above.
+__host__ __device__ inline size_t ch_m_offset(int npa, int mmax, int NT, size_t s) {
+    return (ch_lds_bytes(npa, mmax, NT, s) + 15) & ~size_t(15);
+}
+__host__ __device__ inline size_t ch_lds_bytes_mlds(int npa, int mmax, int NT, size_t s) {
+    return ch_m_offset(npa, mmax, NT, s) + (size_t)npa * npa * s;
+}
+
 template <typename T>
 __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int NT) {
     ChLds<T> L;
@@ -188,13 +197,13 @@ template <> __device__ inline double osum8<double>(double v) {
 // memory) with an LDS vector x.  Eight lanes per row; lane `part` of an
 // octet always takes columns part, part + 8, ... (CPL of them), so x is read
 // from LDS once per pass.  Rows go in blocks of NT / 8 (octet o of the
-// workgroup takes row o of each block), two blocks' loads issued before any
-// use; addresses are clamped so every load is unconditional.  fn(i, s) runs
+// workgroup takes row o of each block), 32 / CPL blocks' loads issued before
+// any use; addresses are clamped so every load is unconditional.  fn(i, s) runs
 // on every lane of every octet with the row's dot s (rows i >= m included,
 // so calls stay wave-convergent).
 template <int NT, int CPL, typename T, typename Fn>
 __device__ inline void ch_rows_dot_t(const T *__restrict__ J, int n, int m, const T *x, Fn &fn) {
-    constexpr int RPB = NT / 8, UN = 2;
+    constexpr int RPB = NT / 8, UN = 32 / CPL > 1 ? 32 / CPL : 1;
     const int part = threadIdx.x & 7, oct = threadIdx.x >> 3;
     T xv[CPL];
     int cl[CPL];
@@ -553,7 +562,7 @@ __device__ inline void ch_gather(const T *__restrict__ J, int n, int ldj, int c,
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool MLDS>
 __global__ __launch_bounds__(NT) void k_forward_chunk(
     BatchView bv, int count, int max_iter, T tol, int npa, int mmax, const T *__restrict__ gM,
     const T *__restrict__ gJ, const T *__restrict__ ga0, const T *__restrict__ garef,
@@ -565,6 +574,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
     const int tid = threadIdx.x;
     const int ldj = npa + 1, ldh = npa + 1;
     const int cap = ch_list_cap(mmax, NT);
+    T *Ms = MLDS ? reinterpret_cast<T *>(smem + ch_m_offset(npa, mmax, NT, sizeof(T))) : nullptr;
     for (int e = tid; e < CR; e += NT) L.Lr[e] = e;   // gathered chunks: slot e is row e
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
@@ -592,17 +602,26 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
             for (int e = tid; e < n * n; e += NT) {
                 const T x = M[e];
                 L.H[rr * ldh + jj] = x;
+                if constexpr (MLDS) Ms[e] = x;
                 bad |= !finite_val(x);
                 rr += dr;
                 jj += dc;
                 if (jj >= n) { jj -= n; ++rr; }
             }
         }
-        for (int e = tid; e < m * n; e += NT) bad |= !finite_val(J[e]);
+        // J is checked by the first residual pass (a non-finite entry makes
+        // its row's dot non-finite, a being finite); only when M fails does
+        // it get a scan of its own, so that NONFINITE still takes precedence
         const int anybad = __syncthreads_or(bad);
+        const T *Mk = MLDS ? Ms : M;   // M for the rest of the solve
         int st = 0, k = 0;
-        if (anybad) st = ST_NONFINITE;
-        else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) st = ST_NOTSPD;
+        if (anybad) {
+            st = ST_NONFINITE;
+        } else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) {
+            bool jb = false;
+            for (int e = tid; e < m * n; e += NT) jb |= !finite_val(J[e]);
+            st = __syncthreads_or(jb) ? ST_NONFINITE : ST_NOTSPD;
+        }
         // FP32: the residual rides in column n of the staged chunk (which
         // the row stride npa + 1 always has), so one matrix-core pass gives
         // H and J^T w; tiles of this instance's own width, not the class's
@@ -612,12 +631,12 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
         acc.init(sizeof(T) == 4 ? round16(fused ? n + 1 : n) : n);
         if (st == 0) {
             T trM = T(0);
-            for (int j = 0; j < n; ++j) trM += M[(int64_t)j * n + j];
+            for (int j = 0; j < n; ++j) trM += Mk[j * n + j];
             // u = M (a - a0), kept up to date across steps
             for (int j = tid; j < n; j += NT) {
                 T s = T(0);
 #pragma unroll 16
-                for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * (L.a[l] - L.a0[l]);
+                for (int l = 0; l < n; ++l) s += Mk[l * n + j] * (L.a[l] - L.a0[l]);
                 L.u[j] = s;
             }
             T step_inf = T(-1);
@@ -630,7 +649,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 // rows add nothing to either).
                 acc.zero();
                 cs.plan(n);
-                bool changed = false;
+                bool changed = false, nonfin = false;
                 {
                     int cntw = 0;   // wave-uniform
                     int *lw = L.Li + (tid >> 6) * cap;
@@ -638,6 +657,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                         bool an = false;
                         if ((tid & 7) == 0 && i < m) {
                             const T r = s - L.ar[i];
+                            nonfin |= !finite_val(r);
                             an = r < T(0);
                             changed |= an != (L.A[i] != 0);
                             L.A[i] = an;
@@ -652,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     });
                     if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
                 }
-                __syncthreads();
+                if (__syncthreads_or(k == 0 && nonfin)) { st = ST_NONFINITE; break; }
                 {
                     int off[NT / 64], total = 0;
 #pragma unroll
@@ -670,14 +690,14 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 const bool same = !__syncthreads_or(changed);
                 if constexpr (sizeof(T) == 4) {
                     if (fused) {
-                        acc.store_hf(n, ldh, M, L.H, L.u, L.F);
+                        acc.store_hf(n, ldh, Mk, L.H, L.u, L.F);
                         __syncthreads();
                     } else {
-                        acc.store(n, ldh, M, L.H);
+                        acc.store(n, ldh, Mk, L.H);
                         cs.finish(n, ldj, L.Jc, L.u, L.F);
                     }
                 } else {
-                    acc.store(n, ldh, M, L.H);
+                    acc.store(n, ldh, Mk, L.H);
                     cs.finish(n, ldj, L.Jc, L.u, L.F);
                 }
                 T g2 = T(0), an = T(0);
@@ -709,7 +729,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 for (int j = tid; j < n; j += NT) {
                     T mp = T(0);
 #pragma unroll 16
-                    for (int l = 0; l < n; ++l) mp += M[(int64_t)l * n + j] * L.p[l];
+                    for (int l = 0; l < n; ++l) mp += Mk[l * n + j] * L.p[l];
                     L.v[j] = mp;
                     c0 += L.p[j] * mp;
                     b0 += L.p[j] * L.u[j];
@@ -916,19 +936,21 @@ int launch_chunk_forward(const BatchView &bv, int count, int nmax, int mmax, int
                          int32_t *iters, hipStream_t stream) {
     const int npa = round16(nmax);
     const int NT = chunk_nt(nmax);
-    const size_t lds = ch_lds_bytes(npa, mmax, NT, sizeof(T));
-    if (NT == 64) {
-        auto k = k_forward_chunk<T, 64>;
+    // FP32 keeps M in LDS whenever the copy fits beside the rest
+    const size_t lds_m = ch_lds_bytes_mlds(npa, mmax, NT, sizeof(T));
+    const bool mlds = sizeof(T) == 4 && lds_m <= 160 * 1024;
+    const size_t lds = mlds ? lds_m : ch_lds_bytes(npa, mmax, NT, sizeof(T));
+    auto go = [&](auto k, int nt) {
         if (chunk_prepare(k, lds)) return -3;
-        hipLaunchKernelGGL(k, dim3(chunk_grid(count)), dim3(64), lds, stream, bv, count, max_iter,
+        hipLaunchKernelGGL(k, dim3(chunk_grid(count)), dim3(nt), lds, stream, bv, count, max_iter,
                            tol, npa, mmax, M, J, a0, aref, D, a_init, a_out, fac, mask, status, iters);
-    } else {
-        auto k = k_forward_chunk<T, 256>;
-        if (chunk_prepare(k, lds)) return -3;
-        hipLaunchKernelGGL(k, dim3(chunk_grid(count)), dim3(256), lds, stream, bv, count, max_iter,
-                           tol, npa, mmax, M, J, a0, aref, D, a_init, a_out, fac, mask, status, iters);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    };
+    if constexpr (sizeof(T) == 4) {
+        if (mlds) return NT == 64 ? go(k_forward_chunk<T, 64, true>, 64)
+                                  : go(k_forward_chunk<T, 256, true>, 256);
     }
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return NT == 64 ? go(k_forward_chunk<T, 64, false>, 64) : go(k_forward_chunk<T, 256, false>, 256);
 }
 
 template <typename T>
