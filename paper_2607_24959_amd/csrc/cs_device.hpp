@@ -6,6 +6,8 @@
 // partials in LDS.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -157,6 +159,26 @@ __device__ inline double lane_bcast(double v, int k) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Value of v in lane k of the lane's own row of 16 (k a compile-time
+// constant), by a DPP row broadcast: the result stays in a vector register.
+template <int K> __device__ inline float row_bcast16(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xF, 0xF, false));
+}
+template <int K> __device__ inline double row_bcast16(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Compile-time loop: f(integral_constant<int, I>) for I = 0 .. N-1.
+template <int I, int N, typename F> __device__ inline void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Trailing update of the blocked Cholesky: for c1 <= j <= i < n,
@@ -176,18 +198,31 @@ __device__ inline void chol_trailing(float *H, int n, int ld, int c0, int c1) {
         while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
         const int tj = t - ti * (ti + 1) / 2;
         const int ra = c1 + 16 * ti + li, rb = c1 + 16 * tj + li;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int col = c1 + 16 * tj + li;
+        // every load (operands and the entries updated) issued before any
+        // use, from clamped addresses; the empty asm keeps the compiler from
+        // turning each into a branch that waits for it
+        float a[4], b[4], h[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kc = c0 + 4 * ks + lk;
-            const float a = ra < n ? H[ra * ld + kc] : 0.f;
-            const float b = rb < n ? H[rb * ld + kc] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            a[ks] = H[min(ra, n - 1) * ld + kc];
+            b[ks] = H[min(rb, n - 1) * ld + kc];
         }
 #pragma unroll
+        for (int r = 0; r < 4; ++r)
+            h[r] = H[min(c1 + 16 * ti + 4 * lk + r, n - 1) * ld + min(col, n - 1)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(a[q]), "+v"(b[q]), "+v"(h[q]));
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ra < n ? a[ks] : 0.f, rb < n ? b[ks] : 0.f,
+                                                       acc, 0, 0, 0);
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = c1 + 16 * ti + 4 * lk + r, col = c1 + 16 * tj + li;
-            if (row < n && col <= row) H[row * ld + col] -= acc[r];
+            const int row = c1 + 16 * ti + 4 * lk + r;
+            if (row < n && col <= row) H[row * ld + col] = h[r] - acc[r];
         }
     }
 }
@@ -225,14 +260,19 @@ __device__ inline void chol_panel(float *H, int n, int ld, int c0, int c1, const
     const int nt = (n - c1 + 15) / 16;
     for (int t = wave; t < nt; t += NT / 64) {
         const int ra = c1 + 16 * t + li;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        float a[4], b[4];   // all loads in flight together (see chol_trailing)
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int k = 4 * ks + lk;
-            const float a = ra < n ? H[ra * ld + c0 + k] : 0.f;
-            const float b = B[k * 17 + li];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            a[ks] = H[min(ra, n - 1) * ld + c0 + k];
+            b[ks] = B[k * 17 + li];
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(a[q]), "+v"(b[q]));
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ra < n ? a[ks] : 0.f, b[ks], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = c1 + 16 * t + 4 * lk + r;
@@ -304,7 +344,7 @@ __device__ inline int opaque_lane(int l) {
 // stride ld): the lower triangle is read, L is written strictly below the
 // diagonal and L_jj goes to diag[j].  Right-looking over 16-column blocks:
 // every wave factors the diagonal block in registers (one row per lane,
-// lane broadcasts) and forms its inverse X = L_D^{-1} (one column per
+// DPP row broadcasts) and forms its inverse X = L_D^{-1} (one column per
 // lane); wave 0 stores L_D and X^T (to work, 16 x 17 values).  The panel
 // below is H_panel X^T and the trailing lower triangle takes the block's
 // rank-16 update.  n <= 32 for NT = 64, n <= 128 for NT = 256.  The caller
@@ -324,50 +364,62 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
         {
             const int l = threadIdx.x & 63;
             const bool w0 = threadIdx.x < 64;
+            // Row l of the block (clamped, always in-bounds loads; the empty
+            // asm keeps the compiler from sinking each load into a branch of
+            // its own that waits for it).  Entries above the diagonal and
+            // rows past the block hold whatever H holds there: the lower
+            // triangle of rows < bs never reads them (each update of L_lk,
+            // k <= l, reads L_kj and L_lj with j < k), and nothing else is
+            // stored from them.  Lanes 16..63 repeat rows of their own row
+            // of 16 and store nothing.
             T d[16];
-            // clamped (always in-bounds) loads, then select: rows past the
-            // block and the upper triangle are zero
-            const T *hr = H + (c0 + min(l, bs - 1)) * ld + c0;
+            const T *hr = H + (c0 + min(l & 15, bs - 1)) * ld + c0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const T x = hr[min(k, bs - 1)];
-                d[k] = (l < bs && k <= l) ? x : T(0);
-            }
-            // Branch-free over the 16 columns: lanes also update entries
-            // above their diagonal (never stored; every stored entry only
-            // reads entries below or on the diagonal of other rows), and
-            // columns past bs (zero rows and columns) take pivot 1.  A branch
-            // that changes d[] would make the compiler copy the row at its
-            // join.  Lane j's own d[j] is the pivot, so scaling gives L_jj.
+            for (int k = 0; k < 16; ++k) d[k] = hr[min(k, bs - 1)];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const T piv = (j < bs) ? lane_bcast(d[j], j) : T(1);
-                d[j] *= chol_rsq(piv);
-#pragma unroll
-                for (int k = j + 1; k < 16; ++k) d[k] -= d[j] * lane_bcast(d[j], k);
-            }
+            for (int k = 0; k < 16; ++k) asm volatile("" : "+v"(d[k]));
+            // right-looking, one DPP row broadcast per entry; columns past bs
+            // take pivot 1
+            static_for<0, 16>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const T pv = row_bcast16<j>(d[j]);
+                d[j] *= chol_rsq((j < bs) ? pv : T(1));
+                static_for<j + 1, 16>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    d[k] -= d[j] * row_bcast16<k>(d[j]);
+                });
+            });
             T dl = d[0];   // this lane's L_ll, picked in one pass
-            {
-                const int lo = opaque_lane(l);
+            const int lo = opaque_lane(l & 15);
 #pragma unroll
-                for (int k = 1; k < 16; ++k) dl = (k == lo) ? d[k] : dl;
-            }
-            // column l of X = L_D^{-1}: x_c = 0 (c < l), x_l = 1 / L_ll,
-            // x_c = -(sum_{k<c} L_ck x_k) / L_cc (c > l)
-            T x[16];
+            for (int k = 1; k < 16; ++k) dl = (k == lo) ? d[k] : dl;
+            // every wave holds the whole block: positive definiteness from a
+            // ballot of the block's diagonal (NaN fails), no LDS round trip
+            ok = ok && __builtin_amdgcn_ballot_w64(l < bs && !(dl > T(0))) == 0;
+            // column l of X = L_D^{-1}: x_c = (delta_cl - sum_{k<c} L_ck x_k) / L_cc,
+            // right-looking (each x_k feeds the sums of the later rows at
+            // once); entries above the diagonal come out zero by themselves.
+            // Only the last block has bs < 16, and it has no panel, so X's
+            // columns past bs are never used.
+            T x[16], acc[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                T acc = T(0);
-#pragma unroll
-                for (int k = 0; k < c; ++k) acc += lane_bcast(d[k], c) * x[k];
-                const T rc = chol_rcp(lane_bcast(d[c], c));
-                const T xc = (c == l) ? rc : -acc * rc;
-                x[c] = (c < l || c >= bs) ? T(0) : xc;
-            }
+            for (int c = 0; c < 16; ++c) acc[c] = T(0);
+            static_for<0, 16>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const T rk = chol_rcp(row_bcast16<k>(d[k]));
+                x[k] = ((k == lo ? T(1) : T(0)) - acc[k]) * rk;
+                static_for<k + 1, 16>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    acc[c] += row_bcast16<c>(d[k]) * x[k];
+                });
+            });
+            // whole rows of the block (a team-uniform bound, no lane masks):
+            // the block's upper triangle in H is free storage (readers take L
+            // strictly below the diagonal and L_jj from diag)
             if (w0 && l < bs) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k)
-                    if (k < l) H[(c0 + l) * ld + c0 + k] = d[k];
+                    if (k < bs) H[(c0 + l) * ld + c0 + k] = d[k];
                 diag[c0 + l] = dl;
             }
             if (w0 && l < 16) {
@@ -376,7 +428,6 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
             }
         }
         __syncthreads();
-        for (int j = 0; j < bs; ++j) ok = ok && (diag[c0 + j] > T(0));
         const int c1 = c0 + bs;
         if (c1 < n) {
             chol_panel<NT>(H, n, ld, c0, c1, work);
@@ -389,7 +440,7 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
 
 // Solve L L^T x = b with the factor from team_cholesky.  b is overwritten;
 // the solution is returned in x.  Blocked like the factorisation: wave 0
-// solves each 16 x 16 diagonal block with lane broadcasts, then every thread
+// solves each 16 x 16 diagonal block with DPP row broadcasts, then every thread
 // updates one remaining entry with the block's 16 values; two barriers per
 // block and direction.  The caller has synchronised the team after writing b.
 template <int NT, typename T>
@@ -418,11 +469,11 @@ __device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, i
                 lrow[c] = L[lr * ld + cc];
                 rd[c] = chol_rcp(diag[cc]);
             }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const T yc = lane_bcast(y, c) * rd[c];   // y_c = (lane c's value) / L_cc
+            static_for<0, 16>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                const T yc = row_bcast16<c>(y) * rd[c];   // y_c = (lane c's value) / L_cc
                 y = (l == c) ? yc : ((l > c) ? y - lrow[c] * yc : y);
-            }
+            });
             if (l < bs) x[c0 + l] = y;
         }
         __syncthreads();
@@ -454,11 +505,11 @@ __device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, i
             }
             // columns past the block update nobody (c < bs), so the lanes of
             // the block see exactly the bs steps
-#pragma unroll
-            for (int c = 15; c >= 0; --c) {
-                const T xc = lane_bcast(v, c) * rd[c];
+            static_for<0, 16>([&](auto ic) {
+                constexpr int c = 15 - decltype(ic)::value;
+                const T xc = row_bcast16<c>(v) * rd[c];
                 v = (l == c) ? xc : ((l < c && c < bs) ? v - lcol[c] * xc : v);
-            }
+            });
             if (l < bs) x[c0 + l] = v;
         }
         __syncthreads();
