@@ -378,6 +378,10 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
             for (int k = 0; k < 16; ++k) d[k] = hr[min(k, bs - 1)];
 #pragma unroll
             for (int k = 0; k < 16; ++k) asm volatile("" : "+v"(d[k]));
+            // every wave has its copy before wave 0 stores the factored rows
+            // (each wave's ok below comes from its own copy, so all must see
+            // the same block)
+            __syncthreads();
             // right-looking, one DPP row broadcast per entry; columns past bs
             // take pivot 1
             static_for<0, 16>([&](auto jc) {
