@@ -1,10 +1,11 @@
 // cs_chunk.hpp -- team kernels for instances whose J does not stay in LDS.
 //
 // One workgroup (NT = 64 for n <= 32, 256 otherwise) solves one instance at
-// a time.  Forward, per Newton step: the residuals r = J a - aref come
-// straight from global memory (eight lanes per row, many rows' loads in
-// flight, no staging), each wave listing its active rows (r < 0) in row
-// order; the listed rows are then gathered into LDS in chunks of CR rows
+// a time.  Forward, per Newton step: the residuals r = J a - aref (the
+// first step straight from global memory, eight lanes per row, many rows'
+// loads in flight, no staging; later steps from the previous step's second
+// pass, r_{k+1} = (J a_k - aref) + alpha_k J p_k), each wave listing its
+// active rows (r < 0) in row order; the listed rows are then gathered into LDS in chunks of CR rows
 // (row stride npa + 1, conflict-free) for the Newton-matrix contribution
 // J_A^T diag(D_A) J_A and the gradient J_A^T w -- inactive rows add nothing
 // to either.  In FP32 the contraction runs on the matrix cores
@@ -12,7 +13,8 @@
 // over the waves and interleaved per K-step, accumulators in registers), and
 // when n is not a multiple of 16 the residual rides in column n so the same
 // pass yields J^T w; in FP64 lanes accumulate lower-triangle entries on the
-// VALU.  A second direct pass forms q = J p for the line search.  The VJP
+// VALU.  A second direct pass forms q = J p for the line search and, from
+// the same read of J, J a - aref afresh for the next step.  The VJP
 // streams J through LDS in CR-row chunks (each thread holds its share of the
 // next chunk in registers while the current one is used).  H (row stride
 // npa + 1), the row arrays r, q, D, aref and the chunk buffer live in LDS; M
@@ -31,7 +33,7 @@ __host__ __device__ inline int round16(int n) { return (n + 15) & ~15; }
 template <typename T>
 struct ChLds {
     T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *red;
-    T *r, *q, *Dv, *ar, *Jc, *Wc, *Wr;
+    T *r, *q, *Dv, *ar, *rx, *Jc, *Wc, *Wr;   // rx: forward, J a_k - aref from pass B
     T *Lw;          // weights of the chunk's active rows, compacted per wave
     int *Lr, *Lc;   // their chunk rows, and the padded count per wave
     int *Li, *Ln;   // forward: each wave's active rows (row order), and their counts
@@ -46,12 +48,12 @@ __host__ __device__ inline int ch_list_cap(int mmax, int NT) {
 }
 
 // H (npa x (npa + 1)), eight n-vectors and the diagonal, reduction scratch,
-// four row arrays, the chunk (CR x (npa + 1)), two chunk-row arrays, the
+// five row arrays, the chunk (CR x (npa + 1)), two chunk-row arrays, the
 // per-wave active-row lists, A.
 __host__ __device__ inline size_t ch_lds_bytes(int npa, int mmax, int NT, size_t s) {
     const size_t ld = (size_t)npa + 1;
     const size_t nT = (size_t)npa * ld + 9 * (size_t)npa + 16 * (size_t)(NT / 64) +
-                      4 * (size_t)mmax + CR * ld + 4 * CR + 8;
+                      5 * (size_t)mmax + CR * ld + 4 * CR + 8;
     const size_t lists = 4 * ((size_t)(NT / 64) * ch_list_cap(mmax, NT) + 8);
     return nT * s + lists + (size_t)mmax + 64;
 }
@@ -83,6 +85,7 @@ __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int 
     L.q = p; p += mmax;
     L.Dv = p; p += mmax;
     L.ar = p; p += mmax;
+    L.rx = p; p += mmax;
     L.Jc = p; p += (size_t)CR * (npa + 1);
     L.Wc = p; p += CR;
     L.Wr = p; p += CR;
@@ -246,6 +249,68 @@ __device__ inline void ch_rows_dot(const T *__restrict__ J, int n, int m, const 
         else if (n <= 96) ch_rows_dot_t<NT, 12>(J, n, m, x, fn);
         else ch_rows_dot_t<NT, 16>(J, n, m, x, fn);
     }
+}
+
+// Two dot products per row from one read of J: fn(i, J_i . x, J_i . y).
+template <int NT, int CPL, typename T, typename Fn>
+__device__ inline void ch_rows_dot2_t(const T *__restrict__ J, int n, int m, const T *x,
+                                      const T *y, Fn &fn) {
+    constexpr int RPB = NT / 8, UN = 32 / CPL > 1 ? 32 / CPL : 1;
+    const int part = threadIdx.x & 7, oct = threadIdx.x >> 3;
+    T xv[CPL], yv[CPL];
+    int cl[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int c = part + 8 * k;
+        xv[k] = c < n ? x[c] : T(0);
+        yv[k] = c < n ? y[c] : T(0);
+        cl[k] = min(c, n - 1);
+    }
+    for (int b0 = 0; b0 < m; b0 += UN * RPB) {
+        T v[UN][CPL];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const T *row = J + (int64_t)min(b0 + u * RPB + oct, m - 1) * n;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) v[u][k] = row[cl[k]];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            T sx = T(0), sy = T(0);
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                sx += v[u][k] * xv[k];
+                sy += v[u][k] * yv[k];
+            }
+            fn(b0 + u * RPB + oct, osum8(sx), osum8(sy));
+        }
+    }
+}
+
+template <int NT, typename T, typename Fn>
+__device__ inline void ch_rows_dot2(const T *__restrict__ J, int n, int m, const T *x, const T *y,
+                                    Fn &&fn) {
+    if constexpr (NT == 64) {
+        ch_rows_dot2_t<NT, 4>(J, n, m, x, y, fn);
+    } else {
+        if (n <= 32) ch_rows_dot2_t<NT, 4>(J, n, m, x, y, fn);
+        else if (n <= 64) ch_rows_dot2_t<NT, 8>(J, n, m, x, y, fn);
+        else if (n <= 96) ch_rows_dot2_t<NT, 12>(J, n, m, x, y, fn);
+        else ch_rows_dot2_t<NT, 16>(J, n, m, x, y, fn);
+    }
+}
+
+// Visit the rows without reading J, every lane taking one: each wave meets
+// the rows ch_rows_dot gives it (rows 8 w .. 8 w + 7 of each block of NT / 8)
+// in the same order -- lane 8 b + j takes row j of the wave's eight in block
+// b of a group of eight blocks -- so lists built in lane order come out the
+// same.  fn(i) runs on every lane (rows i >= m included).
+template <int NT, typename Fn>
+__device__ inline void ch_rows_each(int m, Fn &&fn) {
+    constexpr int RPB = NT / 8;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nblk = (m + RPB - 1) / RPB;
+    for (int b0 = 0; b0 < nblk; b0 += 8) fn((b0 + (lane >> 3)) * RPB + 8 * w + (lane & 7));
 }
 
 // Per-thread partial of J^T x over the chunks: column fj, rows fp, fp + fparts, ...
@@ -639,24 +704,27 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 for (int l = 0; l < n; ++l) s += Mk[l * n + j] * (L.a[l] - L.a0[l]);
                 L.u[j] = s;
             }
-            T step_inf = T(-1);
+            T step_inf = T(-1), alpha_prev = T(0);
             int lsfail = 0;
             for (k = 0;; ++k) {
                 // pass A: r, A, F = M (a - a0) + J^T w and H = M + J^T diag(D o A) J.
-                // Residuals straight from global memory; each wave lists its
-                // active rows in row order; the listed rows are then gathered
-                // into LDS chunks for the contraction and J^T w (inactive
-                // rows add nothing to either).
+                // The first step's residuals come straight from global memory;
+                // later ones from the previous step's pass B, which read J
+                // once for both J a_k and J p_k: r_{k+1} = (J a_k - aref) +
+                // alpha_k J p_k (one rounding from the direct product, never
+                // accumulated across steps).  Each wave lists its active rows
+                // in row order; the listed rows are then gathered into LDS
+                // chunks for the contraction and J^T w (inactive rows add
+                // nothing to either).
                 acc.zero();
                 cs.plan(n);
                 bool changed = false, nonfin = false;
                 {
                     int cntw = 0;   // wave-uniform
                     int *lw = L.Li + (tid >> 6) * cap;
-                    ch_rows_dot<NT>(J, n, m, L.a, [&](int i, T s) {
+                    auto visit = [&](int i, bool mine, T r) {
                         bool an = false;
-                        if ((tid & 7) == 0 && i < m) {
-                            const T r = s - L.ar[i];
+                        if (mine) {
                             nonfin |= !finite_val(r);
                             an = r < T(0);
                             changed |= an != (L.A[i] != 0);
@@ -669,7 +737,18 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                                           (uint32_t)(bal >> 32),
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = i;
                         cntw += (int)__builtin_popcountll(bal);
-                    });
+                    };
+                    if (k == 0) {
+                        ch_rows_dot<NT>(J, n, m, L.a, [&](int i, T s) {
+                            const bool mine = (tid & 7) == 0 && i < m;
+                            visit(i, mine, mine ? s - L.ar[i] : T(0));
+                        });
+                    } else {
+                        ch_rows_each<NT>(m, [&](int i) {
+                            const bool mine = i < m;
+                            visit(i, mine, mine ? L.rx[i] + alpha_prev * L.q[i] : T(0));
+                        });
+                    }
                     if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
                 }
                 if (__syncthreads_or(k == 0 && nonfin)) { st = ST_NONFINITE; break; }
@@ -721,9 +800,16 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
                 team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
-                // pass B: q = J p (straight from global memory), and v = M p
-                ch_rows_dot<NT>(J, n, m, L.p, [&](int i, T s) {
-                    if ((tid & 7) == 0 && i < m) L.q[i] = s;
+                // pass B (straight from global memory): q = J p and, from the
+                // same read of J, J a - aref afresh for the next step's
+                // residuals (kept apart from r: the line search works with the
+                // r that formed F and p, so p stays a descent direction); and
+                // v = M p
+                ch_rows_dot2<NT>(J, n, m, L.a, L.p, [&](int i, T sa, T sp) {
+                    if ((tid & 7) == 0 && i < m) {
+                        L.rx[i] = sa - L.ar[i];
+                        L.q[i] = sp;
+                    }
                 });
                 T c0 = T(0), b0 = T(0);
                 for (int j = tid; j < n; j += NT) {
@@ -747,6 +833,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 const T alpha = team_line_search<NT>(m, L.r, L.q, L.Dv, c0, b0, L.red, bits,
                                                      cpiece, fl);
                 lsfail |= fl;
+                alpha_prev = alpha;
                 T si = T(0);
                 for (int j = tid; j < n; j += NT) {
                     const T s = alpha * L.p[j];
