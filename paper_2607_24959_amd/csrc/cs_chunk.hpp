@@ -5,21 +5,21 @@
 // first step straight from global memory, eight lanes per row, many rows'
 // loads in flight, no staging; later steps from the previous step's second
 // pass, r_{k+1} = (J a_k - aref) + alpha_k J p_k), each wave listing its
-// active rows (r < 0) in row order; the listed rows are then gathered into LDS in chunks of CR rows
-// (row stride npa + 1, conflict-free) for the Newton-matrix contribution
-// J_A^T diag(D_A) J_A and the gradient J_A^T w -- inactive rows add nothing
-// to either.  In FP32 the contraction runs on the matrix cores
-// (v_mfma_f32_16x16x4f32 on 16 x 16 tiles of the lower triangle, tiles spread
-// over the waves and interleaved per K-step, accumulators in registers), and
-// when n is not a multiple of 16 the residual rides in column n so the same
-// pass yields J^T w; in FP64 lanes accumulate lower-triangle entries on the
-// VALU.  A second direct pass forms q = J p for the line search and, from
-// the same read of J, J a - aref afresh for the next step.  The VJP
-// streams J through LDS in CR-row chunks (each thread holds its share of the
-// next chunk in registers while the current one is used).  H (row stride
-// npa + 1), the row arrays r, q, D, aref and the chunk buffer live in LDS; M
-// stays in global memory (read column-wise, coalesced, as a symmetric
-// matrix).
+// active rows (r < 0) in row order; the listed rows are then gathered into
+// LDS in chunks of CR rows (row stride npa + 1, conflict-free) for the
+// Newton-matrix contribution J_A^T diag(D_A) J_A and the gradient J_A^T w --
+// inactive rows add nothing to either.  In FP32 the contraction runs on the
+// matrix cores (v_mfma_f32_16x16x4f32 on 16 x 16 tiles of the lower
+// triangle, tiles spread over the waves and interleaved per K-step,
+// accumulators in registers), and when n is not a multiple of 16 the
+// residual rides in column n so the same pass yields J^T w; in FP64 lanes
+// accumulate lower-triangle entries on the VALU.  A second direct pass forms
+// q = J p for the line search and, from the same read of J, J a - aref
+// afresh for the next step.  The VJP reads only the active rows of J (the
+// saved A*), gathered the same way.  H (row stride npa + 1), the row arrays
+// and the chunk buffer live in LDS; the FP32 forward also keeps M there when
+// it fits, otherwise M is read from global memory column-wise (coalesced, as
+// a symmetric matrix).
 #pragma once
 
 #include "cs_device.hpp"
@@ -98,44 +98,6 @@ __device__ inline ChLds<T> ch_carve(unsigned char *smem, int npa, int mmax, int 
     L.A = reinterpret_cast<uint8_t *>(ip);
     return L;
 }
-
-// A thread's share of one chunk (CR rows of a row-major J with n <= 128
-// columns; n <= 32 when NT = 64): elements tid + NT s of the chunk, held in
-// registers between the global load and the LDS store.  Elements past the
-// last row of J read as zero.
-template <int NT, typename T>
-struct ChStage {
-    static constexpr int MAXE = CR * (NT == 64 ? 32 : 128) / NT;
-    T v[MAXE];
-    int rho0, j0, drho, dj;
-
-    __device__ inline void plan(int n) {
-        rho0 = (int)threadIdx.x / n;
-        j0 = (int)threadIdx.x - rho0 * n;
-        drho = NT / n;
-        dj = NT - drho * n;
-    }
-    __device__ inline void load(const T *__restrict__ J, int n, int m, int c) {
-        const int r0 = c * CR;
-        const int cnt = min(CR, m - r0) * n;
-        const T *src = J + (int64_t)r0 * n;
-#pragma unroll
-        for (int s = 0; s < MAXE; ++s) {
-            const int e = (int)threadIdx.x + s * NT;
-            v[s] = e < cnt ? src[e] : T(0);
-        }
-    }
-    __device__ inline void store(int n, int ldj, T *Jc) const {
-        int rho = rho0, j = j0;
-#pragma unroll
-        for (int s = 0; s < MAXE; ++s) {
-            if (rho < CR) Jc[rho * ldj + j] = v[s];
-            rho += drho;
-            j += dj;
-            if (j >= n) { j -= n; ++rho; }
-        }
-    }
-};
 
 // Dot products of the chunk's rows with one or two LDS vectors; NT / CR
 // lanes per row, two partial sums per lane, combined with butterflies.
@@ -556,6 +518,16 @@ __device__ inline T team_max(T v, T *sred) {
     return v;
 }
 
+// Entry pos (< total) of the concatenated per-wave active-row lists.
+template <int NT, typename T>
+__device__ inline int ch_list_at(const ChLds<T> &L, const int (&off)[NT / 64], int cap, int pos) {
+    int w = 0, o = 0;
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q)
+        if (pos >= off[q]) { w = q; o = off[q]; }
+    return L.Li[w * cap + pos - o];
+}
+
 // Chunk c of the active-row list (entries c CR .. c CR + CR - 1 of the
 // per-wave lists taken wave after wave) into LDS: slot s of Jc gets the
 // row of J, Wc[s] its weight D_i, Wr[s] = D_i r_i and, when fused, Jc[s][n]
@@ -573,14 +545,7 @@ __device__ inline void ch_gather_t(const T *__restrict__ J, int n, int ldj, int 
 #pragma unroll
     for (int g = 0; g < GP; ++g) {
         const int pos = c * CR + g * RPB + oct;
-        int row = -1;
-        if (pos < total) {
-            int w = 0, o = 0;
-#pragma unroll
-            for (int q = 1; q < NW; ++q)
-                if (pos >= off[q]) { w = q; o = off[q]; }
-            row = L.Li[w * cap + pos - o];
-        }
+        const int row = pos < total ? ch_list_at<NT>(L, off, cap, pos) : -1;
         rows[g] = row;
         const T *src = J + (int64_t)max(row, 0) * n;
 #pragma unroll
@@ -868,6 +833,11 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
     }
 }
 
+// IFT VJP (eq. 17).  Every row-level term carries A*: an inactive row has
+// arefbar = Dbar = 0 and Jbar_i = -(0 lambda + 0 a), and adds nothing to
+// J^T (D o A* o J v).  So only the active rows of J are read, gathered into
+// LDS in chunks as in the forward; the inactive rows' outputs are written
+// without touching J.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
     BatchView bv, int count, int npa, int mmax, const T *__restrict__ gfac,
@@ -880,14 +850,12 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
     const ChLds<T> L = ch_carve<T>(smem, npa, mmax, NT);
     const int tid = threadIdx.x;
     const int ldj = npa + 1, ldh = npa + 1;
+    const int cap = ch_list_cap(mmax, NT);
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
         const int n = I.n, m = I.m;
-        const int nch = (m + CR - 1) / CR;
         const T *M = gM + I.onn, *J = gJ + I.omn;
         const T *fac = gfac + fac_offset(I);
-        ChStage<NT, T> stg;
-        stg.plan(n);
         ChColSum<NT, T> cs;
         {
             TriWalk tw;
@@ -907,81 +875,112 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
             L.Dv[i] = gD[I.om + i];
             L.ar[i] = garef[I.om + i];
             L.A[i] = gmask[I.om + i];
+            L.r[i] = T(0);   // read (not used) by the gather
         }
         __syncthreads();
+        // the active rows, listed per wave in row order
+        {
+            int cntw = 0;   // wave-uniform
+            int *lw = L.Li + (tid >> 6) * cap;
+            ch_rows_each<NT>(m, [&](int i) {
+                const bool an = i < m && L.A[i] != 0;
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(an);
+                if (an)
+                    lw[cntw + (int)__builtin_amdgcn_mbcnt_hi(
+                                  (uint32_t)(bal >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = i;
+                cntw += (int)__builtin_popcountll(bal);
+            });
+            if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
+        }
+        __syncthreads();
+        int off[NT / 64], total = 0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) {
+            off[q] = total;
+            total += L.Ln[q];
+        }
+        const int ncha = (total + CR - 1) / CR;
         // lambda = H^{-1} abar with one refinement step, H v = M v + J^T (D o A* o J v)
         team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n, ldh);
         cs.plan(n);
-        if (nch > 0) stg.load(J, n, m, 0);
-        for (int c = 0; c < nch; ++c) {
-            __syncthreads();
-            stg.store(n, ldj, L.Jc);
-            if (c + 1 < nch) stg.load(J, n, m, c + 1);
-            __syncthreads();
+        for (int c = 0; c < ncha; ++c) {
+            ch_gather<NT>(J, n, ldj, c, total, off, cap, false, L);   // Wc = D of each row
             int rho, part;
-            const T s = ch_row_dot<NT>(n, ldj, L.Jc, L.u, rho, part);
-            const int i = c * CR + rho;
-            if (part == 0) L.Wr[rho] = (i < m && L.A[i]) ? L.Dv[i] * s : T(0);
+            const T sv = ch_row_dot<NT>(n, ldj, L.Jc, L.u, rho, part);
+            if (part == 0) L.Wr[rho] = L.Wc[rho] * sv;
             __syncthreads();
             cs.add_chunk(ldj, L.Jc, L.Wr);
         }
         cs.finish(n, ldj, L.Jc, nullptr, L.F);
         for (int j = tid; j < n; j += NT) {
-            T s = gabar[I.on + j] - L.F[j];
+            T sv = gabar[I.on + j] - L.F[j];
 #pragma unroll 16
-            for (int l = 0; l < n; ++l) s -= M[(int64_t)l * n + j] * L.u[l];
-            L.y[j] = s;
+            for (int l = 0; l < n; ++l) sv -= M[(int64_t)l * n + j] * L.u[l];
+            L.y[j] = sv;
         }
         __syncthreads();
         team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
         for (int j = tid; j < n; j += NT) L.u[j] += L.p[j];
-        // per-row cotangents and J-bar, chunk by chunk
-        if (nch > 0) stg.load(J, n, m, 0);
-        for (int c = 0; c < nch; ++c) {
-            __syncthreads();
-            stg.store(n, ldj, L.Jc);
-            if (c + 1 < nch) stg.load(J, n, m, c + 1);
-            __syncthreads();
+        // per-row cotangents and J-bar of the active rows, chunk by chunk
+        for (int c = 0; c < ncha; ++c) {
+            ch_gather<NT>(J, n, ldj, c, total, off, cap, false, L);
             int rho, part;
             T ja, sig;
             ch_row_dot2<NT>(n, ldj, L.Jc, L.a, L.u, ja, sig, rho, part);
-            const int i = c * CR + rho;
             if (part == 0) {
-                if (i < m) {
-                    const bool act = L.A[i] != 0;
+                const int pos = c * CR + rho;
+                if (pos < total) {
+                    const int i = ch_list_at<NT>(L, off, cap, pos);
                     const T r = ja - L.ar[i];
-                    const T wv = act ? L.Dv[i] * r : T(0);
-                    const T arb = act ? L.Dv[i] * sig : T(0);
+                    const T arb = L.Dv[i] * sig;
                     if (garefbar) garefbar[I.om + i] = arb;
-                    if (gDbar) gDbar[I.om + i] = act ? -r * sig : T(0);
-                    L.Wc[rho] = wv;
+                    if (gDbar) gDbar[I.om + i] = -r * sig;
+                    L.Wc[rho] = L.Dv[i] * r;
                     L.Wr[rho] = arb;
+                    L.Lr[rho] = i;
                 } else {
-                    L.Wc[rho] = T(0);
-                    L.Wr[rho] = T(0);
+                    L.Lr[rho] = -1;
                 }
             }
             __syncthreads();
             if (gJbar) {
-                const int r0 = c * CR;
-                const int cnt = min(CR, m - r0) * n;
-                T *dst = gJbar + I.omn + (int64_t)r0 * n;
                 int rr = tid / n, jj = tid - rr * n;
                 const int dr = NT / n, dc = NT - dr * n;
-                for (int e = tid; e < cnt; e += NT) {
-                    dst[e] = -(L.Wc[rr] * L.u[jj] + L.Wr[rr] * L.a[jj]);
+                for (int e = tid; e < CR * n; e += NT) {
+                    const int row = L.Lr[rr];
+                    if (row >= 0)
+                        gJbar[I.omn + (int64_t)row * n + jj] = -(L.Wc[rr] * L.u[jj] + L.Wr[rr] * L.a[jj]);
                     rr += dr;
                     jj += dc;
                     if (jj >= n) { jj -= n; ++rr; }
                 }
             }
         }
+        // the inactive rows: no read of J
+        for (int i = tid; i < m; i += NT) {
+            if (!L.A[i]) {
+                if (garefbar) garefbar[I.om + i] = T(0);
+                if (gDbar) gDbar[I.om + i] = T(0);
+            }
+        }
+        if (gJbar) {
+            T *dst = gJbar + I.omn;
+            int rr = tid / n, jj = tid - rr * n;
+            const int dr = NT / n, dc = NT - dr * n;
+            for (int e = tid; e < m * n; e += NT) {
+                if (!L.A[rr]) dst[e] = -(T(0) * L.u[jj] + T(0) * L.a[jj]);
+                rr += dr;
+                jj += dc;
+                if (jj >= n) { jj -= n; ++rr; }
+            }
+        }
         if (ga0bar) {
             for (int j = tid; j < n; j += NT) {
-                T s = T(0);
+                T sv = T(0);
 #pragma unroll 16
-                for (int l = 0; l < n; ++l) s += M[(int64_t)l * n + j] * L.u[l];
-                ga0bar[I.on + j] = s;
+                for (int l = 0; l < n; ++l) sv += M[(int64_t)l * n + j] * L.u[l];
+                ga0bar[I.on + j] = sv;
             }
         }
         if (gMbar) {
