@@ -217,15 +217,34 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         auto factor_nc = [&](auto ncc, float (&h)[NPA]) -> bool {
             constexpr int NC = decltype(ncc)::value;
             bool ok = true;
+            if constexpr (NC == 16) {
+                // every row in lanes 0..15: column entries by DPP row
+                // broadcast (they stay in vector registers; lanes 16..63 hold
+                // zero rows and broadcast zeros among themselves); the pivot
+                // by a lane read, so ok stays wave-uniform
+                static_for<0, 16>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const float pv = wave_lane(h[j], j);   // unconditional
+                    const bool live = j < n;
+                    const float piv = live ? pv : 1.f;
+                    ok = ok && (!live || piv > 0.f);
+                    h[j] *= __builtin_amdgcn_rsqf(piv);
+                    static_for<j + 1, 16>([&](auto kc) {
+                        constexpr int k2 = decltype(kc)::value;
+                        h[k2] -= h[j] * row_bcast16<k2>(h[j]);
+                    });
+                });
+            } else {
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const bool live = j < n;
-                const float piv = live ? wave_lane(h[j], j) : 1.f;
-                ok = ok && (!live || piv > 0.f);
-                // lane j: the pivot times 1 / sqrt(pivot) = L_jj, final from here
-                h[j] *= __builtin_amdgcn_rsqf(piv);
+                for (int j = 0; j < NC; ++j) {
+                    const bool live = j < n;
+                    const float piv = live ? wave_lane(h[j], j) : 1.f;
+                    ok = ok && (!live || piv > 0.f);
+                    // lane j: the pivot times 1 / sqrt(pivot) = L_jj, final from here
+                    h[j] *= __builtin_amdgcn_rsqf(piv);
 #pragma unroll
-                for (int k2 = j + 1; k2 < NC; ++k2) h[k2] -= h[j] * wave_lane(h[j], k2);
+                    for (int k2 = j + 1; k2 < NC; ++k2) h[k2] -= h[j] * wave_lane(h[j], k2);
+                }
             }
             // lane l's diagonal is h[l]; the updates also reached entries right
             // of it (never read above).  One pass picks the diagonal and clears
@@ -392,8 +411,15 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 float y = -Fj;          // zero in lanes >= n
                 with_nc([&](auto ncc) {
                     constexpr int NC = decltype(ncc)::value;
+                    if constexpr (NC == 16) {
+                        static_for<0, 16>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            y -= h[j] * row_bcast16<j>(y * idl);
+                        });
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < NC; ++j) y -= h[j] * wave_lane(y * idl, j);
+                        for (int j = 0; j < NC; ++j) y -= h[j] * wave_lane(y * idl, j);
+                    }
                     return 0;
                 });
                 y *= idl;
@@ -407,8 +433,15 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 with_nc([&](auto ncc) {
                     constexpr int NC = decltype(ncc)::value;
                     const float *col = Hs + min(l, NPA - 1);    // L_jl at col[j * LD]
+                    if constexpr (NC == 16) {
+                        static_for<0, 16>([&](auto ic) {
+                            constexpr int j = 15 - decltype(ic)::value;
+                            pj -= col[j * LD] * row_bcast16<j>(pj * idl);
+                        });
+                    } else {
 #pragma unroll
-                    for (int j = NC - 1; j >= 0; --j) pj -= col[j * LD] * wave_lane(pj * idl, j);
+                        for (int j = NC - 1; j >= 0; --j) pj -= col[j * LD] * wave_lane(pj * idl, j);
+                    }
                     return 0;
                 });
                 pj = (l < n) ? pj * idl : 0.f;
