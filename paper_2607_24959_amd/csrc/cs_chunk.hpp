@@ -33,7 +33,7 @@ __host__ __device__ inline int round16(int n) { return (n + 15) & ~15; }
 template <typename T>
 struct ChLds {
     T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *red;
-    T *r, *q, *Dv, *ar, *rx, *Jc, *Wc, *Wr;   // rx: forward, J a_k - aref from pass B
+    T *r, *q, *Dv, *ar, *rx, *Jc, *Wc, *Wr;   // rx: forward, J a_k from pass B
     T *Lw;          // weights of the chunk's active rows, compacted per wave
     int *Lr, *Lc;   // their chunk rows, and the padded count per wave
     int *Li, *Ln;   // forward: each wave's active rows (row order), and their counts
@@ -400,17 +400,26 @@ template <int NT> struct ChAcc<float, NT> {
             default: break;
         }
     }
-    // H (lower, stride ldh) = M + acc
+    // H (lower, stride ldh) = M + acc.  Each tile's M entries are read
+    // before any store, from clamped (in-bounds) addresses; the empty asm
+    // keeps the compiler from sinking each read into a masked branch of its
+    // own that waits for it.
     __device__ inline void store(int n, int ldh, const float *__restrict__ M, float *H) const {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int kq = lane >> 4, idx = lane & 15;
 #pragma unroll
         for (int s = 0; s < MAXT; ++s) {
             if (wave + NW * s < ntiles) {
+                const int col = 16 * tj[s] + idx, cc = min(col, n - 1);
+                float mv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) mv[r] = M[min(16 * ti[s] + 4 * kq + r, n - 1) * n + cc];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) asm volatile("" : "+v"(mv[r]));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * ti[s] + 4 * kq + r, col = 16 * tj[s] + idx;
-                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + M[row * n + col];
+                    const int row = 16 * ti[s] + 4 * kq + r;
+                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + mv[r];
                 }
             }
         }
@@ -424,11 +433,18 @@ template <int NT> struct ChAcc<float, NT> {
 #pragma unroll
         for (int s = 0; s < MAXT; ++s) {
             if (wave + NW * s < ntiles) {
+                const int col = 16 * tj[s] + idx, cc = min(col, n - 1);
+                float mv[4], uv = u[cc];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) mv[r] = M[min(16 * ti[s] + 4 * kq + r, n - 1) * n + cc];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) asm volatile("" : "+v"(mv[r]));
+                asm volatile("" : "+v"(uv));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * ti[s] + 4 * kq + r, col = 16 * tj[s] + idx;
-                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + M[row * n + col];
-                    if (row == n && col < n) F[col] = acc[s][r] + u[col];
+                    const int row = 16 * ti[s] + 4 * kq + r;
+                    if (row < n && col <= row) H[row * ldh + col] = acc[s][r] + mv[r];
+                    if (row == n && col < n) F[col] = acc[s][r] + uv;
                 }
             }
         }
@@ -688,11 +704,13 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     int cntw = 0;   // wave-uniform
                     int *lw = L.Li + (tid >> 6) * cap;
                     auto visit = [&](int i, bool mine, T r) {
+                        int was = L.A[min(i, m - 1)];
+                        asm volatile("" : "+v"(was));   // read with the others, not under mine
                         bool an = false;
                         if (mine) {
                             nonfin |= !finite_val(r);
                             an = r < T(0);
-                            changed |= an != (L.A[i] != 0);
+                            changed |= an != (was != 0);
                             L.A[i] = an;
                             L.r[i] = r;
                         }
@@ -703,15 +721,18 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] = i;
                         cntw += (int)__builtin_popcountll(bal);
                     };
+                    // (row reads from clamped indices, unconditional: a read
+                    // under the lane's predicate would become a branch of its
+                    // own that waits for it)
                     if (k == 0) {
                         ch_rows_dot<NT>(J, n, m, L.a, [&](int i, T s) {
                             const bool mine = (tid & 7) == 0 && i < m;
-                            visit(i, mine, mine ? s - L.ar[i] : T(0));
+                            visit(i, mine, s - L.ar[min(i, m - 1)]);
                         });
                     } else {
                         ch_rows_each<NT>(m, [&](int i) {
-                            const bool mine = i < m;
-                            visit(i, mine, mine ? L.rx[i] + alpha_prev * L.q[i] : T(0));
+                            const int ic = min(i, m - 1);
+                            visit(i, i < m, (L.rx[ic] - L.ar[ic]) + alpha_prev * L.q[ic]);
                         });
                     }
                     if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
@@ -766,13 +787,12 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                 __syncthreads();
                 team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
                 // pass B (straight from global memory): q = J p and, from the
-                // same read of J, J a - aref afresh for the next step's
-                // residuals (kept apart from r: the line search works with the
-                // r that formed F and p, so p stays a descent direction); and
-                // v = M p
+                // same read of J, J a afresh for the next step's residuals
+                // (kept apart from r: the line search works with the r that
+                // formed F and p, so p stays a descent direction); and v = M p
                 ch_rows_dot2<NT>(J, n, m, L.a, L.p, [&](int i, T sa, T sp) {
                     if ((tid & 7) == 0 && i < m) {
-                        L.rx[i] = sa - L.ar[i];
+                        L.rx[i] = sa;
                         L.q[i] = sp;
                     }
                 });

@@ -276,11 +276,18 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         };
         // the lane's row of `src`, lower triangle and diagonal (zero elsewhere
         // and in lanes >= n), as the starting h of a factorisation
+        // (every value read before any select: the empty asm keeps the
+        // compiler from sinking each LDS read into a branch of its own that
+        // waits for it)
         auto lower_row = [&](float (&h)[NPA], auto &&src) {
             const int lo = opaque_lane(l);
             const bool rowok = lo < n;
 #pragma unroll
-            for (int c = 0; c < NPA; ++c) h[c] = (rowok && c <= lo) ? src(c) : 0.f;
+            for (int c = 0; c < NPA; ++c) h[c] = src(c);
+#pragma unroll
+            for (int c = 0; c < NPA; ++c) asm volatile("" : "+v"(h[c]));
+#pragma unroll
+            for (int c = 0; c < NPA; ++c) h[c] = (rowok && c <= lo) ? h[c] : 0.f;
         };
 
         int st = 0, k = 0;
