@@ -238,7 +238,8 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 #pragma unroll
                 for (int j = 0; j < NC; ++j) {
                     const bool live = j < n;
-                    const float piv = live ? wave_lane(h[j], j) : 1.f;
+                    const float pv = wave_lane(h[j], j);   // unconditional: no branch around it
+                    const float piv = live ? pv : 1.f;
                     ok = ok && (!live || piv > 0.f);
                     // lane j: the pivot times 1 / sqrt(pivot) = L_jj, final from here
                     h[j] *= __builtin_amdgcn_rsqf(piv);
