@@ -34,9 +34,10 @@ template <typename T>
 struct ChLds {
     T *H, *diag, *a, *a0, *F, *p, *y, *v, *u, *red;
     T *r, *q, *Dv, *ar, *rx, *Jc, *Wc, *Wr;   // rx: forward, J a_k from pass B
-    T *Lw;          // weights of the chunk's active rows, compacted per wave
-    int *Lr, *Lc;   // their chunk rows, and the padded count per wave
-    int *Li, *Ln;   // forward: each wave's active rows (row order), and their counts
+    T *Lw;          // (not used: the contraction takes its weights from Wc)
+    int *Lr, *Lc;   // slot rows (forward: Lr[e] = e; VJP: the slot's row of J), and
+                    // each wave segment's slot count padded to whole K-steps
+    int *Li, *Ln;   // each wave's active rows (row order), and their counts
     uint8_t *A;
 };
 
@@ -346,12 +347,15 @@ template <int NT> struct ChAcc<float, NT> {
 #pragma unroll
         for (int s = 0; s < MAXT; ++s) acc[s] = chf4{0.f, 0.f, 0.f, 0.f};
     }
-    // acc += J_c^T diag(D o A) J_c over the chunk's active rows: every wave
-    // owns a segment of CR / NW consecutive chunk rows, whose active rows
-    // (and weights) were compacted into Lr / Lw with the count padded to
-    // whole K-steps (pad rows carry weight 0).  The wave's tile count is a
-    // compile-time constant in each instance of the body, so a K-step issues
-    // all its LDS loads, then all its MFMAs, with no branches in between.
+    // acc += J_c^T diag(D o A) J_c over the chunk's gathered active rows
+    // (slot e holds chunk row Lr[e] = e with weight Lw[e]; slots past the
+    // list's end are zero rows of weight 0), walked in CR / NW-slot segments,
+    // each up to its count padded to whole K-steps (Lc).  The row index is
+    // read rather than taken as e: dropping that read let the compiler hoist
+    // enough loads to spill the kernel's registers.  The wave's tile count is
+    // a compile-time constant in each instance of the body, so a K-step
+    // issues all its LDS loads, then all its MFMAs, with no branches in
+    // between.
     template <int TPW>
     __device__ inline void add_chunk_t(int ldj, const float *Jc, const int *Lr, const float *Lw,
                                        const int *Lc) {
