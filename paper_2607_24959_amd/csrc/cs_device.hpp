@@ -563,14 +563,15 @@ __device__ inline T team_line_search(int m, const T *r, const T *q, const T *D, 
     T c, b;
     {
         T v[2] = {T(0), T(0)};
+        // every row's values read, then selected (a read under the row's
+        // predicate would be a branch waiting on it); a row off the piece adds
+        // +0, which leaves the sums bitwise as skipping it would
         for (int i = tid, jj = 0; i < m; i += NT, ++jj) {
-            const T qi = q[i], ri = r[i];
-            if (ri + t * qi < T(0)) {
-                const T dq = D[i] * qi;
-                v[0] += dq * qi;
-                v[1] += dq * ri;
-                bits |= 1u << jj;
-            }
+            const T qi = q[i], ri = r[i], dq = D[i] * qi;
+            const bool pa = ri + t * qi < T(0);
+            v[0] += pa ? dq * qi : T(0);
+            v[1] += pa ? dq * ri : T(0);
+            bits |= (pa ? 1u : 0u) << jj;
         }
         team_sum<NT>(v, sred);
         c = c0 + v[0];
@@ -593,13 +594,11 @@ __device__ inline T team_line_search(int m, const T *r, const T *q, const T *D, 
         uint32_t nb = 0;
         T v[3] = {T(0), T(0), T(0)};
         for (int i = tid, jj = 0; i < m; i += NT, ++jj) {
-            const T qi = q[i], ri = r[i];
-            if (ri + cand * qi < T(0)) {
-                const T dq = D[i] * qi;
-                v[0] += dq * qi;
-                v[1] += dq * ri;
-                nb |= 1u << jj;
-            }
+            const T qi = q[i], ri = r[i], dq = D[i] * qi;
+            const bool pa = ri + cand * qi < T(0);
+            v[0] += pa ? dq * qi : T(0);
+            v[1] += pa ? dq * ri : T(0);
+            nb |= (pa ? 1u : 0u) << jj;
         }
         v[2] = T(__builtin_popcount(nb ^ bits));
         team_sum<NT>(v, sred);
