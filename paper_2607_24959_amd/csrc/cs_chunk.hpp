@@ -907,7 +907,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
             int cntw = 0;   // wave-uniform
             int *lw = L.Li + (tid >> 6) * cap;
             ch_rows_each<NT>(m, [&](int i) {
-                const bool an = i < m && L.A[i] != 0;
+                const bool an = i < m && L.A[min(i, m - 1)] != 0;   // read unconditionally
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(an);
                 if (an)
                     lw[cntw + (int)__builtin_amdgcn_mbcnt_hi(
@@ -969,15 +969,16 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
             }
             __syncthreads();
             if (gJbar) {
-                int rr = tid / n, jj = tid - rr * n;
-                const int dr = NT / n, dc = NT - dr * n;
-                for (int e = tid; e < CR * n; e += NT) {
-                    const int row = L.Lr[rr];
-                    if (row >= 0)
-                        gJbar[I.omn + (int64_t)row * n + jj] = -(L.Wc[rr] * L.u[jj] + L.Wr[rr] * L.a[jj]);
-                    rr += dr;
-                    jj += dc;
-                    if (jj >= n) { jj -= n; ++rr; }
+                // eight lanes per slot: the slot's row and weights read once,
+                // each lane writing every eighth entry of the row
+                const int part = tid & 7;
+                for (int sl = tid >> 3; sl < CR; sl += NT >> 3) {
+                    const int row = L.Lr[sl];
+                    if (row >= 0) {
+                        const T wv = L.Wc[sl], arb = L.Wr[sl];
+                        T *dst = gJbar + I.omn + (int64_t)row * n;
+                        for (int j = part; j < n; j += 8) dst[j] = -(wv * L.u[j] + arb * L.a[j]);
+                    }
                 }
             }
         }
@@ -989,14 +990,13 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
             }
         }
         if (gJbar) {
-            T *dst = gJbar + I.omn;
-            int rr = tid / n, jj = tid - rr * n;
-            const int dr = NT / n, dc = NT - dr * n;
-            for (int e = tid; e < m * n; e += NT) {
-                if (!L.A[rr]) dst[e] = -(T(0) * L.u[jj] + T(0) * L.a[jj]);
-                rr += dr;
-                jj += dc;
-                if (jj >= n) { jj -= n; ++rr; }
+            // eight lanes per row: the row's flag read once
+            const int part = tid & 7;
+            for (int i = tid >> 3; i < m; i += NT >> 3) {
+                if (!L.A[i]) {
+                    T *dst = gJbar + I.omn + (int64_t)i * n;
+                    for (int j = part; j < n; j += 8) dst[j] = -(T(0) * L.u[j] + T(0) * L.a[j]);
+                }
             }
         }
         if (ga0bar) {
