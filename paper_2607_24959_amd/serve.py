@@ -183,14 +183,24 @@ class Engine:
         self.list_pin = [torch.zeros(self.cap_list, dtype=torch.int32, pin_memory=pin)
                          for _ in range(2)]
         self.list_evt = [None, None]
+        self.list_ev_obj = [torch.cuda.Event(), torch.cuda.Event()] if pin else [None, None]
         self.ring = 0
         # the kernel launches of one tick touch disjoint slots, so they run
-        # concurrently on side streams (default priority) between the
-        # tick's pre and post kernels on the caller's stream
-        self.side = [torch.cuda.Stream(device=dev) for _ in range(3)] if pin else []
+        # concurrently on two lanes -- the caller's stream and one side
+        # stream (default priority) -- between the tick's pre and post kernels
+        # on the caller's stream.  One side stream: every fork or join costs
+        # the host a stream-wait call of ~12 us, and two lanes already hold
+        # the widest forward apart from the rest.
+        self.side = [torch.cuda.Stream(device=dev)] if pin else []
         self.ev_pre = torch.cuda.Event() if pin else None
         self.ev_side = [torch.cuda.Event() for _ in self.side]
         self.params = N.CsSolverParams(int(max_iter), 0, float(tol))
+        # raw pointers of the persistent buffers, made once
+        cp = lambda t: C.c_void_p(t.data_ptr())
+        self._p = dict(M=cp(self.M), J=cp(self.J), a0=cp(self.a0), aref=cp(self.aref),
+                       D=cp(self.D), a=cp(self.sol.a), state=cp(self.sol.state),
+                       status=cp(self.sol.status), iters=cp(self.sol.iters), abar=cp(self.abar),
+                       a0bar=cp(self.a0bar), arefbar=cp(self.arefbar))
         # host bookkeeping
         self.phase = np.full(S, -1, dtype=np.int64)   # -1 free; 0..W-1 forward; W..2W-1 backward
         self.cls = np.zeros(S, dtype=np.int64)        # kernel class of the slot's request
@@ -203,7 +213,16 @@ class Engine:
         self.keep_results = False
         self.max_active = 0
         self.ticks = 0
+        self._stream = None
         self.classes = self._class_table()
+        # one batch descriptor per class (the library reads it during the
+        # call, so it is reused; each launch sets its order list and count)
+        self.class_desc = []
+        for path, nmax, mmax in self.classes:
+            d = N.CsBatch()
+            C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
+            d.path, d.nv_max, d.nrows_max = path, nmax, mmax
+            self.class_desc.append(d)
 
     # ------------------------------------------------------------ setup
     def _class_table(self):
@@ -287,9 +306,13 @@ class Engine:
         if self.list_evt[self.ring] is not None:
             self.list_evt[self.ring].synchronize()      # its previous copy has been consumed
         buf[:len(flat)].numpy()[:] = flat
-        stream = torch.cuda.current_stream(self.device)
+        # the stream run_stream fixed for its run (looking it up costs the
+        # host ~12 us a call), else the current one
+        stream = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
         self.list_dev[:len(flat)].copy_(buf[:len(flat)], non_blocking=True)
-        ev = torch.cuda.Event()
+        ev = self.list_ev_obj[self.ring]
+        if ev is None:
+            ev = torch.cuda.Event()
         ev.record(stream)
         self.list_evt[self.ring] = ev
         self.ring ^= 1
@@ -300,34 +323,34 @@ class Engine:
         if adm_s:
             N.check(N.serve_admit(tb, self.pool.table, at(0), len(adm_s), st), "cs_serve_admit")
         N.check(N.serve_pre(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_pre")
-        vp = solver._vp
-        sol = self.sol
-        # longest launches first (forwards before VJPs, wider classes first),
-        # dealt round-robin over the caller's stream and the side streams
-        launches.sort(key=lambda L: (L[0] == "fwd", self.classes[L[1]][1], self.classes[L[1]][2]),
-                      reverse=True)
+        P = self._p
+        nst = self.sol.state.numel()
+        # longest launches first, each dealt to the less loaded of the two
+        # lanes by a latency estimate (a class launch of a few instances takes
+        # about one instance's solve time)
+        est = lambda L: ((2.0 * self.classes[L[1]][1] + 40.0) if L[0] == "fwd" else 20.0)
+        launches.sort(key=est, reverse=True)
         lanes = [stream] + (self.side if len(launches) > 1 else [])
-        lanes = lanes[:len(launches)]
+        load = [0.0] * len(lanes)
         if len(lanes) > 1:
             self.ev_pre.record(stream)
             for sd in lanes[1:]:
                 sd.wait_event(self.ev_pre)
-        for j, (kind, c, off, cnt) in enumerate(launches):
-            path, nmax, mmax = self.classes[c]
-            d = N.CsBatch()
-            C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
-            d.order, d.count, d.path = base + 4 * off, cnt, path
-            d.nv_max, d.nrows_max = nmax, mmax
-            ls = C.c_void_p(lanes[j % len(lanes)].cuda_stream) if lanes else st
+        lane_ptr = [C.c_void_p(x.cuda_stream) for x in lanes] if lanes else [st]
+        for kind, c, off, cnt in launches:
+            d = self.class_desc[c]
+            d.order, d.count = base + 4 * off, cnt
+            k = min(range(len(load)), key=load.__getitem__) if load else 0
+            if load:
+                load[k] += est((kind, c))
+            ls = lane_ptr[k]
             if kind == "vjp":
-                rc = N.ift_vjp(d, vp(sol.state), sol.state.numel(), vp(self.M), vp(self.J),
-                               vp(self.a0), vp(self.aref), vp(self.D), vp(sol.a), vp(self.abar),
-                               vp(self.a0bar), vp(self.arefbar), None, None, None, ls)
+                rc = N.ift_vjp(d, P["state"], nst, P["M"], P["J"], P["a0"], P["aref"], P["D"],
+                               P["a"], P["abar"], P["a0bar"], P["arefbar"], None, None, None, ls)
                 N.check(rc, "cs_ift_vjp(serve)")
             else:
-                rc = N.forward(d, self.params, vp(self.M), vp(self.J), vp(self.a0), vp(self.aref),
-                               vp(self.D), None, vp(sol.a), vp(sol.state), sol.state.numel(),
-                               vp(sol.status), vp(sol.iters), ls)
+                rc = N.forward(d, self.params, P["M"], P["J"], P["a0"], P["aref"], P["D"], None,
+                               P["a"], P["state"], nst, P["status"], P["iters"], ls)
                 N.check(rc, "cs_forward(serve)")
         for sd, ev in zip(lanes[1:], self.ev_side):
             ev.record(sd)
@@ -368,6 +391,7 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     pending = deque(reqs)
     engine.finished.clear()
     stream = torch.cuda.current_stream(engine.device)
+    engine._stream = stream
     # the loop allocates an event per tick; a cyclic-GC pass over the
     # growing heap would stall the host for milliseconds mid-stream
     gc_was_enabled = gc.isenabled()
@@ -394,6 +418,7 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
             tick_events.append(ev)
             solves += n_work
     torch.cuda.synchronize()
+    engine._stream = None
     if gc_was_enabled:
         gc.enable()
     t_end = [start.elapsed_time(e) / 1e3 for e in tick_events]     # seconds since start
