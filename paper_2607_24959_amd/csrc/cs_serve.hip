@@ -1,9 +1,12 @@
 // cs_serve.hip -- device steps of the MPC-window serving loop (include/cs_serve.h).
 //
-// One 64-lane workgroup per entry: every entry touches one slot only (a few
-// hundred values), so the launch is latency-bound and a single wave per slot
-// keeps it free of barriers between entries.  All copies and products walk
-// the slot's live sizes with lane-strided, coalesced accesses.
+// One 256-lane workgroup per entry: every entry touches one slot only (a few
+// thousand values at most), so a launch is latency-bound; four waves per slot
+// cut the serial depth of each copy, and no barrier spans entries.  Copies
+// issue a batch of loads before any of its stores (the slot and pool arrays
+// reach the kernel through a struct, so the compiler cannot tell them apart
+// and would otherwise wait for each load before the next), and all accesses
+// walk the slot's live sizes lane-strided and coalesced.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -13,7 +16,8 @@
 
 namespace {
 
-constexpr int WL = 64;   // lanes per entry
+constexpr int NT = 256;  // lanes per entry
+constexpr int CU = 4;    // loads in flight per lane in a copy
 
 struct Geo {
     int S, W, nc, mc;
@@ -26,8 +30,32 @@ __device__ inline Geo geo(const cs_serve_table &t) {
 
 template <typename T> __device__ inline T *P(void *p) { return static_cast<T *>(p); }
 
+// d[i] = s[i] for i < cnt by the workgroup's lanes: CU loads (indices clamped
+// into the span) before the CU stores of each batch.
 template <typename T>
-__global__ __launch_bounds__(WL) void k_serve_admit(cs_serve_table t, cs_serve_table p,
+__device__ inline void copy_span(T *__restrict__ d, const T *__restrict__ s, int64_t cnt, int l) {
+    if (cnt <= 0) return;
+    for (int64_t b = 0; b < cnt; b += (int64_t)NT * CU) {
+        T x[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int64_t i = b + l + (int64_t)NT * u;
+            x[u] = s[i < cnt ? i : cnt - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int64_t i = b + l + (int64_t)NT * u;
+            if (i < cnt) d[i] = x[u];
+        }
+    }
+}
+
+template <typename T> __device__ inline void fill_span(T *d, int64_t cnt, int l) {
+    for (int64_t i = l; i < cnt; i += NT) d[i] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_serve_admit(cs_serve_table t, cs_serve_table p,
                                                     const int32_t *__restrict__ pairs, int count) {
     const int e = blockIdx.x, l = threadIdx.x;
     if (e >= count) return;
@@ -37,26 +65,17 @@ __global__ __launch_bounds__(WL) void k_serve_admit(cs_serve_table t, cs_serve_t
     const int n = p.nv[q], m = p.nrows[q];
     if (n < 1 || n > G.nc || m < 0 || m > G.mc) return;
     const int64_t nn = (int64_t)G.nc * G.nc, mn = (int64_t)G.mc * G.nc;
-    const T *pM = P<T>(p.M) + q * nn, *pMi = P<T>(p.Minv) + q * nn, *pJ = P<T>(p.J) + q * mn;
-    T *sM = P<T>(t.M) + s * nn, *sMi = P<T>(t.Minv) + s * nn, *sJ = P<T>(t.J) + s * mn;
-    for (int i = l; i < n * n; i += WL) {
-        sM[i] = pM[i];
-        sMi[i] = pMi[i];
-    }
-    for (int64_t i = l; i < (int64_t)m * n; i += WL) sJ[i] = pJ[i];
-    for (int i = l; i < m; i += WL) {
-        P<T>(t.D)[(int64_t)s * G.mc + i] = P<T>(p.D)[(int64_t)q * G.mc + i];
-        P<T>(t.pen)[(int64_t)s * G.mc + i] = P<T>(p.pen)[(int64_t)q * G.mc + i];
-    }
-    for (int i = l; i < G.nc; i += WL) {
-        P<T>(t.v)[(int64_t)s * G.nc + i] = P<T>(p.v)[(int64_t)q * G.nc + i];
-        P<T>(t.goal)[(int64_t)s * G.nc + i] = P<T>(p.goal)[(int64_t)q * G.nc + i];
-        P<T>(t.vbar)[(int64_t)s * G.nc + i] = T(0);
-    }
-    for (int i = l; i < G.W * G.nc; i += WL) {
-        P<T>(t.tau)[(int64_t)s * G.W * G.nc + i] = P<T>(p.tau)[(int64_t)q * G.W * G.nc + i];
-        P<T>(t.taubar)[(int64_t)s * G.W * G.nc + i] = T(0);
-    }
+    copy_span(P<T>(t.M) + s * nn, P<T>(p.M) + q * nn, (int64_t)n * n, l);
+    copy_span(P<T>(t.Minv) + s * nn, P<T>(p.Minv) + q * nn, (int64_t)n * n, l);
+    copy_span(P<T>(t.J) + s * mn, P<T>(p.J) + q * mn, (int64_t)m * n, l);
+    copy_span(P<T>(t.D) + (int64_t)s * G.mc, P<T>(p.D) + (int64_t)q * G.mc, m, l);
+    copy_span(P<T>(t.pen) + (int64_t)s * G.mc, P<T>(p.pen) + (int64_t)q * G.mc, m, l);
+    copy_span(P<T>(t.v) + (int64_t)s * G.nc, P<T>(p.v) + (int64_t)q * G.nc, G.nc, l);
+    copy_span(P<T>(t.goal) + (int64_t)s * G.nc, P<T>(p.goal) + (int64_t)q * G.nc, G.nc, l);
+    copy_span(P<T>(t.tau) + (int64_t)s * G.W * G.nc, P<T>(p.tau) + (int64_t)q * G.W * G.nc,
+              (int64_t)G.W * G.nc, l);
+    fill_span(P<T>(t.vbar) + (int64_t)s * G.nc, G.nc, l);
+    fill_span(P<T>(t.taubar) + (int64_t)s * G.W * G.nc, (int64_t)G.W * G.nc, l);
     if (l == 0) {
         t.nv[s] = n;
         t.nrows[s] = m;
@@ -77,7 +96,7 @@ __device__ inline bool entry(const cs_serve_table &t, const Geo &G, const int32_
 }
 
 template <typename T>
-__global__ __launch_bounds__(WL) void k_serve_pre(cs_serve_table t, const int32_t *__restrict__ ent,
+__global__ __launch_bounds__(NT) void k_serve_pre(cs_serve_table t, const int32_t *__restrict__ ent,
                                                   int count) {
     const int e = blockIdx.x, l = threadIdx.x;
     if (e >= count) return;
@@ -90,7 +109,7 @@ __global__ __launch_bounds__(WL) void k_serve_pre(cs_serve_table t, const int32_
         // a0 = M^{-1} tau_t
         const T *Mi = P<T>(t.Minv) + (int64_t)s * G.nc * G.nc;
         const T *tau = P<T>(t.tau) + ((int64_t)s * G.W + st) * G.nc;
-        for (int i = l; i < n; i += WL) {
+        for (int i = l; i < n; i += NT) {
             T acc = T(0);
             for (int j = 0; j < n; ++j) acc += Mi[i * n + j] * tau[j];
             P<T>(t.a0)[on + i] = acc;
@@ -99,33 +118,32 @@ __global__ __launch_bounds__(WL) void k_serve_pre(cs_serve_table t, const int32_
         const T *J = P<T>(t.J) + (int64_t)s * G.mc * G.nc;
         const T *v = P<T>(t.v) + on;
         const T b = T(t.b_damp), k = T(t.k_spring);
-        for (int r = l; r < m; r += WL) {
+        for (int r = l; r < m; r += NT) {
             T acc = T(0);
+#pragma unroll 6
             for (int j = 0; j < n; ++j) acc += J[(int64_t)r * n + j] * v[j];
             P<T>(t.aref)[om + r] = -b * acc - k * P<T>(t.pen)[om + r];
         }
     } else {
         const int64_t an = ((int64_t)st * G.S + s) * G.nc, am = ((int64_t)st * G.S + s) * G.mc;
-        for (int i = l; i < n; i += WL) {
+        for (int i = l; i < n; i += NT) {
             P<T>(t.a)[on + i] = P<T>(t.arch_a)[an + i];
             P<T>(t.a0)[on + i] = P<T>(t.arch_a0)[an + i];
             P<T>(t.abar)[on + i] = T(t.h) * P<T>(t.vbar)[on + i];
         }
-        for (int r = l; r < m; r += WL) {
-            P<T>(t.aref)[om + r] = P<T>(t.arch_aref)[am + r];
-            t.state[t.mask_offset + om + r] = t.arch_mask[am + r];
-        }
+        copy_span(P<T>(t.aref) + om, P<T>(t.arch_aref) + am, m, l);
+        copy_span(t.state + t.mask_offset + om, t.arch_mask + am, m, l);
         const int ne = n * (n + 1) / 2;
         const T *src = P<T>(t.arch_fac) + ((int64_t)st * G.S + s) * G.ne;
         T *dst = reinterpret_cast<T *>(t.state) + (int64_t)s * G.ne;
-        for (int i = l; i < ne; i += WL) dst[i] = src[i];
+        copy_span(dst, src, ne, l);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(WL) void k_serve_post(cs_serve_table t, const int32_t *__restrict__ ent,
+__global__ __launch_bounds__(NT) void k_serve_post(cs_serve_table t, const int32_t *__restrict__ ent,
                                                    int count) {
-    __shared__ T part[WL];
+    __shared__ T part[NT];
     const int e = blockIdx.x, l = threadIdx.x;
     if (e >= count) return;
     const Geo G = geo(t);
@@ -136,7 +154,7 @@ __global__ __launch_bounds__(WL) void k_serve_post(cs_serve_table t, const int32
     if (fwd) {
         const int64_t an = ((int64_t)st * G.S + s) * G.nc, am = ((int64_t)st * G.S + s) * G.mc;
         const T h = T(t.h);
-        for (int i = l; i < n; i += WL) {
+        for (int i = l; i < n; i += NT) {
             const T a = P<T>(t.a)[on + i];
             P<T>(t.arch_a)[an + i] = a;
             P<T>(t.arch_a0)[an + i] = P<T>(t.a0)[on + i];
@@ -144,19 +162,16 @@ __global__ __launch_bounds__(WL) void k_serve_post(cs_serve_table t, const int32
             P<T>(t.v)[on + i] = vn;
             if (st == G.W - 1) P<T>(t.vbar)[on + i] = T(2) * (vn - P<T>(t.goal)[on + i]);
         }
-        for (int r = l; r < m; r += WL) {
-            P<T>(t.arch_aref)[am + r] = P<T>(t.aref)[om + r];
-            t.arch_mask[am + r] = t.state[t.mask_offset + om + r];
-        }
+        copy_span(P<T>(t.arch_aref) + am, P<T>(t.aref) + om, m, l);
+        copy_span(t.arch_mask + am, t.state + t.mask_offset + om, m, l);
         const int ne = n * (n + 1) / 2;
-        const T *src = reinterpret_cast<const T *>(t.state) + (int64_t)s * G.ne;
-        T *dst = P<T>(t.arch_fac) + ((int64_t)st * G.S + s) * G.ne;
-        for (int i = l; i < ne; i += WL) dst[i] = src[i];
+        copy_span(P<T>(t.arch_fac) + ((int64_t)st * G.S + s) * G.ne,
+                  reinterpret_cast<const T *>(t.state) + (int64_t)s * G.ne, ne, l);
     } else {
         // taubar_t = M^{-T} a0bar
         const T *Mi = P<T>(t.Minv) + (int64_t)s * G.nc * G.nc;
         const T *a0b = P<T>(t.a0bar) + on;
-        for (int i = l; i < n; i += WL) {
+        for (int i = l; i < n; i += NT) {
             T acc = T(0);
             for (int j = 0; j < n; ++j) acc += Mi[j * n + i] * a0b[j];
             P<T>(t.taubar)[((int64_t)s * G.W + st) * G.nc + i] = acc;
@@ -164,11 +179,13 @@ __global__ __launch_bounds__(WL) void k_serve_post(cs_serve_table t, const int32
         // vbar -= b J^T arefbar: lane (column c, part p) sums rows p, p + np, ...
         const T *J = P<T>(t.J) + (int64_t)s * G.mc * G.nc;
         const T *rb = P<T>(t.arefbar) + om;
-        const int np = WL / n;          // n <= n_cap <= 64
+        const int np = NT / n;          // n <= n_cap <= 64
         const int c = l % n, pp = l / n;
         T acc = T(0);
-        if (pp < np)
+        if (pp < np) {
+#pragma unroll 4
             for (int r = pp; r < m; r += np) acc += J[(int64_t)r * n + c] * rb[r];
+        }
         part[l] = acc;
         __syncthreads();
         if (l < n) {
@@ -199,7 +216,7 @@ int check_table(const cs_serve_table *t, bool slots_table) {
 
 template <typename K>
 int launch(K kernel, int count, hipStream_t st, const cs_serve_table &a, const int32_t *list) {
-    hipLaunchKernelGGL(kernel, dim3(count), dim3(WL), 0, st, a, list, count);
+    hipLaunchKernelGGL(kernel, dim3(count), dim3(NT), 0, st, a, list, count);
     return hipGetLastError() == hipSuccess ? CS_OK : CS_EHIP;
 }
 
@@ -219,10 +236,10 @@ int cs_serve_admit(const cs_serve_table *table, const cs_serve_table *pool, cons
     if (count == 0) return CS_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (table->dtype == CS_F32)
-        hipLaunchKernelGGL(k_serve_admit<float>, dim3(count), dim3(WL), 0, st, *table, *pool, pairs,
+        hipLaunchKernelGGL(k_serve_admit<float>, dim3(count), dim3(NT), 0, st, *table, *pool, pairs,
                            count);
     else
-        hipLaunchKernelGGL(k_serve_admit<double>, dim3(count), dim3(WL), 0, st, *table, *pool, pairs,
+        hipLaunchKernelGGL(k_serve_admit<double>, dim3(count), dim3(NT), 0, st, *table, *pool, pairs,
                            count);
     return hipGetLastError() == hipSuccess ? CS_OK : CS_EHIP;
 }
