@@ -105,6 +105,44 @@ int cs_serve_pre(const cs_serve_table *table, const int32_t *entries, int32_t co
 int cs_serve_post(const cs_serve_table *table, const int32_t *entries, int32_t count,
                   void *stream);
 
+/* One solver launch of a tick: cs_forward (kind 0) or cs_ift_vjp (kind 1) of
+ * the `count` slots whose indices sit in the tick's device list at element
+ * `order`, with the batch description classes[cls] (its order and count
+ * replaced), on `stream` (lane 0) or `side` (lane 1). */
+typedef struct cs_serve_launch {
+    int32_t kind;
+    int32_t cls;
+    int32_t lane;
+    int32_t count;
+    int32_t order;
+} cs_serve_launch;
+
+/* The device work of one serving tick in one call, in stream order:
+ *   1. copy host_list[0 .. list_len) (pinned host memory) to dev_list and
+ *      record ev_list on `stream` (the caller may reuse host_list once
+ *      ev_list has completed);
+ *   2. cs_serve_admit of the n_admit pairs at dev_list[0 ..), if n_admit > 0;
+ *   3. cs_serve_pre of the n_entries (slot, phase) pairs that follow them;
+ *   4. every launch of `launches` on its lane: when any launch is on lane 1,
+ *      `side` first waits for ev_fork recorded on `stream` after step 3, and
+ *      `stream` waits for ev_join recorded on `side` after its last launch;
+ *      the launches of one tick must name disjoint slots;
+ *   5. cs_serve_post of the same entries.
+ * Forwards use table->M, J, a0, aref, D, a and state (state_bytes) and write
+ * status / iters; VJPs read the same and abar and write a0bar and arefbar.
+ * Streams and events are HIP handles (NULL stream: the null stream); side,
+ * ev_fork and ev_join may be NULL when no launch is on lane 1.  Returns
+ * CS_EINVAL for a bad argument before anything is enqueued (kind, lane,
+ * class index, counts, list bounds), else the first error of the steps;
+ * allocates nothing. */
+int cs_serve_tick(const cs_serve_table *table, const cs_serve_table *pool,
+                  const cs_batch *classes, int32_t nclasses, const cs_solver_params *params,
+                  size_t state_bytes, int32_t *status, int32_t *iters,
+                  const int32_t *host_list, int32_t *dev_list, int32_t list_len,
+                  int32_t n_admit, int32_t n_entries,
+                  const cs_serve_launch *launches, int32_t nlaunch,
+                  void *stream, void *side, void *ev_list, void *ev_fork, void *ev_join);
+
 #ifdef __cplusplus
 }
 #endif

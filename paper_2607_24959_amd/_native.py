@@ -20,7 +20,7 @@ PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
-            "cs_serve_admit", "cs_serve_pre", "cs_serve_post")
+            "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
 
 
 class CsBatch(C.Structure):
@@ -97,6 +97,9 @@ def lib():
         for name in ("cs_serve_pre", "cs_serve_post"):
             getattr(L, name).restype = C.c_int
             getattr(L, name).argtypes = [pt, vp, i32, vp]
+        L.cs_serve_tick.restype = C.c_int
+        L.cs_serve_tick.argtypes = [pt, pt, pb, i32, pp, sz, vp, vp, vp, vp, i32, i32, i32, vp, i32,
+                                    vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -151,3 +154,16 @@ def serve_pre(table, entries, count, stream):
 
 def serve_post(table, entries, count, stream):
     return lib().cs_serve_post(C.byref(table), entries, int(count), stream)
+
+
+def serve_tick(table, pool, classes, nclasses, params, state_nbytes, status, iters, host_list,
+               dev_list, list_len, n_admit, n_entries, launches, nlaunch, stream, side, ev_list,
+               ev_fork, ev_join):
+    """One serving tick's device work (list upload, admit, pre, the solver
+    launches on two lanes, post); ``classes`` is a ctypes array of CsBatch and
+    ``launches`` the address of an int32 [nlaunch, 5] array of
+    (kind, class, lane, count, order) rows."""
+    return lib().cs_serve_tick(C.byref(table), None if pool is None else C.byref(pool), classes,
+                               int(nclasses), C.byref(params), state_nbytes, status, iters,
+                               host_list, dev_list, int(list_len), int(n_admit), int(n_entries),
+                               launches, int(nlaunch), stream, side, ev_list, ev_fork, ev_join)

@@ -264,4 +264,62 @@ int cs_serve_post(const cs_serve_table *table, const int32_t *entries, int32_t c
                                   : launch(k_serve_post<double>, count, st, *table, entries);
 }
 
+int cs_serve_tick(const cs_serve_table *table, const cs_serve_table *pool,
+                  const cs_batch *classes, int32_t nclasses, const cs_solver_params *params,
+                  size_t state_bytes, int32_t *status, int32_t *iters,
+                  const int32_t *host_list, int32_t *dev_list, int32_t list_len,
+                  int32_t n_admit, int32_t n_entries,
+                  const cs_serve_launch *launches, int32_t nlaunch,
+                  void *stream, void *side, void *ev_list, void *ev_fork, void *ev_join) {
+    int rc = check_table(table, true);
+    if (rc != CS_OK) return rc;
+    if (!classes || nclasses < 1 || !params || list_len < 0 || n_admit < 0 || n_entries < 0 ||
+        nlaunch < 0 || (nlaunch > 0 && !launches) || (list_len > 0 && (!host_list || !dev_list)))
+        return CS_EINVAL;
+    if (2 * (int64_t)n_admit + 2 * (int64_t)n_entries > list_len) return CS_EINVAL;
+    if (n_admit > 0 && !pool) return CS_EINVAL;
+    bool use_side = false;
+    for (int i = 0; i < nlaunch; ++i) {
+        const cs_serve_launch &L = launches[i];
+        if (L.kind < 0 || L.kind > 1 || L.cls < 0 || L.cls >= nclasses || L.lane < 0 ||
+            L.lane > 1 || L.count < 1 || L.order < 0 || (int64_t)L.order + L.count > list_len)
+            return CS_EINVAL;
+        use_side = use_side || L.lane == 1;
+    }
+    if (use_side && (!side || !ev_fork || !ev_join)) return CS_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream), sd = static_cast<hipStream_t>(side);
+    if (list_len > 0 && hipMemcpyAsync(dev_list, host_list, sizeof(int32_t) * (size_t)list_len,
+                                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return CS_EHIP;
+    if (ev_list && hipEventRecord(static_cast<hipEvent_t>(ev_list), st) != hipSuccess) return CS_EHIP;
+    if (n_admit > 0 && (rc = cs_serve_admit(table, pool, dev_list, n_admit, stream)) != CS_OK)
+        return rc;
+    const int32_t *ent = dev_list + 2 * (int64_t)n_admit;
+    if ((rc = cs_serve_pre(table, ent, n_entries, stream)) != CS_OK) return rc;
+    if (use_side && (hipEventRecord(static_cast<hipEvent_t>(ev_fork), st) != hipSuccess ||
+                     hipStreamWaitEvent(sd, static_cast<hipEvent_t>(ev_fork), 0) != hipSuccess))
+        return CS_EHIP;
+    for (int i = 0; i < nlaunch && rc == CS_OK; ++i) {
+        const cs_serve_launch &L = launches[i];
+        cs_batch d = classes[L.cls];
+        d.order = dev_list + L.order;
+        d.count = L.count;
+        void *ls = L.lane == 1 ? side : stream;
+        if (L.kind == 0)
+            rc = cs_forward(&d, params, table->M, table->J, table->a0, table->aref, table->D, nullptr,
+                            table->a, table->state, state_bytes, status, iters, ls);
+        else
+            rc = cs_ift_vjp(&d, table->state, state_bytes, table->M, table->J, table->a0,
+                            table->aref, table->D, table->a, table->abar, table->a0bar,
+                            table->arefbar, nullptr, nullptr, nullptr, ls);
+    }
+    // the join is enqueued even after a failed launch, so the caller's stream
+    // stays ordered after everything the side stream was given
+    if (use_side && (hipEventRecord(static_cast<hipEvent_t>(ev_join), sd) != hipSuccess ||
+                     hipStreamWaitEvent(st, static_cast<hipEvent_t>(ev_join), 0) != hipSuccess))
+        return rc != CS_OK ? rc : CS_EHIP;
+    if (rc != CS_OK) return rc;
+    return cs_serve_post(table, ent, n_entries, stream);
+}
+
 }  // extern "C"

@@ -20,8 +20,10 @@ Every tick it
      gradient recursion, and advances every slot's phase on the host.
 Requests at different phases share launches; admission needs only a free
 slot, so new work overlaps with work already on the device.  The host side
-of a tick is one pinned host-to-device copy of the tick's index lists and a
-fixed number of launches; it never synchronises.  An instance's arithmetic
+of a tick is its bookkeeping and one native call (cs_serve_tick) that
+uploads the tick's index lists from pinned memory and enqueues steps 1-4;
+the host waits for the previous tick to start on the device, so it runs
+one tick ahead.  An instance's arithmetic
 does not depend on its slot or on the other slots (kernel classes have fixed
 compile-time sizes), so a request's result is the same alone and in any mix.
 """
@@ -195,12 +197,9 @@ class Engine:
         self.ev_pre = torch.cuda.Event() if pin else None
         self.ev_side = [torch.cuda.Event() for _ in self.side]
         self.params = N.CsSolverParams(int(max_iter), 0, float(tol))
-        # raw pointers of the persistent buffers, made once
+        # raw pointers of the solver outputs the table does not hold, made once
         cp = lambda t: C.c_void_p(t.data_ptr())
-        self._p = dict(M=cp(self.M), J=cp(self.J), a0=cp(self.a0), aref=cp(self.aref),
-                       D=cp(self.D), a=cp(self.sol.a), state=cp(self.sol.state),
-                       status=cp(self.sol.status), iters=cp(self.sol.iters), abar=cp(self.abar),
-                       a0bar=cp(self.a0bar), arefbar=cp(self.arefbar))
+        self._p = dict(status=cp(self.sol.status), iters=cp(self.sol.iters))
         # host bookkeeping
         self.phase = np.full(S, -1, dtype=np.int64)   # -1 free; 0..W-1 forward; W..2W-1 backward
         self.cls = np.zeros(S, dtype=np.int64)        # kernel class of the slot's request
@@ -223,6 +222,22 @@ class Engine:
             C.memmove(C.byref(d), C.byref(self.batch.desc), C.sizeof(N.CsBatch))
             d.path, d.nv_max, d.nrows_max = path, nmax, mmax
             self.class_desc.append(d)
+        self.class_arr = (N.CsBatch * len(self.class_desc))(*self.class_desc)
+        # a tick's launches, rows of (kind, class, lane, count, order); at most
+        # one forward and one VJP launch per class
+        self.launch_rows = np.zeros((2 * len(self.classes), 5), dtype=np.int32)
+        self._launch_ptr = self.launch_rows.ctypes.data
+        self.list_np = [b.numpy() for b in self.list_pin]
+        self._list_host = [b.data_ptr() for b in self.list_pin]
+        self._list_dev = self.list_dev.data_ptr()
+        self._ev = None
+        if pin:
+            # one record each makes the events, so their HIP handles exist
+            s0 = torch.cuda.current_stream(dev)
+            for ev in self.list_ev_obj + [self.ev_pre] + self.ev_side:
+                ev.record(s0)
+            self._ev = ([e.cuda_event for e in self.list_ev_obj], self.ev_pre.cuda_event,
+                        self.ev_side[0].cuda_event)
 
     # ------------------------------------------------------------ setup
     def _class_table(self):
@@ -302,60 +317,41 @@ class Engine:
                 launches.append((kind, int(c), pos, len(idx)))
                 pos += len(idx)
         flat = np.concatenate(parts).astype(np.int32)
-        buf = self.list_pin[self.ring]
-        if self.list_evt[self.ring] is not None:
-            self.list_evt[self.ring].synchronize()      # its previous copy has been consumed
-        buf[:len(flat)].numpy()[:] = flat
+        # wait until the previous tick has started on the device (its list
+        # upload, the first thing it enqueued, is done): the host then stays
+        # one tick ahead, enough to keep the device busy while preparing a
+        # tick takes less than running one, and a new request queues behind
+        # one tick at most.  The upload of two ticks ago, which filled this
+        # ring buffer, completed before it.
+        ring = self.ring
+        if self.list_evt[ring ^ 1] is not None:
+            self.list_evt[ring ^ 1].synchronize()
+        self.list_np[ring][:len(flat)] = flat
+        self.list_evt[ring] = self.list_ev_obj[ring]
+        self.ring ^= 1
         # the stream run_stream fixed for its run (looking it up costs the
         # host ~12 us a call), else the current one
         stream = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
-        self.list_dev[:len(flat)].copy_(buf[:len(flat)], non_blocking=True)
-        ev = self.list_ev_obj[self.ring]
-        if ev is None:
-            ev = torch.cuda.Event()
-        ev.record(stream)
-        self.list_evt[self.ring] = ev
-        self.ring ^= 1
-        st = C.c_void_p(stream.cuda_stream)
-        base = self.list_dev.data_ptr()
-        at = lambda k: C.c_void_p(base + 4 * k)
-        tb = self.table
-        if adm_s:
-            N.check(N.serve_admit(tb, self.pool.table, at(0), len(adm_s), st), "cs_serve_admit")
-        N.check(N.serve_pre(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_pre")
-        P = self._p
-        nst = self.sol.state.numel()
         # longest launches first, each dealt to the less loaded of the two
         # lanes by a latency estimate (a class launch of a few instances takes
         # about one instance's solve time)
         est = lambda L: ((2.0 * self.classes[L[1]][1] + 40.0) if L[0] == "fwd" else 20.0)
         launches.sort(key=est, reverse=True)
-        lanes = [stream] + (self.side if len(launches) > 1 else [])
-        load = [0.0] * len(lanes)
-        if len(lanes) > 1:
-            self.ev_pre.record(stream)
-            for sd in lanes[1:]:
-                sd.wait_event(self.ev_pre)
-        lane_ptr = [C.c_void_p(x.cuda_stream) for x in lanes] if lanes else [st]
-        for kind, c, off, cnt in launches:
-            d = self.class_desc[c]
-            d.order, d.count = base + 4 * off, cnt
-            k = min(range(len(load)), key=load.__getitem__) if load else 0
-            if load:
-                load[k] += est((kind, c))
-            ls = lane_ptr[k]
-            if kind == "vjp":
-                rc = N.ift_vjp(d, P["state"], nst, P["M"], P["J"], P["a0"], P["aref"], P["D"],
-                               P["a"], P["abar"], P["a0bar"], P["arefbar"], None, None, None, ls)
-                N.check(rc, "cs_ift_vjp(serve)")
-            else:
-                rc = N.forward(d, self.params, P["M"], P["J"], P["a0"], P["aref"], P["D"], None,
-                               P["a"], P["state"], nst, P["status"], P["iters"], ls)
-                N.check(rc, "cs_forward(serve)")
-        for sd, ev in zip(lanes[1:], self.ev_side):
-            ev.record(sd)
-            stream.wait_event(ev)
-        N.check(N.serve_post(tb, at(2 * len(adm_s)), len(occ), st), "cs_serve_post")
+        two = len(launches) > 1 and bool(self.side)
+        load = [0.0, 0.0]
+        rows = self.launch_rows
+        for i, L in enumerate(launches):
+            k = 1 if two and load[1] < load[0] else 0
+            load[k] += est(L)
+            rows[i] = (0 if L[0] == "fwd" else 1, L[1], k, L[3], L[2])
+        evl, evf, evj = self._ev
+        rc = N.serve_tick(self.table, self.pool.table if adm_s else None, self.class_arr,
+                          len(self.classes), self.params, self.sol.state.numel(),
+                          self._p["status"], self._p["iters"], self._list_host[ring],
+                          self._list_dev, len(flat), len(adm_s), len(occ), self._launch_ptr,
+                          len(launches), stream.cuda_stream,
+                          self.side[0].cuda_stream if two else None, evl[ring], evf, evj)
+        N.check(rc, "cs_serve_tick")
         self.phase[occ] += 1
         done = occ[self.phase[occ] == 2 * W]
         self.ticks += 1
@@ -375,8 +371,8 @@ class Engine:
 def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     """Serve a Poisson stream of ``rate`` requests/s on the wall clock.
 
-    The host issues ticks without waiting for the GPU (at most two ticks
-    ahead, bounded by the list ring); every tick records an event, and a
+    The host issues each tick once the previous one has started on the GPU
+    (one tick ahead of the device); every tick records an event, and a
     request completes when the event of its last tick completes on the GPU.
     Latency is measured from arrival to that completion on one clock.
     Returns percentiles over the requests after the warm-up ones, and

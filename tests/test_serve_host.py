@@ -85,3 +85,45 @@ def test_serve_entry_points_reject_bad_tables():
     t = N.CsServeTable.from_buffer_copy(e.table)
     t.n_cap = 65
     assert N.serve_pre(t, None, 0, None) == N.CS_EINVAL
+
+
+def test_serve_tick_rejects_bad_arguments():
+    """cs_serve_tick checks every argument before it enqueues anything (no
+    device is touched: each case fails a check, and the device list address
+    below is never dereferenced)."""
+    if torch.cuda.is_available():
+        pytest.skip("host argument checks only, with a placeholder device address")
+    e = serve.Engine(slots=2, n_cap=9, m_cap=64, window=3, device="cpu")
+    rows = np.zeros((2, 5), dtype=np.int32)
+    host = np.zeros(16, dtype=np.int32)
+    dev_list = 0x1000
+
+    def tick(table=None, pool=None, ncls=None, list_len=16, n_admit=0, n_entries=1, nl=1,
+             host_ptr=host.ctypes.data, side=None):
+        return N.serve_tick(e.table if table is None else table, pool, e.class_arr,
+                            len(e.classes) if ncls is None else ncls, e.params, 0, None, None,
+                            host_ptr, dev_list, list_len, n_admit, n_entries, rows.ctypes.data,
+                            nl, None, side, None, None, None)
+
+    rows[0] = (0, 0, 0, 1, 2)                     # a forward of class 0 on lane 0
+    assert tick(table=N.CsServeTable()) == N.CS_EINVAL
+    assert tick(ncls=0) == N.CS_EINVAL
+    assert tick(list_len=2) == N.CS_EINVAL        # the launch's order lies past the list
+    assert tick(list_len=-1) == N.CS_EINVAL
+    assert tick(host_ptr=None) == N.CS_EINVAL
+    assert tick(n_admit=1) == N.CS_EINVAL         # admission needs the pool table
+    assert tick(n_entries=-1) == N.CS_EINVAL
+    assert tick(nl=-1) == N.CS_EINVAL
+    for bad in ((2, 0, 0, 1, 2),                  # kind
+                (0, len(e.classes), 0, 1, 2),     # class index
+                (0, -1, 0, 1, 2),
+                (0, 0, 2, 1, 2),                  # lane
+                (0, 0, 0, 0, 2),                  # empty launch
+                (0, 0, 0, 15, 2),                 # order + count past the list
+                (0, 0, 0, 1, -1),
+                (1, 0, 1, 1, 2)):                 # lane 1 without a side stream and events
+        rows[0] = bad
+        assert tick() == N.CS_EINVAL, bad
+    rows[0] = (0, 0, 0, 1, 2)
+    rows[1] = (1, 0, 1, 1, 3)
+    assert tick(nl=2) == N.CS_EINVAL              # side lane named, side stream missing
