@@ -209,8 +209,8 @@ __global__ __launch_bounds__(64) void k_forward_wave(
         // scalar registers and every lane updates its row, with no LDS round
         // trip or barrier on the per-column chain.  Branch-free over NC
         // columns (a branch that changes h[] makes the compiler copy the
-        // whole row at its join); NC >= n is a compile-time 16, 24 or 32
-        // chosen per instance, and columns n .. NC-1 (zero rows and columns)
+        // whole row at its join); NC >= n is a compile-time 16, 20, 24, 28
+        // or 32 chosen per instance, and columns n .. NC-1 (zero rows and columns)
         // take pivot 1.  False when a pivot of the first n columns is not
         // positive.
         float idl = 1.f, dl = 1.f;
@@ -268,7 +268,9 @@ __global__ __launch_bounds__(64) void k_forward_wave(
                 return f(std::integral_constant<int, 16>{});
             } else {
                 if (n <= 16) return f(std::integral_constant<int, 16>{});
+                if (n <= 20) return f(std::integral_constant<int, 20>{});
                 if (n <= 24) return f(std::integral_constant<int, 24>{});
+                if (n <= 28) return f(std::integral_constant<int, 28>{});
                 return f(std::integral_constant<int, 32>{});
             }
         };

@@ -194,11 +194,12 @@ def test_wave_family_mixed_fp32():
 
 def test_wave_family_size_boundaries_fp32():
     """One-wave family at the edges of its compile-time sizes: n in {1, 2, 15,
-    16, 17, 23, 24, 25, 30, 31} (Cholesky column counts 16 / 24 / 32, padded
-    widths 16 / 32) with 0, 1, 16, 17 and 256 contacts (0, 4, 64, 68, 1024 rows:
+    16, 17, 20, 21, 23, 24, 25, 28, 29, 30, 31} (Cholesky column counts 16 / 20
+    / 24 / 28 / 32, padded widths 16 / 32) with 0, 1, 16, 17 and 256 contacts (0, 4, 64, 68, 1024 rows:
     empty, one K-step, exactly one and just over one row group, the maximum)."""
     _needs_gpu()
-    shapes = [(n, nc) for n in (1, 2, 15, 16, 17, 23, 24, 25, 30, 31) for nc in (0, 1, 16, 17, 256)]
+    shapes = [(n, nc) for n in (1, 2, 15, 16, 17, 20, 21, 23, 24, 25, 28, 29, 30, 31)
+              for nc in (0, 1, 16, 17, 256)]
     pb = synth.pack([synth.instance(4242, i, n, nc) for i, (n, nc) in enumerate(shapes)])
     p32, p64 = pb.astype(np.float32), pb.rounded(np.float32)
     batch = solver.Batch.packed_from(pb.nv, pb.nrows, torch.float32, path=N.PATH_WAVE)
