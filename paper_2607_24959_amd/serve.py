@@ -332,18 +332,8 @@ class Engine:
         # the stream run_stream fixed for its run (looking it up costs the
         # host ~12 us a call), else the current one
         stream = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
-        # longest launches first, each dealt to the less loaded of the two
-        # lanes by a latency estimate (a class launch of a few instances takes
-        # about one instance's solve time)
-        est = lambda L: ((2.0 * self.classes[L[1]][1] + 40.0) if L[0] == "fwd" else 20.0)
-        launches.sort(key=est, reverse=True)
         two = len(launches) > 1 and bool(self.side)
-        load = [0.0, 0.0]
-        rows = self.launch_rows
-        for i, L in enumerate(launches):
-            k = 1 if two and load[1] < load[0] else 0
-            load[k] += est(L)
-            rows[i] = (0 if L[0] == "fwd" else 1, L[1], k, L[3], L[2])
+        deal_lanes(launches, self.classes, two, self.launch_rows)
         evl, evf, evj = self._ev
         rc = N.serve_tick(self.table, self.pool.table if adm_s else None, self.class_arr,
                           len(self.classes), self.params, self.sol.state.numel(),
@@ -366,6 +356,27 @@ class Engine:
             self.free.append(s)
             self.finished.append(r)
         return len(occ), done
+
+
+def deal_lanes(launches, classes, two, rows):
+    """Order a tick's launches and pick their lanes.
+
+    ``launches`` holds (kind, class, order offset, count) tuples with kind
+    "fwd" or "vjp"; ``classes`` the engine's (family, n_max, m_max) table.
+    Longest launches go first, each to the less loaded of the two lanes
+    (lane 0 on ties, and always when ``two`` is false) by a latency estimate:
+    a class launch of a few instances takes about one instance's solve, which
+    grows with the class's n_max for a forward.  Fills ``rows[:len]`` with
+    (kind 0 forward / 1 VJP, class, lane, count, order) and sorts
+    ``launches`` in place."""
+    est = lambda L: ((2.0 * classes[L[1]][1] + 40.0) if L[0] == "fwd" else 20.0)
+    launches.sort(key=est, reverse=True)
+    load = [0.0, 0.0]
+    for i, L in enumerate(launches):
+        k = 1 if two and load[1] < load[0] else 0
+        load[k] += est(L)
+        rows[i] = (0 if L[0] == "fwd" else 1, L[1], k, L[3], L[2])
+    return rows[:len(launches)]
 
 
 def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):

@@ -127,3 +127,21 @@ def test_serve_tick_rejects_bad_arguments():
     rows[0] = (0, 0, 0, 1, 2)
     rows[1] = (1, 0, 1, 1, 3)
     assert tick(nl=2) == N.CS_EINVAL              # side lane named, side stream missing
+
+
+def test_deal_lanes_orders_and_balances():
+    """Longest launches first (forwards by class width, VJPs shortest), each
+    to the less loaded lane; one lane when the tick has no second lane."""
+    classes = [(N.PATH_SMALL, 3, 64), (N.PATH_SMALL, 9, 64), (N.PATH_WAVE, 15, 256),
+               (N.PATH_WAVE, 18, 256)]
+    rows = np.zeros((8, 5), dtype=np.int32)
+    launches = [("vjp", 3, 10, 2), ("fwd", 0, 12, 3), ("fwd", 3, 15, 1), ("fwd", 2, 16, 4),
+                ("vjp", 0, 20, 1)]
+    out = serve.deal_lanes(list(launches), classes, True, rows)
+    # estimates: fwd c3 76, fwd c2 70, fwd c0 46, vjp 20, vjp 20
+    assert [tuple(r) for r in out] == [(0, 3, 0, 1, 15), (0, 2, 1, 4, 16), (0, 0, 1, 3, 12),
+                                       (1, 3, 0, 2, 10), (1, 0, 0, 1, 20)]
+    out1 = serve.deal_lanes(list(launches), classes, False, rows)
+    assert set(out1[:, 2].tolist()) == {0}
+    assert sorted(map(tuple, out1[:, [0, 1, 3, 4]].tolist())) == \
+        sorted((0 if k == "fwd" else 1, c, n, o) for k, c, o, n in launches)
