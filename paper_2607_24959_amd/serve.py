@@ -383,7 +383,7 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     """Serve a Poisson stream of ``rate`` requests/s on the wall clock.
 
     The host issues each tick once the previous one has started on the GPU
-    (one tick ahead of the device); every tick records an event, and a
+    (one tick ahead of the device); every tick records a timing event, and a
     request completes when the event of its last tick completes on the GPU.
     Latency is measured from arrival to that completion on one clock.
     Returns percentiles over the requests after the warm-up ones, and
@@ -408,9 +408,21 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     start = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     t0 = time.perf_counter()
-    tick_events = [start]
+    # one timing event per tick from a recycled pool: an event is read once
+    # it is LAG ticks old (long complete by then) and reused, so a run makes
+    # a bounded number of events instead of one per tick
+    LAG = 64
+    t_end = [0.0]                       # seconds since start, per tick
+    in_flight: deque = deque()          # (tick number, event)
+    spare: deque = deque()
     solves = 0
     t_first = engine.ticks
+
+    def read_oldest():
+        i, e = in_flight.popleft()
+        t_end[i] = start.elapsed_time(e) / 1e3
+        spare.append(e)
+
     while len(engine.finished) < total:
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
@@ -420,15 +432,20 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
         before = engine.ticks
         n_work, _ = engine.tick(now)
         if engine.ticks != before:
-            ev = torch.cuda.Event(enable_timing=True)
+            ev = spare.popleft() if spare else torch.cuda.Event(enable_timing=True)
             ev.record(stream)
-            tick_events.append(ev)
+            t_end.append(0.0)
+            in_flight.append((len(t_end) - 1, ev))
+            if len(in_flight) > LAG:
+                in_flight[0][1].synchronize()
+                read_oldest()
             solves += n_work
     torch.cuda.synchronize()
+    while in_flight:
+        read_oldest()
     engine._stream = None
     if gc_was_enabled:
         gc.enable()
-    t_end = [start.elapsed_time(e) / 1e3 for e in tick_events]     # seconds since start
     for r in engine.finished:
         r.done = t_end[r.done_tick - t_first]
     fin = sorted(engine.finished, key=lambda r: r.rid)[warmup:]
@@ -436,5 +453,5 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
     span = max(r.done for r in fin) - min(r.arrival for r in fin)
     return dict(rate=rate, requests=len(fin), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), requests_per_s=len(fin) / span,
-                solves_per_s=solves / t_end[-1], ticks=len(tick_events) - 1, slots=engine.S,
+                solves_per_s=solves / t_end[-1], ticks=len(t_end) - 1, slots=engine.S,
                 max_active=engine.max_active)
