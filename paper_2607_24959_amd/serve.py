@@ -193,7 +193,14 @@ class Engine:
         # on the caller's stream.  One side stream: every fork or join costs
         # the host a stream-wait call of ~12 us, and two lanes already hold
         # the widest forward apart from the rest.
-        self.side = [torch.cuda.Stream(device=dev)] if pin else []
+        # The two lanes are taken from torch's stream pool one after the
+        # other: run_stream runs on the first and the side lane is the
+        # second.  (A serving run on the caller's stream, with a side stream
+        # taken whenever an engine was made, was ~1.8x slower per tick in
+        # some runs of a process that had made other streams before: the
+        # two lanes then seemed to share one hardware queue.)
+        self.lanes = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)] if pin else []
+        self.side = self.lanes[1:]
         self.ev_pre = torch.cuda.Event() if pin else None
         self.ev_side = [torch.cuda.Event() for _ in self.side]
         self.params = N.CsSolverParams(int(max_iter), 0, float(tol))
@@ -397,7 +404,7 @@ def run_stream(engine: Engine, rate, n_requests, warmup=0, seed=0):
                     arrival=float(arrivals[i])) for i in range(total)]
     pending = deque(reqs)
     engine.finished.clear()
-    stream = torch.cuda.current_stream(engine.device)
+    stream = engine.lanes[0] if engine.lanes else torch.cuda.current_stream(engine.device)
     engine._stream = stream
     # the loop allocates an event per tick; a cyclic-GC pass over the
     # growing heap would stall the host for milliseconds mid-stream
