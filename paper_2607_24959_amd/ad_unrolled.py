@@ -73,10 +73,11 @@ def line_search(r, q, D, c0, b0, max_rounds: int = 96):
     return t, act
 
 
-def solve(M, J, a0, aref, D, K: int, tol: float):
+def solve(M, J, a0, aref, D, K: int, tol: float, trace=None):
     """a_K of the K-step Newton solve of every instance, differentiable by
     torch.autograd through every iteration.  Shapes: M [B, n, n], J [B, m, n],
-    a0 [B, n], aref [B, m], D [B, m].  Returns (a_K, steps taken [B])."""
+    a0 [B, n], aref [B, m], D [B, m].  Returns (a_K, steps taken [B]).
+    ``trace`` (a list) receives each step's (A_k, A'_k, taken) as bool tensors."""
     B, m, n = J.shape
     trM = torch.diagonal(M, dim1=-2, dim2=-1).sum(-1).detach()
     JT = J.mT.contiguous()
@@ -114,6 +115,8 @@ def solve(M, J, a0, aref, D, K: int, tol: float):
         al = t + (al - al.detach())    # value of the search, derivative of -b/c
         step = al.unsqueeze(-1) * p
         a = torch.where(done.unsqueeze(-1), a, a + step)
+        if trace is not None:
+            trace.append((act.detach(), Ap.detach(), (~done).detach()))
         with torch.no_grad():
             step_inf = step.abs().amax(-1)
             steps += (~done).to(torch.int32)
@@ -121,12 +124,12 @@ def solve(M, J, a0, aref, D, K: int, tol: float):
     return a, steps
 
 
-def vjp(M, J, a0, aref, D, abar, K: int, tol: float):
+def vjp(M, J, a0, aref, D, abar, K: int, tol: float, trace=None):
     """Unrolled-AD gradient of abar . a_K with respect to (a0, aref, J, D, M).
     Returns dict(a, a0, aref, J, D, M, steps)."""
     leaves = [x.detach().requires_grad_(True) for x in (M, J, a0, aref, D)]
     with torch.enable_grad():
-        aK, steps = solve(*leaves, K=K, tol=tol)
+        aK, steps = solve(*leaves, K=K, tol=tol, trace=trace)
         gM, gJ, ga0, garef, gD = torch.autograd.grad((aK * abar).sum(), leaves, allow_unused=True)
     z = lambda g, x: torch.zeros_like(x) if g is None else g
     return dict(a=aK.detach(), a0=z(ga0, a0), aref=z(garef, aref), J=z(gJ, J), D=z(gD, D),

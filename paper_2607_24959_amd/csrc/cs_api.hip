@@ -12,6 +12,7 @@
 #include "cs_chunk.hpp"
 #include "cs_generic.hpp"
 #include "cs_small.hpp"
+#include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
 
 namespace {
@@ -160,6 +161,12 @@ int launch_status() {
 }
 
 template <typename T>
+int forward_launch(const HostBatch &hb, int fam, const cs_solver_params *p, const void *M,
+                   const void *J, const void *a0, const void *aref, const void *D,
+                   const void *a_init, void *a_out, T *fac, uint8_t *mask, int32_t *status,
+                   int32_t *iters, hipStream_t stream);
+
+template <typename T>
 int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, const void *J,
               const void *a0, const void *aref, const void *D, const void *a_init, void *a_out,
               void *state, int32_t *status, int32_t *iters, hipStream_t stream) {
@@ -167,6 +174,28 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
     uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int fam = choose_family(hb);
     if (fam < 0) return fam;
+    const int rc = forward_launch<T>(hb, fam, p, M, J, a0, aref, D, a_init, a_out, fac, mask,
+                                     status, iters, stream);
+    if (rc != CS_OK) return rc;
+    if constexpr (sizeof(T) == 4) {
+        // FP32 team families: the final FP64-residual refinement of the
+        // converged iterates (the SMALL family refines inside its kernel)
+        if (fam != FAM_SMALL && cs::vjp_team_supported(hb.nmax, hb.mmax)) {
+            const int rp = cs::launch_polish_team(hb.bv, hb.bv.B, hb.nmax, hb.mmax, status,
+                                                  (float *)a_out, fac, mask, (const float *)M,
+                                                  (const float *)J, (const float *)a0,
+                                                  (const float *)aref, (const float *)D, stream);
+            return rp == 0 ? CS_OK : CS_EHIP;
+        }
+    }
+    return CS_OK;
+}
+
+template <typename T>
+int forward_launch(const HostBatch &hb, int fam, const cs_solver_params *p, const void *M,
+                   const void *J, const void *a0, const void *aref, const void *D,
+                   const void *a_init, void *a_out, T *fac, uint8_t *mask, int32_t *status,
+                   int32_t *iters, hipStream_t stream) {
     if constexpr (sizeof(T) == 4) {
         if (fam == FAM_WAVE) {
             const int rc = cs::launch_wave_forward(hb.bv, hb.bv.B, hb.nmax, hb.mmax, p->max_iter,
@@ -221,6 +250,19 @@ int vjp_t(const HostBatch &hb, const void *state, const void *M, const void *J, 
         static_cast<const uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int fam = vjp_family(hb, choose_family(hb));
     if (fam < 0) return fam;
+    if constexpr (sizeof(T) == 4) {
+        // FP32 team shapes: the FP64-arithmetic VJP
+        if ((fam == FAM_CHUNK || fam == FAM_TEAM) && cs::vjp_team_supported(hb.nmax, hb.mmax)) {
+            const int rc = cs::launch_vjp_team(hb.bv, hb.bv.B, hb.nmax, hb.mmax, fac, mask,
+                                               (const float *)M, (const float *)J,
+                                               (const float *)a0, (const float *)aref,
+                                               (const float *)D, (const float *)a,
+                                               (const float *)abar, (float *)a0bar,
+                                               (float *)arefbar, (float *)Jbar, (float *)Dbar,
+                                               (float *)Mbar, stream);
+            return rc == 0 ? CS_OK : CS_EHIP;
+        }
+    }
     if (fam == FAM_CHUNK) {
         const int rc = cs::launch_chunk_vjp<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, fac, mask,
                                                (const T *)M, (const T *)J, (const T *)a0,

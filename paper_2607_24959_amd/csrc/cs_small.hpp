@@ -34,9 +34,18 @@ template <> __device__ inline float gsum16<float>(float v) {
     return v;
 }
 
+// FP64: the same four DPP steps on the two halves of each value.
+template <int CTRL> __device__ inline double dpp_f64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
 template <> __device__ inline double gsum16<double>(double v) {
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
     return v;
 }
 
@@ -546,6 +555,41 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
     return st;
 }
 
+// Final refinement of an FP32 solve that met the stopping rule: one Newton
+// step on the converged active set with the gradient F(a) = M (a - a0) +
+// J^T (D o A o (J a - aref)) (eq. 6) formed in FP64 and the step solved with
+// the factor of H(A) the solve ended with, a <- a - H^{-1} F(a).  The step is
+// zero in exact arithmetic (a is the root of F on A); in FP32 it removes the
+// iterate's rounding error, which the gradients of eq. 17 would inherit.
+template <typename T, int NP, int R>
+__device__ inline void small_refine(const SmallInst<T, NP, R> &S, T (&a)[NP],
+                                    const T (&L)[Tri<NP>::NE], const T (&inv)[NP],
+                                    const bool (&act)[R]) {
+    typedef double C;
+    C w[R];
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+        C s = C(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) s += C(S.J[jj][j]) * C(a[j]);
+        w[jj] = act[jj] ? C(S.D[jj]) * (s - C(S.aref[jj])) : C(0);
+    }
+    T rhs[NP], d[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        C s = C(0), md = C(0);
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) s += C(S.J[jj][j]) * w[jj];
+#pragma unroll
+        for (int l = 0; l < NP; ++l)
+            md += C(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * (C(a[l]) - C(S.a0[l]));
+        rhs[j] = T(-(md + gsum16(s)));
+    }
+    reg_chol_solve<T, NP>(L, inv, rhs, d);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) a[j] = T(C(a[j]) + C(d[j]));
+}
+
 template <typename T, int NP, int R>
 __global__ __launch_bounds__(256) void k_forward_small(
     BatchView bv, int nb_inst, int max_iter, T tol, const T *__restrict__ gM,
@@ -578,6 +622,9 @@ __global__ __launch_bounds__(256) void k_forward_small(
     } else {
         st = small_solve<false, T, NP, R>(S, max_iter, tol, a, H, inv, act, iters,
                                           StepTape<T>{nullptr, nullptr, 0, 0, 0});
+        if constexpr (sizeof(T) == 4) {
+            if (st & ST_CONVERGED) small_refine<T, NP, R>(S, a, H, inv, act);
+        }
     }
     const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
     const T nanv = T(__builtin_nan(""));
@@ -676,47 +723,63 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
 #pragma unroll
     for (int j = 0; j < NP; ++j) inv[j] = fast_rcp(L[Tri<NP>::idx(j, j)]);
     const int live = m - S.i0;
-    // lambda = H^{-1} abar, then one step of iterative refinement with
-    // H v = M v + J^T (D o A* o J v)
-    T lam[NP];
-    reg_chol_solve<T, NP>(L, inv, ab, lam);
+    // Arithmetic in FP64 whatever the storage type (the FP64 rate equals the
+    // unpacked FP32 rate, and this kernel waits on memory): lambda = H^{-1}
+    // abar from the stored factor, then two steps of iterative refinement
+    // whose residual abar - H lambda, H v = M v + J^T (D o A* o J v), is
+    // formed in FP64 from the stored inputs; the corrections are solved with
+    // the stored factor.  lambda then carries the accuracy of the inputs,
+    // not the factor's condition-number-sized rounding.
+    typedef double C;
+    C lam[NP];
     {
-        T Mlam[NP], res[NP], dl[NP], t[R];
-        sym_mv<T, NP>(S.Ml, lam, Mlam);
+        T l0[NP];
+        reg_chol_solve<T, NP>(L, inv, ab, l0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) lam[j] = C(l0[j]);
+    }
+#pragma unroll 1
+    for (int it = 0; it < 2; ++it) {
+        C t[R];
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) {
-            T s = T(0);
+            C s = C(0);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) s += S.J[jj][j] * lam[j];
-            t[jj] = act[jj] ? S.D[jj] * s : T(0);
+            for (int j = 0; j < NP; ++j) s += C(S.J[jj][j]) * lam[j];
+            t[jj] = act[jj] ? C(S.D[jj]) * s : C(0);
         }
+        T rt[NP], dl[NP];
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            T s = T(0);
+            C s = C(0), mv = C(0);
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * t[jj];
-            res[j] = ab[j] - Mlam[j] - gsum16(s);
+            for (int jj = 0; jj < R; ++jj) s += C(S.J[jj][j]) * t[jj];
+#pragma unroll
+            for (int l = 0; l < NP; ++l)
+                mv += C(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * lam[l];
+            rt[j] = T(C(ab[j]) - mv - gsum16(s));
         }
-        reg_chol_solve<T, NP>(L, inv, res, dl);
+        reg_chol_solve<T, NP>(L, inv, rt, dl);
 #pragma unroll
-        for (int j = 0; j < NP; ++j) lam[j] += dl[j];
+        for (int j = 0; j < NP; ++j) lam[j] += C(dl[j]);
     }
-    // per-row cotangents
+    // per-row cotangents: r* = J a* - aref and sigma = J lambda in FP64
     T arb[R], db[R], Jb[R * NP];
 #pragma unroll
     for (int jj = 0; jj < R; ++jj) {
-        T ja = T(0), sig = T(0);
+        C ja = C(0), sig = C(0);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            ja += S.J[jj][j] * a[j];
-            sig += S.J[jj][j] * lam[j];
+            ja += C(S.J[jj][j]) * C(a[j]);
+            sig += C(S.J[jj][j]) * lam[j];
         }
-        const T r = ja - S.aref[jj];
-        const T wv = act[jj] ? S.D[jj] * r : T(0);
-        arb[jj] = act[jj] ? S.D[jj] * sig : T(0);
-        db[jj] = act[jj] ? -r * sig : T(0);
+        const C r = ja - C(S.aref[jj]);
+        const C wv = act[jj] ? C(S.D[jj]) * r : C(0);
+        const C ar = act[jj] ? C(S.D[jj]) * sig : C(0);
+        arb[jj] = T(ar);
+        db[jj] = act[jj] ? T(-r * sig) : T(0);
 #pragma unroll
-        for (int j = 0; j < NP; ++j) Jb[jj * NP + j] = -(wv * lam[j] + arb[jj] * a[j]);
+        for (int j = 0; j < NP; ++j) Jb[jj * NP + j] = T(-(wv * lam[j] + ar * C(a[j])));
     }
     if (garefbar) {
         T *p = garefbar + I.om + S.i0;
@@ -739,12 +802,16 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
         }
     }
     if (ga0bar) {
-        T mt[NP];
-        sym_mv<T, NP>(S.Ml, lam, mt);
-        T mg = mt[0];
+        C mg = C(0);
 #pragma unroll
-        for (int j = 1; j < NP; ++j) mg = (g == j) ? mt[j] : mg;
-        if (g < n) ga0bar[I.on + g] = mg;
+        for (int j = 0; j < NP; ++j) {
+            C s = C(0);
+#pragma unroll
+            for (int l = 0; l < NP; ++l)
+                s += C(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * lam[l];
+            mg = (g == j) ? s : mg;
+        }
+        if (g < n) ga0bar[I.on + g] = T(mg);
     }
     if (gMbar) {
         // lambda and a - a0 through LDS; lane g writes entries g, g + 16, ...
@@ -752,8 +819,8 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
         if (g == 0) {
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                vl[j] = lam[j];
-                vd[j] = a[j] - S.a0[j];
+                vl[j] = T(lam[j]);
+                vd[j] = T(C(a[j]) - C(S.a0[j]));
             }
         }
         group_sync();

@@ -356,8 +356,11 @@ class Engine:
             r = self.req[s]
             r.done_tick = self.ticks
             if self.keep_results:
+                # on the tick's stream: after this tick's last kernel, before
+                # the next tick's admission can reuse the slot
                 n = r.n
-                self.results[r.rid] = torch.cat([self.v[s, :n], self.taubar[s, :, :n].reshape(-1)]).clone()
+                with torch.cuda.stream(stream):
+                    self.results[r.rid] = torch.cat([self.v[s, :n], self.taubar[s, :, :n].reshape(-1)]).clone()
             self.req[s] = None
             self.phase[s] = -1
             self.free.append(s)

@@ -139,18 +139,100 @@ def test_rollout_forward_matches_oracle_driven_rollout():
     assert err.max() <= 1e-9, err.max()
 
 
-def test_rollout_fp32_gradient_close_to_fp64():
+def _oracle_rollout_grad(Pn, b, max_iter, tol):
+    """tau-bar of instance b's rollout loss, driven by the oracle: forwards step by
+    step, then the IFT adjoints in reverse (a-bar_t = h v-bar_{t+1},
+    tau-bar_t = M^-T a0-bar_t, v-bar_t = v-bar_{t+1} - b_damp J^T aref-bar_t)."""
+    M, J, D = Pn["M"][b], Pn["J"][b], Pn["D"][b]
+    pen_rows = np.repeat(Pn["pen"][b], 4)
+    v = Pn["v0"][b].copy()
+    steps = []
+    for t in range(Pn["tau"].shape[0]):
+        a0 = np.linalg.solve(M, Pn["tau"][t, b])
+        aref = -synth.B_DAMP * (J @ v) - synth.K_SPRING * pen_rows
+        res = oracle.forward(M, J, a0, aref, D, max_iter=max_iter, tol=tol)
+        steps.append((a0, aref, res["a"], res["active"], res["status"]))
+        v = v + H_STEP * res["a"]
+    vbar = 2.0 * (v - Pn["v_goal"][b])
+    taubar = np.zeros((Pn["tau"].shape[0], M.shape[0]))
+    for t in reversed(range(len(steps))):
+        a0, aref, a, act, _ = steps[t]
+        g = oracle.ift_vjp(M, J, a0, aref, D, a, H_STEP * vbar, active=act)
+        taubar[t] = np.linalg.solve(M.T, g["a0"])
+        vbar = vbar - synth.B_DAMP * (J.T @ g["aref"])
+    return taubar, all(s[4] == oracle.ST_CONVERGED for s in steps)
+
+
+def test_rollout_gradient_matches_oracle_adjoint():
+    """Config 3 (B=1024, nv=18, 32 contacts, horizon 50, FP64): the first 48
+    instances' tau gradient against the oracle-driven adjoint, each within 1e-9."""
     _needs_gpu()
-    P64 = make_rollout_problem(256, 18, 32, 20, seed=20260730)
-    P32 = {k: v.float() for k, v in P64.items()}
-    out = {}
-    for name, P in (("64", P64), ("32", P32)):
+    P = make_rollout_problem(1024, 18, 32, 50, seed=20260727)
+    tau = P["tau"].clone().requires_grad_(True)
+    _loss_per_instance(P, tau, max_iter=60).sum().backward()
+    g = tau.grad.detach().cpu().numpy()
+    Pn = {k: v.cpu().numpy() for k, v in P.items()}
+    errs = []
+    for b in range(48):
+        ref, conv = _oracle_rollout_grad(Pn, b, 60, 1e-12)
+        assert conv, b
+        errs.append(np.linalg.norm(g[:, b] - ref) / np.linalg.norm(ref))
+    print("rollout gradient vs oracle adjoint: max", max(errs))
+    assert max(errs) <= 1e-9, max(errs)
+
+
+def test_rollout_fp32_gradient_close_to_fp64():
+    """FP32 rollout gradient against FP64 on the same (FP32-rounded) inputs,
+    instance by instance, wherever both rollouts take the same contact schedule
+    (every step's active set and status): within 1e-3, or, where the FP64
+    gradient itself moves by more than 1e-4 under a one-rounding-unit (2^-24)
+    perturbation of the rollout's inputs, within 10 times that movement."""
+    _needs_gpu()
+    P32 = {k: v.float() for k, v in make_rollout_problem(256, 18, 32, 20, seed=20260730).items()}
+    P64 = {k: v.double() for k, v in P32.items()}
+
+    def grad(P, collect=None):
         tau = P["tau"].clone().requires_grad_(True)
-        _loss_per_instance(P, tau, max_iter=60).sum().backward()
-        out[name] = tau.grad.detach().double().transpose(0, 1).reshape(256, -1).cpu().numpy()
-    e = np.linalg.norm(out["32"] - out["64"], axis=1) / np.linalg.norm(out["64"], axis=1)
-    print("FP32 vs FP64 rollout gradient: median", np.median(e), "p90", np.percentile(e, 90))
-    assert np.median(e) <= 1e-3
+        _loss_per_instance(P, tau, max_iter=60, collect=collect).sum().backward()
+        return tau.grad.detach().double().transpose(0, 1).reshape(256, -1).cpu().numpy()
+
+    c64, c32 = [], []
+    g64 = grad(P64, c64)
+    g32 = grad(P32, c32)
+    s64 = _schedule(P64, c64)
+    s32 = _schedule(P64, [(a.double(), st) for a, st in c32])
+    same = np.all(s64 == s32, axis=(1, 2)) & np.all(s64[:, :, -1] == N.ST_CONVERGED, axis=1)
+    # a step whose solution has a row within 1e-7 (relative) of the cone
+    # boundary is degenerate (one-sided derivative): such rollouts are left out
+    v = P64["v0"]
+    pen_rows = torch.repeat_interleave(P64["pen"], 4, dim=-1)
+    step_deg = []
+    for a, _ in c64:
+        aref = -synth.B_DAMP * torch.bmm(P64["J"], v.unsqueeze(-1)).squeeze(-1) - synth.K_SPRING * pen_rows
+        r = torch.bmm(P64["J"], a.unsqueeze(-1)).squeeze(-1) - aref
+        sc = aref.abs() + torch.bmm(P64["J"].abs(), a.abs().unsqueeze(-1)).squeeze(-1)
+        step_deg.append(((r.abs() / sc).amin(-1) < 1e-7).cpu().numpy())
+        v = v + H_STEP * a
+    step_deg = np.stack(step_deg, 1)
+    deg = step_deg.any(axis=1)
+    print("degenerate solves", step_deg.mean(), "rollouts with one", int(deg.sum()))
+    assert step_deg.mean() < 0.01
+    same &= ~deg
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    sens = np.zeros(256)
+    for _ in range(2):
+        Pp = {k: v * (1 + 2.0 ** -24 * (2 * torch.randint(0, 2, v.shape, generator=gen) - 1)
+                      .to(v.device, torch.float64)) for k, v in P64.items()}
+        gp = grad(Pp)
+        sens = np.maximum(sens, np.linalg.norm(gp - g64, axis=1) / np.linalg.norm(g64, axis=1))
+    e = np.linalg.norm(g32 - g64, axis=1) / np.linalg.norm(g64, axis=1)
+    bound = np.maximum(1e-3, 10 * sens)
+    print("FP32 vs FP64 rollout gradient: same schedule", same.mean(), "max", e[same].max(),
+          "ill-conditioned", int((same & (bound > 1e-3)).sum()))
+    assert same.mean() >= 0.85
+    bad = np.flatnonzero(same & (e > bound))
+    nr = np.linalg.norm(g64, axis=1)
+    assert bad.size == 0, [(int(i), float(e[i]), float(sens[i]), float(nr[i] / np.median(nr))) for i in bad[:5]]
 
 
 def _peak_backward_bytes(P, backward, K):
