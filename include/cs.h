@@ -175,6 +175,26 @@ int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params,
                     void *tape, size_t tape_bytes, int32_t *status, int32_t *iters,
                     void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as cs_unrolled_vjp with flags 0 (record and reverse sweep in
+ * one call), with the tape in a library-owned static device array of
+ * CS_STATIC_TAPE_BYTES bytes instead of a caller buffer.  Each GPU the
+ * library runs on holds its own array until the process ends; every call on
+ * a GPU uses that GPU's array (on the device current at the call), so calls
+ * that overlap on one GPU (different streams, no ordering between them) race
+ * and give undefined results.  The tape is written before it is read within
+ * a call: nothing carries over from the previous call.  Returns CS_ENOSPC
+ * when cs_unrolled_tape_bytes(batch, params->max_iter) exceeds
+ * CS_STATIC_TAPE_BYTES, CS_EINVAL for params->flags != 0 and otherwise the
+ * errors of cs_unrolled_vjp.  Allocates nothing. */
+#define CS_STATIC_TAPE_BYTES ((size_t)64 << 20)
+int cs_unrolled_vjp_static(const cs_batch *batch, const cs_solver_params *params,
+                           const void *M, const void *J, const void *a0, const void *aref,
+                           const void *D, const void *abar, void *a_out,
+                           void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar,
+                           int32_t *status, int32_t *iters, void *stream);
+
 /* Name of an error code. */
 const char *cs_strerror(int code);
 

@@ -16,9 +16,10 @@ CS_OK, CS_EINVAL, CS_ENOSPC, CS_EHIP, CS_EUNSUPPORTED = 0, -1, -2, -3, -4
 CS_F32, CS_F64 = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL = 1, 2, 4, 8, 16
 NV_MAX, NROWS_MAX = 128, 4096
+STATIC_TAPE_BYTES = 64 << 20
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
 
-EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_state_bytes",
+EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_unrolled_vjp_static", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
             "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
 
@@ -91,6 +92,9 @@ def lib():
         L.cs_unrolled_vjp.restype = C.c_int
         L.cs_unrolled_vjp.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                       sz, vp, vp, vp]
+        L.cs_unrolled_vjp_static.restype = C.c_int
+        L.cs_unrolled_vjp_static.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             vp, vp, vp, vp]
         pt = C.POINTER(CsServeTable)
         L.cs_serve_admit.restype = C.c_int
         L.cs_serve_admit.argtypes = [pt, pt, vp, i32, vp]
@@ -142,6 +146,14 @@ def unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, 
     return lib().cs_unrolled_vjp(C.byref(batch), C.byref(params), M, J, a0, aref, D, abar, a_out,
                                  a0bar, arefbar, Jbar, Dbar, Mbar, tape, tape_nbytes, status,
                                  iters, stream)
+
+
+def unrolled_vjp_static(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
+                        Dbar, Mbar, status, iters, stream):
+    """cs_unrolled_vjp_static: the unrolled VJP with the library's static tape."""
+    return lib().cs_unrolled_vjp_static(C.byref(batch), C.byref(params), M, J, a0, aref, D, abar,
+                                        a_out, a0bar, arefbar, Jbar, Dbar, Mbar, status, iters,
+                                        stream)
 
 
 def serve_admit(table, pool, pairs, count, stream):

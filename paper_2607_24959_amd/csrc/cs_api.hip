@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "cs.h"
 #include "cs_chunk.hpp"
@@ -15,9 +16,33 @@
 #include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
 
+// The tape of cs_unrolled_vjp_static: one array per GPU, for the life of the
+// process.  Host code never uses this name as an address (it is a host-side
+// stand-in); static_tape_ptr() gives the device address on the current GPU.
+static __device__ __align__(256) unsigned char scratch[CS_STATIC_TAPE_BYTES];
+
 namespace {
 
 constexpr int kAbiVersion = 1;
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current GPU, looked up once per device
+// (with that device current) and kept.
+int static_tape_ptr(void **out) {
+    static std::mutex mu;
+    static void *ptr[kMaxDevices];
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return CS_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return CS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CS_EHIP;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return CS_OK;
+}
 constexpr int kMaxIterCap = 100000;
 constexpr size_t kLdsLimit = 160 * 1024;
 
@@ -434,6 +459,22 @@ int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params, const
                                  Jbar, Dbar, Mbar, tape, status, iters, s);
     return unrolled_t<double>(hb, params, mode, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
                               Dbar, Mbar, tape, status, iters, s);
+}
+
+int cs_unrolled_vjp_static(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                           const void *J, const void *a0, const void *aref, const void *D,
+                           const void *abar, void *a_out, void *a0bar, void *arefbar, void *Jbar,
+                           void *Dbar, void *Mbar, int32_t *status, int32_t *iters, void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = check_params(params, true)) != CS_OK) return rc;
+    if (params->flags != 0) return CS_EINVAL;
+    if (tape_bytes(hb, params->max_iter) > CS_STATIC_TAPE_BYTES) return CS_ENOSPC;
+    void *tape = nullptr;
+    if ((rc = static_tape_ptr(&tape)) != CS_OK) return rc;
+    return cs_unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar,
+                           Dbar, Mbar, tape, CS_STATIC_TAPE_BYTES, status, iters, stream);
 }
 
 }  // extern "C"

@@ -127,3 +127,19 @@ def test_batch_wrapper_checks_shapes():
         b.check("J", torch.zeros(4, 8, 3, dtype=torch.float64), 4 * 8 * 3)
     with pytest.raises(ValueError):
         solver.Batch.packed_from(np.array([3, 0]), np.array([4, 4]), device="cpu")
+
+
+def test_static_tape_entry_rejects_before_any_launch():
+    """cs_unrolled_vjp_static checks its limits on the host: a tape larger than
+    the static array is CS_ENOSPC, a RECORD/REPLAY phase is CS_EINVAL."""
+    b = solver.Batch.uniform(4096, 9, 64, torch.float32, device="cpu")
+    big = 1
+    while b.tape_bytes(big) <= N.STATIC_TAPE_BYTES:
+        big += 1
+    p = N.CsSolverParams(big, 0, 1e-5)
+    z = C.c_void_p(16)   # never dereferenced: the call returns before any launch
+    args = [z] * 12 + [z, z, None]
+    assert N.unrolled_vjp_static(b.desc, p, *args) == N.CS_ENOSPC
+    for flags in (1, 2):
+        p = N.CsSolverParams(10, flags, 1e-5)
+        assert N.unrolled_vjp_static(b.desc, p, *args) == N.CS_EINVAL
