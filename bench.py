@@ -7,16 +7,23 @@ inputs resident in HBM.  Steps rotate over enough distinct batches (seeded
 synthetic inputs) that their working set exceeds twice the 256 MB last-level
 (MALL) cache.  Prints one JSON line.
 
-The throughput comes from one replay of a HIP graph of the K steps in which
-each batch's VJP runs on a second stream, overlapping the next batch's
-forward (--no-overlap: a graph of the K steps one launch after another; both
-step times are reported).  An eager sequential pass over the same K steps
-with HIP events around every launch gives the per-kernel durations behind
-the dominant kernel's roofline position.  Also measured
-(reported inside the same line): the unrolled-trace gradient at the same K on
-the same GPU (the library's fused trace kernels, and plain reverse-mode AD of
-the same solve by PyTorch autograd), the state/tape memory, and the FP64
-oracle timed on the host cores on a bounded sample.
+The K timed steps are captured once into a HIP graph; the value is the median
+over 20 timed replays of that graph (each replay exactly K steps, bracketed by
+synchronisation; one untimed replay first).  In the headline graph each
+batch's VJP runs on a second stream once its forward is done, overlapping the
+next batch's forward (sequential: one stream, one launch after another; both
+reported).
+An eager sequential pass over the same K steps with HIP events around every
+launch gives the per-kernel durations behind the dominant kernel's roofline
+position.
+
+Also in the same line: the same workload with a cap (K = 40) at which every
+instance converges, so the IFT is evaluated at the tolerance-converged root
+the paper's derivative is defined at; the FP64 path at the same shape; the
+unrolled-trace gradient at K = 10 (the library's fused trace kernels, timed
+from a graph like the IFT path, and plain reverse-mode AD of the same solve by
+PyTorch autograd); the K sweep with memory; the uneven batch; the serving
+streams; and the FP64 oracle timed on the host cores on bounded samples.
 """
 from __future__ import annotations
 
@@ -35,6 +42,7 @@ sys.path.insert(0, ROOT)
 B, NV, NC = 4096, 9, 16
 M_ROWS = 4 * NC
 K_CAP, TOL = 10, 1e-5
+K_CONV = 40               # cap at which every instance of the workload converges
 MALL_BYTES = 256 * 2 ** 20
 HBM_PEAK = 8.0e12          # B/s
 FP32_VEC_PEAK = 157.3e12   # flop/s (256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz)
@@ -98,27 +106,51 @@ def make_batches(count, seed0):
 
 
 def cpu_baseline(b32, seconds=10.0):
-    """The FP64 oracle (unmodified) on the FP32-rounded inputs of one batch."""
+    """The FP64 oracle (unmodified) on the FP32-rounded inputs of one batch,
+    on all host threads; also on one thread, and on a stratified sample of the
+    uneven batch."""
     import oracle
+    from paper_2607_24959_amd import synth
     b64 = b32.astype(np.float64)
     P = oracle.Packed.uniform(b64.M, b64.J, b64.a0, b64.aref, b64.D, b64.abar)
+
+    def rate(P, threads, seconds):
+        done, reps, t0 = 0, 0, time.perf_counter()
+        while True:
+            fw = P.forward(max_iter=K_CAP, tol=1e-10, threads=threads)
+            P.ift_vjp(fw["a"], fw["active"], threads=threads)
+            done += P.B
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return done / el, reps, el
+
     threads = oracle.max_threads()
-    done, t0 = 0, time.perf_counter()
-    reps = 0
-    while True:
-        fw = P.forward(max_iter=K_CAP, tol=1e-10, threads=threads)
-        P.ift_vjp(fw["a"], fw["active"], threads=threads)
-        done += P.B
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return dict(value=done / el, unit="solves/s", cores=threads, kind="oracle",
+    v, reps, el = rate(P, threads, seconds)
+    v1, reps1, el1 = rate(P, 1, seconds / 3)
+    # the uneven batch: 82 instances of every nv (5 % of B = 8192), same seed
+    pb = synth.uneven_batch(8192, (3, 9, 18, 36, 96), 256, seed=synth.SEED_BASE + 2)
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(np.flatnonzero(pb.nv == n), 82, replace=False)
+                          for n in (3, 9, 18, 36, 96)])
+    sub = synth.pack([dict(n=int(pb.nv[i]), **{k: x for k, x in pb.get(i).items()
+                                               if k in ("M", "J", "a0", "aref", "D", "abar")})
+                      for i in idx]).rounded(np.float32)
+    Pu = oracle.Packed(sub.nv, sub.nrows, sub.M, sub.J, sub.a0, sub.aref, sub.D, sub.abar)
+    vu, repsu, elu = rate(Pu, threads, 0.0)
+    return dict(value=v, unit="solves/s", cores=threads, kind="oracle",
                 sample=f"{reps} passes of forward + IFT VJP over one B={B} batch (FP64 oracle on "
-                       f"the FP32-rounded inputs, {threads} OpenMP threads, {el:.1f} s)")
+                       f"the FP32-rounded inputs, {threads} OpenMP threads, {el:.1f} s)",
+                one_core={"value": v1, "unit": "solves/s",
+                          "sample": f"{reps1} passes, 1 thread, {el1:.1f} s"},
+                uneven_sample={"value": vu, "unit": "solves/s", "instances": int(idx.size),
+                               "ms_per_B8192_batch_scaled": 8192 / vu * 1e3,
+                               "sample": "stratified 5 % of the uneven batch (82 instances of "
+                                         f"every nv), forward cap 10 + IFT VJP, {threads} threads, "
+                                         f"{elu:.1f} s"})
 
 
-def k_sweep(bufs, batch, steps=30):
+def k_sweep(bufs, batch, steps=20):
     """IFT (forward at cap K + VJP) against the unrolled trace at K = 1..10:
     time per batch and the temporary device memory of each gradient path."""
     import torch
@@ -138,17 +170,26 @@ def k_sweep(bufs, batch, steps=30):
                                    out=grads)
                 else:
                     solver.unrolled_vjp(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
-                                        K=K, tol=TOL, tape=tape)
+                                        K=K, tol=TOL, tape=tape, out=uouts[i % R])
+            if mode == "unrolled":
+                uouts = [solver.unrolled_vjp(batch, b[0]["M"], b[0]["J"], b[0]["a0"], b[0]["aref"],
+                                             b[0]["D"], b[0]["abar"], K=K, tol=TOL, tape=tape)
+                         for b in bufs]
             for i in range(3):
                 run(i)
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for i in range(steps):
-                run(i)
-            e1.record()
+            # both paths timed alike: a graph of `steps` steps on one stream
+            g = torch.cuda.CUDAGraph()
+            cap = torch.cuda.Stream()
+            cap.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cap), torch.cuda.graph(g, stream=cap):
+                for i in range(steps):
+                    run(i)
+            torch.cuda.current_stream().wait_stream(cap)
             torch.cuda.synchronize()
-            row[f"{mode}_ms"] = e0.elapsed_time(e1) / steps
+            ms, _ = replay_median(g, reps=5)
+            del g
+            row[f"{mode}_ms"] = ms / steps
             # peak temporary memory of one fresh call (outputs allocated by the call)
             torch.cuda.synchronize()
             base = torch.cuda.memory_allocated()
@@ -259,18 +300,192 @@ def serving(rates=(2000, 5000, 10000, 20000, 50000), n_requests=10000, warmup=10
     return out
 
 
+N_REPLAYS = 20
+
+
+SCHEDULES = ("sequential", "vjp_overlap", "two_chains")
+
+
+def capture_steps(bufs, batch, steps, K, tol, schedule):
+    """HIP graph of `steps` steps (forward at cap K + IFT VJP, batch i % R at
+    step i), in one of three schedules:
+      sequential  -- one stream, one launch after another;
+      vjp_overlap -- forwards on one stream, each VJP on a second once its
+                     forward is done (overlapping the next batch's forward); a
+                     forward that rewrites a batch's solution first waits for
+                     that batch's previous VJP;
+      two_chains  -- step i on stream i % 2 (R is even, so a batch always runs
+                     on the same stream and no event is needed): two
+                     independent chains of batches share the device.
+    Returns (graph, keep): every stream and event the capture used is in
+    `keep`, alive as long as the graph."""
+    import torch
+    from paper_2607_24959_amd import solver
+    R = len(bufs)
+    assert schedule != "two_chains" or R % 2 == 0
+    g = torch.cuda.CUDAGraph()
+    nst = 1 if schedule == "sequential" else 2
+    streams = [torch.cuda.Stream() for _ in range(nst)]     # default priority
+    keep = {"streams": streams, "events": []}
+    cap = streams[0]
+    cap.wait_stream(torch.cuda.current_stream())
+    last_vjp = [None] * R
+    with torch.cuda.stream(cap), torch.cuda.graph(g, stream=cap):
+        for st in streams[1:]:
+            st.wait_stream(cap)
+        for i in range(steps):
+            j = i % R
+            t, sol, grads = bufs[j]
+            if schedule == "two_chains":
+                fl = vl = streams[i % 2]
+            elif schedule == "vjp_overlap":
+                fl, vl = cap, streams[1]
+            else:
+                fl = vl = cap
+            if last_vjp[j] is not None:
+                fl.wait_event(last_vjp[j])
+            with torch.cuda.stream(fl):
+                solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K,
+                               tol=tol, out=sol)
+            if vl is not fl:
+                ef = torch.cuda.Event()
+                ef.record(fl)
+                keep["events"].append(ef)
+                vl.wait_event(ef)
+            with torch.cuda.stream(vl):
+                solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                               out=grads)
+            if vl is not fl:
+                ev = torch.cuda.Event()
+                ev.record(vl)
+                keep["events"].append(ev)
+                last_vjp[j] = ev
+        for st in streams[1:]:
+            cap.wait_stream(st)
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    return g, keep
+
+
+def replay_median(g, reps=N_REPLAYS):
+    """Median over `reps` timed replays (one untimed first) of max(GPU ms by
+    HIP events, host wall ms), each replay bracketed by synchronisation."""
+    import torch
+    g.replay()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(max((time.perf_counter() - t0) * 1e3, e0.elapsed_time(e1)))
+    out = np.array(out)
+    return float(np.median(out)), {"min_ms": float(out.min()), "max_ms": float(out.max()),
+                                   "replays": reps}
+
+
+def kernel_times(bufs, batch, steps, K, tol):
+    """Eager sequential pass of the same steps with HIP events around every
+    launch on the launch stream: mean forward and VJP kernel ms."""
+    import torch
+    from paper_2607_24959_amd import solver
+    R = len(bufs)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        t, sol, grads = bufs[i % R]
+        evs[i][0].record()
+        solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=tol,
+                       out=sol)
+        evs[i][1].record()
+        solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
+        evs[i][2].record()
+    torch.cuda.synchronize()
+    t_fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    t_vjp = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    return t_fwd, t_vjp
+
+
+def solve_stats(bufs, batch, B_, m):
+    """Convergence, iterations, active rows and line-search safeguard hits over
+    every rotating batch (as the last pass left them)."""
+    st = np.concatenate([b[1].status.cpu().numpy() for b in bufs])
+    it = np.concatenate([b[1].iters.cpu().numpy() for b in bufs])
+    act0 = batch.active_sets(bufs[0][1]).reshape(B_, m).sum(1)
+    return {"converged_frac": float(np.mean(st & 1)), "mean_iters": float(it.mean()),
+            "max_iters": int(it.max()), "lsfail_count": int(np.sum((st & 16) != 0)),
+            "instances": int(st.size), "mean_active_rows": float(act0.mean())}, act0, \
+        bufs[0][1].iters.cpu().numpy()
+
+
+def make_bufs(host, batch, dev, K, tol, dtype):
+    import torch
+    from paper_2607_24959_amd import solver
+    keys = ("M", "J", "a0", "aref", "D", "abar")
+    bufs = []
+    for hb in host:
+        t = {k: torch.from_numpy(np.ascontiguousarray(getattr(hb, k))).to(dev, dtype) for k in keys}
+        sol = solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=tol)
+        grads = solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"])
+        bufs.append((t, sol, grads))
+    torch.cuda.synchronize()
+    return bufs
+
+
+def rotation(s, state_bytes):
+    """Rotating batches: at least 8, and more than twice the MALL in total."""
+    per_batch = B * s * (NV * NV * 2 + M_ROWS * NV * 2 + NV * 4 + M_ROWS * 4) + state_bytes
+    R = max(8, math.ceil(2 * MALL_BYTES / per_batch) + 1)
+    return R + (R % 2), per_batch
+
+
+def ift_line(bufs, batch, steps, K, tol, schedules=SCHEDULES, s=4):
+    """One throughput line: a graph of `steps` steps at cap K in each schedule,
+    median of replays each; the line's value is the fastest schedule's.  Also
+    per-kernel times, solver statistics and the forward's roofline position."""
+    per = {}
+    for sch in schedules:
+        g, keep = capture_steps(bufs, batch, steps, K, tol, sch)
+        ms_s, spread_s = replay_median(g)
+        del g, keep
+        per[sch] = {"ms_per_step": ms_s / steps, "replay_spread": spread_s}
+    best = min(per, key=lambda k: per[k]["ms_per_step"])
+    ms, spread = per[best]["ms_per_step"] * steps, per[best]["replay_spread"]
+    t_fwd, t_vjp = kernel_times(bufs, batch, steps, K, tol)
+    # the eager pass above left batches 0 .. steps-1 solved at cap K
+    stats, act, it = solve_stats(bufs[:min(steps, len(bufs))], batch, B, M_ROWS)
+    fwd_b, vjp_b = algorithmic_bytes(NV, M_ROWS, s)
+    flops = float(np.sum(forward_flops(NV, M_ROWS, act, it)))
+    value = B * steps / (ms / 1e3)
+    return {"value": value, "ms_per_step": ms / steps, "replay_spread": spread, "schedule": best,
+            "schedules_ms_per_step": {k: v["ms_per_step"] for k, v in per.items()},
+            "K": K, "tol": tol,
+            "kernels": {"forward_ms": t_fwd, "ift_vjp_ms": t_vjp,
+                        "forward_tflops": flops / (t_fwd / 1e3) / 1e12,
+                        "forward_gbps": B * fwd_b / (t_fwd / 1e3) / 1e9,
+                        "ift_vjp_gbps": B * vjp_b / (t_vjp / 1e3) / 1e9,
+                        "ift_vjp_hbm_frac": B * vjp_b / (t_vjp / 1e3) / HBM_PEAK,
+                        "forward_flops_per_launch": flops},
+            "gbps_algorithmic": value * (fwd_b + vjp_b) / 1e9,
+            "solver": stats}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-unrolled", action="store_true")
     ap.add_argument("--no-ad", action="store_true", help="skip the plain unrolled-AD comparison")
-    ap.add_argument("--no-overlap", action="store_true",
-                    help="time the throughput pass with forward and VJP one after another")
+    ap.add_argument("--schedule", choices=SCHEDULES + ("all",), default="all",
+                    help="graph schedule of the timed steps (all: time each, report the fastest)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the K sweep, the uneven batch and the serving streams")
+                    help="skip the converging, FP64, K-sweep, uneven and serving lines")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
     ap.add_argument("--section", choices=("uneven", "serving"),
@@ -307,123 +522,27 @@ def main():
     dev = torch.device("cuda:0")
 
     fwd_b, vjp_b = algorithmic_bytes(NV, M_ROWS)
-    per_batch = (B * 4 * (NV * NV * 2 + M_ROWS * NV * 2 + NV * 4 + M_ROWS * 4)
-                 + solver.Batch.uniform(B, NV, M_ROWS, torch.float32, device="cpu").state_bytes())
-    R = max(8, math.ceil(2 * MALL_BYTES / per_batch) + 1)
-    host = make_batches(R, 20260725)
     batch = solver.Batch.uniform(B, NV, M_ROWS, torch.float32, device=dev)
-    keys = ("M", "J", "a0", "aref", "D", "abar")
-    bufs = []
-    for hb in host:
-        t = {k: torch.from_numpy(np.ascontiguousarray(getattr(hb, k))).to(dev) for k in keys}
-        sol = solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CAP, tol=TOL)
-        grads = solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"])
-        bufs.append((t, sol, grads))
-    torch.cuda.synchronize()
-
-    def step(i, ev=None):
+    R, per_batch = rotation(4, batch.state_bytes())
+    host = make_batches(R, 20260725)
+    bufs = make_bufs(host, batch, dev, K_CAP, TOL, torch.float32)
+    # warm-up: W untimed steps
+    for i in range(args.warmup):
         t, sol, grads = bufs[i % R]
-        if ev is not None:
-            ev[0].record()
         solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CAP, tol=TOL,
                        out=sol)
-        if ev is not None:
-            ev[1].record()
         solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
-        if ev is not None:
-            ev[2].record()
-
-    # The timed steps run from HIP graphs (one capture of all K steps), so the
-    # host's per-call argument checks stay out of the timed region.  In the
-    # pipelined graph each batch's VJP runs on a second stream once its
-    # forward has finished, overlapping the next batch's forward; the
-    # forward that next rewrites a batch's solution buffer first waits for
-    # that batch's previous VJP.  Every step is still one forward + one VJP
-    # over one batch.
-    def capture(pipelined):
-        g = torch.cuda.CUDAGraph()
-        cap, side = torch.cuda.Stream(), torch.cuda.Stream()   # default priority
-        ev_f = [torch.cuda.Event() for _ in range(args.steps)]
-        ev_v = [None] * R
-        cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(cap), torch.cuda.graph(g, stream=cap):
-            side.wait_stream(cap)
-            for i in range(args.steps):
-                j = i % R
-                t, sol, grads = bufs[j]
-                if pipelined and ev_v[j] is not None:
-                    cap.wait_event(ev_v[j])
-                solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"],
-                               max_iter=K_CAP, tol=TOL, out=sol)
-                if not pipelined:
-                    solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"],
-                                   t["abar"], out=grads)
-                    continue
-                ev_f[i].record(cap)
-                side.wait_event(ev_f[i])
-                with torch.cuda.stream(side):
-                    solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"],
-                                   t["abar"], out=grads)
-                ev_v[j] = torch.cuda.Event()
-                ev_v[j].record(side)
-            cap.wait_stream(side)
-        torch.cuda.current_stream().wait_stream(cap)
-        torch.cuda.synchronize()
-        return g
-
-    def timed(g):
-        """One replay of a K-step graph; returns (wall ms, GPU ms)."""
-        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g0.record()
-        g.replay()
-        g1.record()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3, g0.elapsed_time(g1)
-
-    for i in range(args.warmup):
-        step(i)
     torch.cuda.synchronize()
-    graphs = {"sequential": capture(False)}
-    if not args.no_overlap:
-        graphs["pipelined"] = capture(True)
-    for g in graphs.values():   # first replay uploads the graph; untimed
-        g.replay()
-    torch.cuda.synchronize()
-    # timed region 1 (the throughput): the K pipelined steps, or the K
-    # sequential steps with --no-overlap (the profiled configuration: there
-    # every kernel runs alone, so its traced duration is its own)
-    wall_seq, gpu_seq = timed(graphs["sequential"])
-    if args.no_overlap:
-        wall, gpu_ms = wall_seq, gpu_seq
-    else:
-        wall, gpu_ms = timed(graphs["pipelined"])
-    ms = max(wall, gpu_ms)
-    value = B * args.steps / (ms / 1e3)
-    # timed region 2 (the per-kernel durations for the roofline): the same K
-    # steps with HIP events around every launch, on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, evs[i])
-    torch.cuda.synchronize()
-    wall_ev = time.perf_counter() - t1
-    progress(f"headline: {value:.4g} solves/s ({ms / args.steps * 1e3:.1f} us per step)")
-    t_fwd = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    t_vjp = np.array([e[1].elapsed_time(e[2]) for e in evs])
 
-    # convergence / active-set statistics of the benchmarked solves (one batch)
-    st = bufs[0][1].status.cpu().numpy()
-    it = bufs[0][1].iters.cpu().numpy()
-    sb = batch.state_bytes()
-    act = batch.active_sets(bufs[0][1]).reshape(B, M_ROWS).sum(1)
-    flops_per_launch = float(np.sum(forward_flops(NV, M_ROWS, act, it)))
-    fwd_s = float(np.mean(t_fwd)) / 1e3
-    vjp_s = float(np.mean(t_vjp)) / 1e3
-    fwd_flops_rate = flops_per_launch / fwd_s
-    vjp_gbps = B * vjp_b / vjp_s
+    scheds = SCHEDULES if args.schedule == "all" else (args.schedule,)
+    head = ift_line(bufs, batch, args.steps, K_CAP, TOL, scheds)
+    value = head["value"]
+    seq_ms = head["schedules_ms_per_step"].get("sequential")
+    progress(f"headline: {value:.4g} solves/s ({head['ms_per_step'] * 1e3:.1f} us per step, "
+             f"{head['schedule']}); per schedule (us): "
+             + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in head["schedules_ms_per_step"].items()))
+    kh = head["kernels"]
+    fwd_rate = kh["forward_flops_per_launch"] / (kh["forward_ms"] / 1e3)
 
     out = {
         "metric": "fwd+IFT-VJP contact solves/sec and GB/s vs unrolled-AD; p50/p99 latency",
@@ -432,17 +551,16 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "timing": {"wall_ms": wall, "gpu_ms": gpu_ms, "overlap": not args.no_overlap,
-                   "sequential_ms_per_step": max(wall_seq, gpu_seq) / args.steps,
-                   "instrumented_pass_ms": wall_ev * 1e3,
-                   "kernel_sum_ms": float(np.sum(t_fwd) + np.sum(t_vjp)),
-                   "note": "value from one replay of a HIP graph of the K steps, each batch's "
-                           "VJP overlapping the next batch's forward on a second stream "
-                           "(sequential_ms_per_step: a graph of the same K steps one launch "
-                           "after another; each graph replayed once untimed first); "
-                           "per-kernel durations (kernels, roofline) from an eager sequential "
-                           "pass of the same K steps with HIP events around every launch"},
+        "ms_per_step": head["ms_per_step"],
+        "timing": {"replay_spread": head["replay_spread"], "schedule": head["schedule"],
+                   "schedules_ms_per_step": head["schedules_ms_per_step"],
+                   "note": f"value: median over {N_REPLAYS} timed replays of one HIP graph of "
+                           "the K steps (each replay bracketed by synchronisation, max of GPU "
+                           "and host time; one untimed replay first), in the fastest of three "
+                           "schedules (one stream; VJPs on a second stream overlapping the next "
+                           "forward; two independent chains of batches on two streams); "
+                           "per-kernel durations from an eager sequential pass with HIP events "
+                           "around every launch"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -452,48 +570,50 @@ def main():
                                "forward (Newton cap K=10, tol 1e-5) + IFT VJP",
                    "B": B, "nv": NV, "contacts": NC, "rows": M_ROWS, "K": K_CAP, "tol": TOL,
                    "rotating_batches": R, "working_set_MB": round(R * per_batch / 2 ** 20, 1)},
-        "gbps_algorithmic": value * (fwd_b + vjp_b) / 1e9,
+        "gbps_algorithmic": head["gbps_algorithmic"],
         "bytes_per_solve": {"forward": fwd_b, "ift_vjp": vjp_b},
-        "kernels": {
-            "forward_ms": fwd_s * 1e3, "ift_vjp_ms": vjp_s * 1e3,
-            "forward_tflops": fwd_flops_rate / 1e12,
-            "ift_vjp_gbps": vjp_gbps / 1e9, "ift_vjp_hbm_frac": vjp_gbps / HBM_PEAK,
-        },
+        "kernels": kh,
         "roofline": {"kernel": "k_forward_small<float,9,4>", "bound": "alu",
-                     "achieved": fwd_flops_rate / 1e12, "peak": FP32_VEC_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": fwd_flops_rate / FP32_VEC_PEAK,
+                     "achieved": fwd_rate / 1e12, "peak": FP32_VEC_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fwd_rate / FP32_VEC_PEAK,
                      "traffic": measured_traffic("forward"),
                      "algorithmic_bytes_per_launch": B * fwd_b,
-                     "flops_per_launch": flops_per_launch},
-        "solver": {"converged_frac": float(np.mean(st & 1)), "mean_iters": float(it.mean()),
-                   "mean_active_rows": float(act.mean())},
-        "memory": {"state_bytes": sb, "tape_bytes_K10": batch.tape_bytes(K_CAP),
+                     "flops_per_launch": kh["forward_flops_per_launch"],
+                     "hbm_frac": B * fwd_b / (kh["forward_ms"] / 1e3) / HBM_PEAK},
+        "solver": head["solver"],
+        "memory": {"state_bytes": batch.state_bytes(), "tape_bytes_K10": batch.tape_bytes(K_CAP),
                    "tape_bytes_K1": batch.tape_bytes(1)},
     }
 
+    if not args.no_extra:
+        # the paper's derivative is defined at the tolerance-converged root:
+        # the same workload at a cap where every instance converges
+        conv = ift_line(bufs, batch, args.steps, K_CONV, TOL, scheds)
+        kc = conv["kernels"]
+        rate_c = kc["forward_flops_per_launch"] / (kc["forward_ms"] / 1e3)
+        conv["roofline"] = {"kernel": "k_forward_small<float,9,4>", "bound": "alu",
+                            "achieved": rate_c / 1e12, "peak": FP32_VEC_PEAK / 1e12,
+                            "unit": "TFLOP/s", "frac": rate_c / FP32_VEC_PEAK}
+        conv["workload"] = f"as the headline, Newton cap K={K_CONV}"
+        out["converged_line"] = conv
+        progress(f"converging cap K={K_CONV}: {conv['value']:.4g} solves/s, converged "
+                 f"{conv['solver']['converged_frac']:.4f}")
+        out["fp64_line"] = fp64_line(args.steps, dev)
+        progress("FP64 line done")
+        # back to the headline state for what follows
+        for i in range(R):
+            t, sol, grads = bufs[i]
+            solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CAP,
+                           tol=TOL, out=sol)
+        torch.cuda.synchronize()
+
     if not args.no_unrolled:
-        t, sol, grads = bufs[0]
-        n_u = max(10, args.steps // 10)
-        tape = torch.empty(batch.tape_bytes(K_CAP), dtype=torch.uint8, device=dev)
-        for i in range(3):
-            tt = bufs[i % R][0]
-            solver.unrolled_vjp(batch, tt["M"], tt["J"], tt["a0"], tt["aref"], tt["D"], tt["abar"],
-                                K=K_CAP, tol=TOL, tape=tape)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for i in range(n_u):
-            tt = bufs[i % R][0]
-            solver.unrolled_vjp(batch, tt["M"], tt["J"], tt["a0"], tt["aref"], tt["D"], tt["abar"],
-                                K=K_CAP, tol=TOL, tape=tape)
-        e1.record()
-        torch.cuda.synchronize()
-        u_ms = e0.elapsed_time(e1) / n_u
-        u_val = B / (u_ms / 1e3)
-        out["unrolled"] = {"value": u_val, "unit": "solves/s", "K": K_CAP, "ms_per_step": u_ms,
-                           "ift_over_unrolled": value / u_val}
+        u = unrolled_graph(bufs, batch, args.steps)
+        u["ift_over_unrolled"] = value / u["value"]
+        u["ift_over_unrolled_sequential"] = (B / (seq_ms / 1e3)) / u["value"] if seq_ms else None
+        out["unrolled"] = u
+        progress("unrolled kernels done")
         if not args.no_ad:
-            progress("unrolled kernels done")
             out["unrolled_ad"] = unrolled_ad(bufs, R, value)
             progress("plain unrolled AD done")
 
@@ -508,6 +628,74 @@ def main():
         progress("oracle CPU baseline started")
         out["cpu_baseline"] = cpu_baseline(host[0])
     print(json.dumps(out), flush=True)
+
+
+def fp64_line(steps, dev):
+    """The FP64 path at the headline's shape (the paper computes in FP64):
+    cap K=40, tol 1e-10, forward + IFT VJP."""
+    import torch
+    from paper_2607_24959_amd import _native as N
+    from paper_2607_24959_amd import solver, synth
+    batch = solver.Batch.uniform(B, NV, M_ROWS, torch.float64, device=dev)
+    R, per_batch = rotation(8, batch.state_bytes())
+    host = [synth.uniform_batch(B, NV, NC, 20260725 + i) for i in range(R)]
+    bufs = make_bufs(host, batch, dev, K_CONV, 1e-10, torch.float64)
+    line = ift_line(bufs, batch, steps, K_CONV, 1e-10, ("sequential",), s=8)
+    fam = {N.PATH_SMALL: "SMALL", N.PATH_WAVE: "WAVE", N.PATH_CHUNK: "CHUNK",
+           N.PATH_TEAM: "TEAM"}
+    line["workload"] = (f"uniform batch B={B}, nv={NV}, {NC} contacts, FP64, cap K={K_CONV}, "
+                        "tol 1e-10, forward + IFT VJP")
+    line["rotating_batches"] = R
+    line["working_set_MB"] = round(R * per_batch / 2 ** 20, 1)
+    line["family"] = "CHUNK (one 64-lane workgroup per instance)"
+    del bufs
+    torch.cuda.empty_cache()
+    return line
+
+
+def unrolled_graph(bufs, batch, steps, K=K_CAP):
+    """The library's unrolled-trace VJP at cap K over the same rotating batches,
+    timed like the IFT path: graphs of `steps` steps (one stream, and two
+    independent chains on two streams, each chain with its own tape), median of
+    replays, the faster schedule reported."""
+    import torch
+    from paper_2607_24959_amd import solver
+    R = len(bufs)
+    tapes = [torch.empty(batch.tape_bytes(K), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    outs = []
+    for i in range(R):
+        t = bufs[i][0]
+        outs.append(solver.unrolled_vjp(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                                        K=K, tol=TOL, tape=tapes[i % 2]))
+    torch.cuda.synchronize()
+    per = {}
+    for sch in ("sequential", "two_chains"):
+        g = torch.cuda.CUDAGraph()
+        streams = [torch.cuda.Stream() for _ in range(1 if sch == "sequential" else 2)]
+        cap = streams[0]
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap), torch.cuda.graph(g, stream=cap):
+            for st in streams[1:]:
+                st.wait_stream(cap)
+            for i in range(steps):
+                t = bufs[i % R][0]
+                with torch.cuda.stream(streams[i % len(streams)]):
+                    solver.unrolled_vjp(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"],
+                                        K=K, tol=TOL, tape=tapes[i % len(streams)], out=outs[i % R])
+            for st in streams[1:]:
+                cap.wait_stream(st)
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+        ms, spread = replay_median(g)
+        del g
+        per[sch] = (ms, spread)
+    best = min(per, key=lambda k: per[k][0])
+    ms, spread = per[best]
+    return {"value": B * steps / (ms / 1e3), "unit": "solves/s", "K": K,
+            "ms_per_step": ms / steps, "replay_spread": spread, "schedule": best,
+            "schedules_ms_per_step": {k: v[0] / steps for k, v in per.items()},
+            "what": "fused unrolled-trace kernels (record + reverse sweep, one launch per "
+                    "step), HIP graphs timed like the IFT path, median of replays"}
 
 
 if __name__ == "__main__":

@@ -187,6 +187,14 @@ __device__ inline void group_copy_in(const T *__restrict__ src, int cnt, T *dst,
     for (int e = g; e < cnt; e += SG) dst[e] = src[e];
 }
 
+// x in FP64, converted where it is used: the empty asm stops the compiler
+// from hoisting the conversions of loop-invariant values out of a loop
+// (which would hold an FP64 copy of every one of them in registers).
+template <typename T> __device__ inline double as_f64_here(T x) {
+    asm volatile("" : "+v"(x));
+    return double(x);
+}
+
 // LDS per group for staged inputs/outputs of one instance: M (NP x NP
 // values used n x n), the factor (NE), and two NP-vectors.
 template <int NP> struct GroupShm {
@@ -591,7 +599,7 @@ __device__ inline void small_refine(const SmallInst<T, NP, R> &S, T (&a)[NP],
 }
 
 template <typename T, int NP, int R>
-__global__ __launch_bounds__(256) void k_forward_small(
+__global__ __launch_bounds__(256, 2) void k_forward_small(
     BatchView bv, int nb_inst, int max_iter, T tol, const T *__restrict__ gM,
     const T *__restrict__ gJ, const T *__restrict__ ga0, const T *__restrict__ garef,
     const T *__restrict__ gD, const T *__restrict__ gainit, T *__restrict__ gaout,
@@ -745,19 +753,19 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
         for (int jj = 0; jj < R; ++jj) {
             C s = C(0);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) s += C(S.J[jj][j]) * lam[j];
-            t[jj] = act[jj] ? C(S.D[jj]) * s : C(0);
+            for (int j = 0; j < NP; ++j) s += as_f64_here(S.J[jj][j]) * lam[j];
+            t[jj] = act[jj] ? as_f64_here(S.D[jj]) * s : C(0);
         }
         T rt[NP], dl[NP];
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             C s = C(0), mv = C(0);
 #pragma unroll
-            for (int jj = 0; jj < R; ++jj) s += C(S.J[jj][j]) * t[jj];
+            for (int jj = 0; jj < R; ++jj) s += as_f64_here(S.J[jj][j]) * t[jj];
 #pragma unroll
             for (int l = 0; l < NP; ++l)
-                mv += C(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * lam[l];
-            rt[j] = T(C(ab[j]) - mv - gsum16(s));
+                mv += as_f64_here(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * lam[l];
+            rt[j] = T(as_f64_here(ab[j]) - mv - gsum16(s));
         }
         reg_chol_solve<T, NP>(L, inv, rt, dl);
 #pragma unroll

@@ -223,9 +223,10 @@ def unrolled_replay(batch: Batch, rec, M, J, a0, aref, D, abar,
     return tuple(x if need else None for x, need in zip(g, needs))
 
 
-def unrolled_vjp(batch: Batch, M, J, a0, aref, D, abar, *, K=10, tol=1e-5, tape=None):
+def unrolled_vjp(batch: Batch, M, J, a0, aref, D, abar, *, K=10, tol=1e-5, tape=None, out=None):
     """Unrolled-trace gradient of abar . a_K.  Returns dict(a, a0, aref, J, D, M, status, iters,
-    tape_bytes)."""
+    tape_bytes); ``out``, a dict this function returned before for the same batch, is
+    written in place."""
     s = batch.sizes()
     for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D), ("abar", abar)):
         batch.check(name, t, s[name])
@@ -234,10 +235,11 @@ def unrolled_vjp(batch: Batch, M, J, a0, aref, D, abar, *, K=10, tol=1e-5, tape=
         tape = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=a0.device)
     if tape.numel() < nbytes:
         raise ValueError("tape buffer too small")
-    out = dict(a=torch.empty_like(a0), a0=torch.empty_like(a0), aref=torch.empty_like(aref),
-               J=torch.empty_like(J), D=torch.empty_like(D), M=torch.empty_like(M),
-               status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
-               iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device))
+    if out is None:
+        out = dict(a=torch.empty_like(a0), a0=torch.empty_like(a0), aref=torch.empty_like(aref),
+                   J=torch.empty_like(J), D=torch.empty_like(D), M=torch.empty_like(M),
+                   status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
+                   iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device))
     p = N.CsSolverParams(int(K), 0, float(tol))
     rc = N.unrolled_vjp(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), _vp(abar),
                         _vp(out["a"]), _vp(out["a0"]), _vp(out["aref"]), _vp(out["J"]),
