@@ -56,6 +56,11 @@ extern "C" {
 #define CS_ST_NONFINITE 4   /* an input was NaN/Inf; outputs are NaN */
 #define CS_ST_NOTSPD 8      /* M (or a Newton matrix) is not positive definite; outputs NaN */
 #define CS_ST_LSFAIL 16     /* the line search hit its safeguard cap (step still taken) */
+#define CS_ST_BADDESC 32    /* packed descriptor malformed: 1 <= n <= nv_max, 0 <= m <= nrows_max,
+                             * offsets >= 0 and offset + extent <= total_* must hold; the
+                             * instance is skipped (no output written; cs_ift_vjp leaves its
+                             * outputs untouched).  An order[] entry outside [0, B) is skipped
+                             * with no status written. */
 
 /* Kernel families (cs_batch.path), chosen from the batch's (or subset's)
  * largest n and m.  SMALL: 16 lanes per instance with the instance held in

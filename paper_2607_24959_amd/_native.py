@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "libcs.so")
 
 CS_OK, CS_EINVAL, CS_ENOSPC, CS_EHIP, CS_EUNSUPPORTED = 0, -1, -2, -3, -4
 CS_F32, CS_F64 = 0, 1
-ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL = 1, 2, 4, 8, 16
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL, ST_BADDESC = 1, 2, 4, 8, 16, 32
 NV_MAX, NROWS_MAX = 128, 4096
 STATIC_TAPE_BYTES = 64 << 20
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4

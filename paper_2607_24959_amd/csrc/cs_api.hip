@@ -104,6 +104,13 @@ int describe(const cs_batch *b, HostBatch &hb) {
     hb.bv.off_n = b->off_n;
     hb.bv.off_m = b->off_m;
     hb.bv.order = b->order;
+    hb.bv.Bfull = b->B;
+    hb.bv.nmax = hb.nmax;
+    hb.bv.mmax = hb.mmax;
+    hb.bv.tot_nn = hb.tot_nn;
+    hb.bv.tot_mn = hb.tot_mn;
+    hb.bv.tot_n = hb.tot_n;
+    hb.bv.tot_m = hb.tot_m;
     return CS_OK;
 }
 

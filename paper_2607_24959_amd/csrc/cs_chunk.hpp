@@ -628,6 +628,10 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
     for (int e = tid; e < CR; e += NT) L.Lr[e] = e;   // gathered chunks: slot e is row e
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) {   // team-uniform
+            mark_bad(I, gstatus, giters, tid == 0);
+            continue;
+        }
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn;
         ChColSum<NT, T> cs;
@@ -877,6 +881,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_chunk(
     const int cap = ch_list_cap(mmax, NT);
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) continue;   // team-uniform: outputs untouched
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn;
         const T *fac = gfac + fac_offset(I);

@@ -21,28 +21,57 @@ enum : int {
     ST_NONFINITE = 4,
     ST_NOTSPD = 8,
     ST_LSFAIL = 16,
+    ST_BADDESC = 32,
 };
 
 // cs_unrolled_vjp phases (cs_solver_params.flags)
 enum : int { ST_BOTH = 0, ST_REC = 1, ST_REP = 2 };
 
-// Device view of the batch descriptor.
+// Device view of the batch descriptor.  B is the number of instances a
+// launch walks (order[0 .. B-1]); Bfull, nmax, mmax and the totals are what
+// the launch was sized for (the host describes them).
 struct BatchView {
     int B, nv_u, nr_u;
     const int32_t *nv, *nr;
     const int64_t *off_nn, *off_mn, *off_n, *off_m;
     const int32_t *order;
+    int Bfull, nmax, mmax;
+    int64_t tot_nn, tot_mn, tot_n, tot_m;
 };
 
-// One instance's shape and element offsets.
+// One instance's shape and element offsets.  ok: the descriptor is well
+// formed (below); bvalid: the instance index itself is in range, so its
+// status word may be written.
 struct Inst {
     int b, n, m;
     int64_t onn, omn, on, om;
+    bool ok, bvalid;
 };
+
+// A packed instance's descriptor is well formed when its shape fits what the
+// launch was sized for and every array it addresses lies inside the batch's
+// totals: 1 <= n <= nmax, 0 <= m <= mmax, offsets >= 0 and offset + extent
+// <= total for M (n^2), J (m n), the n-vectors and the m-vectors (the saved
+// factor, the active set and the tape follow from these).
+__host__ __device__ inline bool desc_ok(int n, int m, int64_t onn, int64_t omn, int64_t on,
+                                        int64_t om, int nmax, int mmax, int64_t tot_nn,
+                                        int64_t tot_mn, int64_t tot_n, int64_t tot_m) {
+    return n >= 1 && n <= nmax && m >= 0 && m <= mmax && onn >= 0 && omn >= 0 && on >= 0 &&
+           om >= 0 && onn <= tot_nn - (int64_t)n * n && omn <= tot_mn - (int64_t)m * n &&
+           on <= tot_n - n && om <= tot_m - m;
+}
 
 __device__ inline Inst inst_at(const BatchView &bv, int w) {
     Inst I;
     I.b = bv.order ? bv.order[w] : w;
+    I.bvalid = I.b >= 0 && I.b < bv.Bfull;
+    I.n = 1;
+    I.m = 0;
+    I.onn = I.omn = I.on = I.om = 0;
+    if (!I.bvalid) {
+        I.ok = false;
+        return I;
+    }
     if (bv.nv) {
         I.n = bv.nv[I.b];
         I.m = bv.nr[I.b];
@@ -50,6 +79,8 @@ __device__ inline Inst inst_at(const BatchView &bv, int w) {
         I.omn = bv.off_mn[I.b];
         I.on = bv.off_n[I.b];
         I.om = bv.off_m[I.b];
+        I.ok = desc_ok(I.n, I.m, I.onn, I.omn, I.on, I.om, bv.nmax, bv.mmax, bv.tot_nn, bv.tot_mn,
+                       bv.tot_n, bv.tot_m);
     } else {
         const int64_t b = I.b;
         I.n = bv.nv_u;
@@ -58,8 +89,18 @@ __device__ inline Inst inst_at(const BatchView &bv, int w) {
         I.omn = b * I.m * I.n;
         I.on = b * I.n;
         I.om = b * I.m;
+        I.ok = true;
     }
     return I;
+}
+
+// A malformed descriptor is reported in the instance's status word (when the
+// instance index is in range) and the instance is skipped.
+__device__ inline void mark_bad(const Inst &I, int32_t *status, int32_t *iters, bool leader) {
+    if (leader && I.bvalid) {
+        if (status) status[I.b] = ST_BADDESC;
+        if (iters) iters[I.b] = 0;
+    }
 }
 
 // Layouts shared by every kernel family.
@@ -309,12 +350,12 @@ __device__ inline void chol_panel(double *H, int n, int ld, int c0, int c1, cons
     }
 }
 
-// The out-of-line team routines below work on the launching kernel's
-// dynamic LDS (every caller carves its LDS from that one region).  They take
-// element offsets into it rather than pointers: a pointer crossing a call
-// boundary loses its address space and every access would become a flat
-// access waiting on both memory counters; an offset rebuilt against the LDS
-// symbol keeps them ds_* instructions.
+// The team routines below work on the launching kernel's dynamic LDS (every
+// caller carves its LDS from that one region) and are inlined into every
+// caller: no call boundary, so no callee addresses the kernel's dynamic LDS
+// through a pointer or a base handed across a call.  They take element
+// offsets into that region and rebuild their pointers against the LDS
+// symbol, which keeps every access a ds_* instruction.
 template <typename T> __device__ inline T *lds_at(int off) {
     extern __shared__ __align__(16) unsigned char smem[];
     return reinterpret_cast<T *>(smem) + off;
@@ -351,7 +392,7 @@ __device__ inline int opaque_lane(int l) {
 // has synchronised the team after writing H.  Returns false (team-uniform)
 // when a pivot is not positive.
 template <int NT, typename T>
-__device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int n, int ld, int wko) {
+__device__ __attribute__((always_inline)) inline bool team_cholesky_lds(int ho, int dgo, int n, int ld, int wko) {
     // sizes are team-uniform: keep them (and every branch on them) scalar
     n = __builtin_amdgcn_readfirstlane(n);
     ld = __builtin_amdgcn_readfirstlane(ld);
@@ -448,7 +489,7 @@ __device__ __attribute__((noinline)) bool team_cholesky_lds(int ho, int dgo, int
 // updates one remaining entry with the block's 16 values; two barriers per
 // block and direction.  The caller has synchronised the team after writing b.
 template <int NT, typename T>
-__device__ __attribute__((noinline)) void team_chol_solve_lds(int lo, int dgo, int bo, int xo, int n,
+__device__ __attribute__((always_inline)) inline void team_chol_solve_lds(int lo, int dgo, int bo, int xo, int n,
                                                              int ld) {
     n = __builtin_amdgcn_readfirstlane(n);
     ld = __builtin_amdgcn_readfirstlane(ld);

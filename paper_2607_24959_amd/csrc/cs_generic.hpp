@@ -120,6 +120,10 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
     const int tid = threadIdx.x;
     for (int w = blockIdx.x; w < bv.B; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) {   // team-uniform
+            mark_bad(I, gstatus, giters, tid == 0);
+            continue;
+        }
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn, *a0 = ga0 + I.on, *aref = garef + I.om,
                 *D = gD + I.om;
@@ -250,6 +254,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
     const int tid = threadIdx.x;
     for (int w = blockIdx.x; w < bv.B; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) continue;   // team-uniform: outputs untouched
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn, *aref = garef + I.om, *D = gD + I.om;
         const T *fac = gfac + fac_offset(I);
@@ -343,6 +348,10 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
     const int tid = threadIdx.x;
     for (int w = blockIdx.x; w < bv.B; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) {   // team-uniform
+            if (mode != ST_REP) mark_bad(I, gstatus, giters, tid == 0);
+            continue;
+        }
         const int n = I.n, m = I.m;
         const T *M = gM + I.onn, *J = gJ + I.omn, *a0 = ga0 + I.on, *aref = garef + I.om,
                 *D = gD + I.om;

@@ -610,6 +610,10 @@ __global__ __launch_bounds__(256, 2) void k_forward_small(
     const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
     if (w >= nb_inst) return;   // whole groups only: no cross-group traffic follows
     const Inst I = inst_at(bv, w);
+    if (!I.ok) {   // group-uniform
+        mark_bad(I, gstatus, giters, g == 0);
+        return;
+    }
     SmallInst<T, NP, R> S;
     S.load(I, g, gM, gJ, ga0, garef, gD);
     T a[NP];
@@ -686,6 +690,7 @@ __global__ __launch_bounds__(256) void k_ift_vjp_small(
     const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
     if (w >= nb_inst) return;
     const Inst I = inst_at(bv, w);
+    if (!I.ok) return;   // group-uniform: outputs untouched
     const int n = I.n, m = I.m;
     __shared__ T sh[(256 / SG) * GroupShm<NP>::SIZE];
     T *gsh = sh + (threadIdx.x / SG) * GroupShm<NP>::SIZE;
@@ -861,6 +866,10 @@ __global__ __launch_bounds__(256) void k_unrolled_small(
     const int w = blockIdx.x * (blockDim.x / SG) + threadIdx.x / SG;
     if (w >= nb_inst) return;
     const Inst I = inst_at(bv, w);
+    if (!I.ok) {   // group-uniform
+        if (mode != ST_REP) mark_bad(I, gstatus, giters, g == 0);
+        return;
+    }
     const int n = I.n, m = I.m;
     SmallInst<T, NP, R> S;
     S.load(I, g, gM, gJ, ga0, garef, gD);

@@ -105,6 +105,7 @@ __global__ __launch_bounds__(NT) void k_team_mixed(
 
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) continue;   // team-uniform: a malformed descriptor is skipped
         const int n = I.n, m = I.m;
         const float *M = gM + I.onn, *J = gJ + I.omn, *aref = garef + I.om, *D = gD + I.om;
         const uint8_t *mk = gmask + I.om;

@@ -143,6 +143,10 @@ __global__ __launch_bounds__(64) void k_forward_wave(
 
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
+        if (!I.ok) {   // wave-uniform
+            mark_bad(I, gstatus, giters, l == 0);
+            continue;
+        }
         const int n = I.n, m = I.m;
         const int m4 = (m + 3) & ~3;
         const float *M = gM + I.onn, *J = gJ + I.omn;
