@@ -259,17 +259,13 @@ def uneven(reps=20):
     plan = batching.Plan(batch)
     t = {k: torch.from_numpy(np.ascontiguousarray(getattr(pb, k))).to("cuda") for k in
          ("M", "J", "a0", "aref", "D", "abar")}
-    sol, grads = plan.capture(t, max_iter=K_CAP, tol=TOL)
-    for _ in range(2):
-        plan.graph.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        plan.graph.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    per = {}
+    for lanes in (1, 2):
+        sol, grads = plan.capture(t, max_iter=K_CAP, tol=TOL, lanes=lanes)
+        per[lanes], _ = replay_median(plan.graph, reps=reps)
+        plan.graph = None
+    lanes = min(per, key=per.get)
+    ms = per[lanes]
     n = pb.nv.astype(np.float64)
     m = pb.nrows.astype(np.float64)
     byt = float(np.sum([sum(algorithmic_bytes(a, b)) for a, b in zip(n, m)]))
@@ -278,6 +274,7 @@ def uneven(reps=20):
             "ms_per_batch": ms, "solves_per_s": 8192 / (ms / 1e3),
             "gbps_algorithmic": byt / (ms / 1e3) / 1e9, "bytes_per_batch": byt,
             "converged_frac": float(np.mean(st & 1)), "classes": plan.summary(),
+            "lanes": lanes, "ms_per_batch_by_lanes": per,
             "table": os.path.basename(batching.TABLE_PATH) if os.path.exists(batching.TABLE_PATH) else None,
             "generation_s": round(gen_s, 1)}
 

@@ -6,7 +6,8 @@ compile-time sizes per class), orders each class longest-processing-time
 first by a cost model, and issues one cs_forward / cs_ift_vjp per class on
 the same stream with ``order``/``count`` selecting the class's instances, so
 the whole batch shares one set of buffers and one state.  The sequence can
-be captured in a HIP graph and replayed.
+be captured in a HIP graph and replayed, on one stream or with the classes
+dealt to two streams that run concurrently inside the graph.
 
 Class rules come from a table keyed by (dtype, padded n, row bucket); the
 autotuner (autotune.py) fills it by timing the candidate families, and the
@@ -164,23 +165,64 @@ class Plan:
             N.check(rc, f"cs_ift_vjp(class path={c.path})")
         return out
 
+    # ------------------------------------------------------------------ lanes
+    def lane_split(self, lanes: int) -> List[List[int]]:
+        """Classes dealt to `lanes` streams longest first, each to the lane with
+        the least estimated work (cost model summed over the class)."""
+        nv, nr = self.batch.nv_host, self.batch.nrows_host
+        cost = [float(cost_model(nv[c.idx], nr[c.idx]).sum()) for c in self.classes]
+        out: List[List[int]] = [[] for _ in range(lanes)]
+        load = [0.0] * lanes
+        for ci in sorted(range(len(self.classes)), key=lambda i: -cost[i]):
+            k = int(np.argmin(load))
+            out[k].append(ci)
+            load[k] += cost[ci]
+        return out
+
+    def _issue(self, t, sol, grads, max_iter, tol, classes, stream):
+        """Forward then VJP of each listed class on `stream` (classes touch
+        disjoint instances, so lanes need no ordering between them)."""
+        vp = solver._vp
+        p = N.CsSolverParams(int(max_iter), 0, float(tol))
+        st = C.c_void_p(stream.cuda_stream)
+        for ci in classes:
+            c = self.classes[ci]
+            rc = N.forward(c.desc, p, vp(t["M"]), vp(t["J"]), vp(t["a0"]), vp(t["aref"]), vp(t["D"]),
+                           None, vp(sol.a), vp(sol.state), sol.state.numel(), vp(sol.status),
+                           vp(sol.iters), st)
+            N.check(rc, f"cs_forward(class path={c.path})")
+            if grads is not None:
+                rc = N.ift_vjp(c.desc, vp(sol.state), sol.state.numel(), vp(t["M"]), vp(t["J"]),
+                               vp(t["a0"]), vp(t["aref"]), vp(t["D"]), vp(sol.a), vp(t["abar"]),
+                               *(vp(x) for x in grads), st)
+                N.check(rc, f"cs_ift_vjp(class path={c.path})")
+
     # ------------------------------------------------------------------ graphs
-    def capture(self, tensors, *, max_iter, tol, with_vjp=True):
-        """Capture forward (+ IFT VJP) of every class into one HIP graph."""
+    def capture(self, tensors, *, max_iter, tol, with_vjp=True, lanes=1):
+        """Capture forward (+ IFT VJP) of every class into one HIP graph.  With
+        lanes = 2 the classes are dealt to two streams (lane_split) that run
+        concurrently inside the graph, so small classes fill the compute units
+        the longest class leaves idle; the streams stay alive with the graph."""
         t = tensors
         sol = self.forward(t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=max_iter, tol=tol)
         grads = self.ift_vjp(sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"]) if with_vjp else None
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            with torch.cuda.graph(g, stream=s):
-                self.forward(t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=max_iter, tol=tol,
-                             out=sol)
-                if with_vjp:
-                    self.ift_vjp(sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
-        torch.cuda.current_stream().wait_stream(s)
+        streams = [torch.cuda.Stream() for _ in range(lanes)]    # default priority
+        split = self.lane_split(lanes)
+        cap = streams[0]
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(g, stream=cap):
+                for st in streams[1:]:
+                    st.wait_stream(cap)
+                for k, st in enumerate(streams):
+                    self._issue(t, sol, grads, max_iter, tol, split[k], st)
+                for st in streams[1:]:
+                    cap.wait_stream(st)
+        torch.cuda.current_stream().wait_stream(cap)
         torch.cuda.synchronize()
         self.graph = g
+        self.graph_streams = streams
+        self.lanes = lanes
         return sol, grads

@@ -101,7 +101,11 @@ def test_alone_equals_in_mix_bitwise():
         assert np.array_equal(g1[2].cpu().numpy(), j_mix[pb.off_mn[i]:pb.off_mn[i + 1]]), i
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_graph_replay_matches_eager(lanes):
+    """The captured graph (classes on one stream, or dealt to two concurrent
+    streams) replays to the eager results bitwise, several times, with eager
+    work in between."""
     _needs_gpu()
     pb = synth.uneven_batch(512, (3, 9, 18, 36, 96), 128, seed=321)
     p32 = pb.astype(np.float32)
@@ -112,7 +116,7 @@ def test_graph_replay_matches_eager():
     gref = plan.ift_vjp(ref, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"])
     torch.cuda.synchronize()
     a_ref, j_ref = ref.a.clone(), gref[2].clone()
-    sol, grads = plan.capture(t, max_iter=10, tol=1e-5)
+    sol, grads = plan.capture(t, max_iter=10, tol=1e-5, lanes=lanes)
     for rep in range(3):
         sol.a.zero_()
         grads[2].zero_()
