@@ -8,7 +8,8 @@ generator.
 ``oracle.c`` (compiled to ``liboracle.so`` by :func:`build`) holds the
 method: Newton steps with QR solves and an exact sort-and-scan line search
 (Sec. III-B, eqs. 6, 9, 10), the IFT adjoint VJP (Sec. III-C, eq. 17) and
-the unrolled-trace VJP.  ``brute.py`` pins the forward result by active-set
+the unrolled-trace VJP, and the IFT Jacobian-vector products (eq. 15, forward
+mode).  ``brute.py`` pins the forward result by active-set
 enumeration; ``fd.py`` pins the gradients by central finite differences.
 """
 from __future__ import annotations
@@ -71,6 +72,7 @@ def lib():
         L.oracle_unrolled_vjp.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp,
                                           _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                           C.POINTER(i), C.POINTER(i)]
+        L.oracle_ift_jvp.argtypes = [i, i, _dp, _dp, _dp, _u8, i, _Opt(_dp), _Opt(_dp), _dp]
         L.oracle_line_search.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _u8]
         L.oracle_line_search.restype = C.c_double
         L.oracle_max_threads.restype = C.c_int
@@ -80,6 +82,7 @@ def lib():
         L.oracle_ift_vjp_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, _dp, _Opt(_u8), _dp,
                                                 _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                                 _Opt(_dp), i]
+        L.oracle_ift_jvp_batch.argtypes = pk + [_dp, _dp, _dp, _u8, i, _Opt(_dp), _Opt(_dp), _dp, i]
         L.oracle_unrolled_vjp_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp,
                                                      _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                                      _Opt(_dp), _i32, _i32, i]
@@ -130,6 +133,22 @@ def ift_vjp(M, J, a0, aref, D, a, abar, active=None):
     lib().oracle_ift_vjp(n, m, M, J, a0, aref, D, a, act, abar, out["a0"], out["aref"],
                          out["J"], out["D"], out["M"], out["lam"])
     return out
+
+
+def ift_jvp(M, J, D, active, da0=None, daref=None, k=None):
+    """IFT Jacobian-vector products (eq. 15) for k directions of (a0, aref):
+    da0 [k, n] and daref [k, m] (either None for zero).  Returns da [k, n]."""
+    M, J, D = map(_f64, (M, J, D))
+    n, m = M.shape[0], D.shape[0]
+    J = J.reshape(m, n)
+    if k is None:
+        k = (da0 if da0 is not None else daref).shape[0]
+    act = np.ascontiguousarray(active, dtype=np.uint8)
+    d0 = None if da0 is None else _f64(da0).reshape(k, n)
+    dr = None if daref is None else _f64(daref).reshape(k, m)
+    da = np.empty((max(k, 1), max(n, 1)))
+    lib().oracle_ift_jvp(n, m, M, J, D, act if m else np.zeros(1, np.uint8), k, d0, dr, da)
+    return da[:k, :n]
 
 
 def unrolled_vjp(M, J, a0, aref, D, abar, K, tol=1e-10):
@@ -205,6 +224,20 @@ class Packed:
                                    None if active is None else np.ascontiguousarray(active, np.uint8),
                                    abar, g["a0"], g["aref"], g["J"], g["D"], g["M"], threads)
         return g
+
+    def ift_jvp(self, active, k, da0=None, daref=None, threads=0):
+        """Directional derivatives of a* for k directions per instance:
+        da0 [k * total_n] (instance i at k * off_n[i], direction-major) and
+        daref [k * total_m] (at k * off_m[i]), either None.  Returns da
+        [k * total_n]."""
+        da = np.zeros(max(k * int(self.off_n[-1]), 1))
+        act = np.ascontiguousarray(active, dtype=np.uint8)
+        if act.size == 0:
+            act = np.zeros(1, np.uint8)
+        lib().oracle_ift_jvp_batch(*self._pk(), self.M, self.J, self.D, act, k,
+                                   None if da0 is None else _f64(da0).ravel(),
+                                   None if daref is None else _f64(daref).ravel(), da, threads)
+        return da
 
     def unrolled_vjp(self, K, tol=1e-10, abar=None, threads=0):
         abar = self.abar if abar is None else _f64(abar).ravel()

@@ -365,6 +365,37 @@ int oracle_ift_vjp(int n, int m, const double *M, const double *J, const double 
     return rc;
 }
 
+/* IFT Jacobian-vector products (Sec. III-C, eq. 15, forward mode): for each of
+ * k tangent directions (da0_j, daref_j) of the inputs a0 and aref, the
+ * directional derivative of the solution,
+ *   da_j = -F_a^{-1} F_theta (da0_j, daref_j) = H^{-1} (M da0_j + J^T (D o A* o daref_j)),
+ * since F = M (a - a0) + J^T (D o A o (J a - aref)) gives F_a0 = -M and
+ * F_aref = -J^T diag(D o A).  H = M + J^T diag(D o A*) J is solved by QR for
+ * every direction.  da0 (k x n) and daref (k x m), direction-major, may be
+ * NULL (zero); da is k x n. */
+int oracle_ift_jvp(int n, int m, const double *M, const double *J, const double *D,
+                   const unsigned char *active, int k, const double *da0, const double *daref,
+                   double *da) {
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *H = (double *)malloc(sizeof(double) * (size_t)n1 * n1);
+    double *rhs = (double *)malloc(sizeof(double) * n1);
+    double *t = (double *)malloc(sizeof(double) * mm);
+    assemble_H(n, m, M, J, D, active, H);
+    int rc = 0;
+    for (int d = 0; d < k; ++d) {
+        for (int j = 0; j < n; ++j) rhs[j] = 0.0;
+        if (da0) matvec(n, n, M, da0 + (size_t)d * n, rhs);
+        if (daref) {
+            for (int i = 0; i < m; ++i) t[i] = active[i] ? D[i] * daref[(size_t)d * m + i] : 0.0;
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < n; ++j) rhs[j] += J[(size_t)i * n + j] * t[i];
+        }
+        rc |= qr_solve(n, H, rhs, da + (size_t)d * n);
+    }
+    free(H); free(rhs); free(t);
+    return rc;
+}
+
 /* Unrolled VJP: the gradient of abar . a_K through the executed K-step trace.
  * Steps after the stopping rule fires are the identity (not recorded).  The
  * line-search step alpha = -b/c is differentiated on its accepted piece A'_k
@@ -636,6 +667,20 @@ void oracle_ift_vjp_batch(int B, const int32_t *nv, const int32_t *nrows,
                        a0bar ? a0bar + off_n[b] : NULL, arefbar ? arefbar + off_m[b] : NULL,
                        Jbar ? Jbar + off_mn[b] : NULL, Dbar ? Dbar + off_m[b] : NULL,
                        Mbar ? Mbar + off_nn[b] : NULL, NULL);
+    }
+}
+
+void oracle_ift_jvp_batch(int B, const int32_t *nv, const int32_t *nrows,
+                          const int64_t *off_nn, const int64_t *off_mn, const int64_t *off_n,
+                          const int64_t *off_m, const double *M, const double *J,
+                          const double *D, const unsigned char *active, int k,
+                          const double *da0, const double *daref, double *da, int threads) {
+    set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b) {
+        oracle_ift_jvp(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], D + off_m[b],
+                       active + off_m[b], k, da0 ? da0 + (size_t)k * off_n[b] : NULL,
+                       daref ? daref + (size_t)k * off_m[b] : NULL, da + (size_t)k * off_n[b]);
     }
 }
 
