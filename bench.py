@@ -279,6 +279,50 @@ def uneven(reps=20):
             "generation_s": round(gen_s, 1)}
 
 
+def ilqr_jacobians(reps=20):
+    """iLQR's linearised contact dynamics for the rollout workload's shape
+    (B=1024, nv=18, 32 contacts, FP32): A_t and B_t of one step from one
+    cs_ift_jvp call with 2 nv = 36 directions per instance (eq. 15), timed
+    from a graph.  Roofline: FP64 vector peak (the kernel computes in FP64);
+    flops per direction counted as the two refined solves would need them."""
+    import torch
+    from paper_2607_24959_amd import solver, synth
+    Bn, n, nc = 1024, 18, 32
+    m = 4 * nc
+    b = synth.uniform_batch(Bn, n, nc, synth.SEED_BASE + 3).astype(np.float32)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(b, k))).cuda() for k in
+         ("M", "J", "a0", "aref", "D")}
+    batch = solver.Batch.uniform(Bn, n, m, torch.float32)
+    sol = solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K_CONV, tol=TOL)
+    k = 2 * n
+    rng = np.random.default_rng(0)
+    da0 = torch.from_numpy(rng.standard_normal(k * Bn * n).astype(np.float32)).cuda()
+    daref = torch.from_numpy(rng.standard_normal(k * Bn * m).astype(np.float32)).cuda()
+    out = solver.ift_jvp(batch, sol, t["M"], t["J"], t["D"], k, da0, daref)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap), torch.cuda.graph(g, stream=cap):
+        for _ in range(10):
+            solver.ift_jvp(batch, sol, t["M"], t["J"], t["D"], k, da0, daref, out=out)
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    ms, spread = replay_median(g, reps=reps)
+    ms /= 10
+    act = batch.active_sets(sol).reshape(Bn, m).sum(1).astype(np.float64)
+    # per direction: rhs (2 n^2 + 4 |A| n) and, three times, a solve (2 n^2)
+    # plus (for the two refinements) H x (2 n^2 + 4 |A| n)
+    per_dir = 3 * (2 * n * n + 4 * act * n) + 3 * 2 * n * n
+    flops = float(np.sum(per_dir) * k)
+    return {"workload": f"B={Bn}, nv={n}, {nc} contacts, FP32, {k} directions per instance "
+                        "(the A_t and B_t columns of one step)",
+            "ms_per_batch": ms, "jacobian_columns_per_s": Bn * k / (ms / 1e3),
+            "replay_spread": spread,
+            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 78.6,
+                         "unit": "TFLOP/s (FP64 vector)", "frac": flops / (ms / 1e3) / 78.6e12}}
+
+
 def serving(rates=(2000, 5000, 10000, 20000, 50000), n_requests=10000, warmup=1000,
             budget_bytes=256 * 2 ** 20):
     """Poisson streams of 6-step MPC windows (nv in {3,9,18}, contacts U{0..64},
@@ -619,6 +663,8 @@ def main():
         progress("K sweep done")
         out["uneven"] = uneven()
         progress("uneven batch done")
+        out["ilqr_jacobians"] = ilqr_jacobians()
+        progress("iLQR Jacobians done")
         out["serving"] = serving(rates, n_requests=args.serve_requests,
                                  warmup=max(1, args.serve_requests // 10))
     if not args.no_cpu:

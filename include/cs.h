@@ -166,6 +166,24 @@ int cs_ift_vjp(const cs_batch *batch, const void *state, size_t state_bytes,
                const void *a, const void *abar,
                void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar, void *stream);
 
+/* IFT Jacobian-vector products (Sec. III-C, eq. 15, forward mode): for k
+ * tangent directions (da0_j, daref_j) of a0 and aref per instance, the
+ * directional derivatives of the solution cs_forward returned,
+ *   da_j = -F_a^{-1} F_theta (da0_j, daref_j) = H^{-1} (M da0_j + J^T (D o A* o daref_j)),
+ * with the saved factor of H(A*) and A* from `state` (the same inputs as that
+ * cs_forward call).  These are the columns of the linearised contact dynamics
+ * an iLQR step needs: a direction of the actuation enters through a0, a
+ * direction of the velocity through aref.  Layout, direction-major: instance
+ * i's k directions of a0 at element k * off_n[i] of da0 (k x n), of aref at
+ * k * off_m[i] of daref (k x m), results at k * off_n[i] of da (k x n); uniform
+ * batches use off_n[i] = i n, off_m[i] = i m.  da0 or daref may be NULL (zero
+ * tangent); da is required when k > 0.  k >= 0.  n <= 96 per instance (else
+ * CS_EUNSUPPORTED).  Arithmetic in FP64 for both dtypes (two steps of
+ * iterative refinement with the saved factor). */
+int cs_ift_jvp(const cs_batch *batch, const void *state, size_t state_bytes,
+               const void *M, const void *J, const void *D, int32_t k,
+               const void *da0, const void *daref, void *da, void *stream);
+
 /* Unrolled-trace VJP (the baseline gradient): runs exactly K = params->max_iter
  * steps of the same solver from a0 (steps after the stopping rule fires are the
  * identity), records each step on `tape`, then differentiates abar . a_K

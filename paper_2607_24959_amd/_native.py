@@ -19,7 +19,7 @@ NV_MAX, NROWS_MAX = 128, 4096
 STATIC_TAPE_BYTES = 64 << 20
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
 
-EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_unrolled_vjp", "cs_unrolled_vjp_static", "cs_state_bytes",
+EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
             "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
 
@@ -89,6 +89,8 @@ def lib():
         L.cs_forward.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
         L.cs_ift_vjp.restype = C.c_int
         L.cs_ift_vjp.argtypes = [pb, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cs_ift_jvp.restype = C.c_int
+        L.cs_ift_jvp.argtypes = [pb, vp, sz, vp, vp, vp, i32, vp, vp, vp, vp]
         L.cs_unrolled_vjp.restype = C.c_int
         L.cs_unrolled_vjp.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                       sz, vp, vp, vp]
@@ -139,6 +141,11 @@ def ift_vjp(batch, state, state_nbytes, M, J, a0, aref, D, a, abar, a0bar, arefb
             Mbar, stream):
     return lib().cs_ift_vjp(C.byref(batch), state, state_nbytes, M, J, a0, aref, D, a, abar,
                             a0bar, arefbar, Jbar, Dbar, Mbar, stream)
+
+
+def ift_jvp(batch, state, state_nbytes, M, J, D, k, da0, daref, da, stream):
+    return lib().cs_ift_jvp(C.byref(batch), state, state_nbytes, M, J, D, int(k), da0, daref, da,
+                            stream)
 
 
 def unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar, Dbar, Mbar,

@@ -12,6 +12,7 @@
 #include "cs.h"
 #include "cs_chunk.hpp"
 #include "cs_generic.hpp"
+#include "cs_jvp.hpp"
 #include "cs_small.hpp"
 #include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
@@ -436,6 +437,34 @@ int cs_ift_vjp(const cs_batch *batch, const void *state, size_t state_bytes_give
                             Mbar, s);
     return vjp_t<double>(hb, state, M, J, a0, aref, D, a, abar, a0bar, arefbar, Jbar, Dbar, Mbar,
                          s);
+}
+
+int cs_ift_jvp(const cs_batch *batch, const void *state, size_t state_bytes_given, const void *M,
+               const void *J, const void *D, int32_t k, const void *da0, const void *daref,
+               void *da, void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if (k < 0) return CS_EINVAL;
+    if (hb.B == 0 || k == 0) return CS_OK;
+    if (!state || !M || !da) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !D)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    if (!cs::jvp_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    const uint8_t *mask = static_cast<const uint8_t *>(state) + align256(hb.s * factor_elems(hb));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int r;
+    if (hb.dtype == CS_F32)
+        r = cs::launch_ift_jvp<float>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, k,
+                                      static_cast<const float *>(state), mask,
+                                      (const float *)M, (const float *)J, (const float *)D,
+                                      (const float *)da0, (const float *)daref, (float *)da, s);
+    else
+        r = cs::launch_ift_jvp<double>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, k,
+                                       static_cast<const double *>(state), mask,
+                                       (const double *)M, (const double *)J, (const double *)D,
+                                       (const double *)da0, (const double *)daref, (double *)da, s);
+    return r == 0 ? CS_OK : CS_EHIP;
 }
 
 int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params, const void *M,

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import torch
 
-from . import synth
+from . import solver, synth
 from .autograd import contact_solve
 
 
@@ -46,3 +46,26 @@ def make_rollout_problem(B, n, nc, horizon, seed, dtype=torch.float64, device="c
     tau = rng.standard_normal((horizon, B, n))
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(device, dtype)
     return dict(M=t(b.M), J=t(b.J), D=t(b.D), pen=t(b.pen), v0=t(v0), v_goal=t(v_goal), tau=t(tau))
+
+
+def step_jacobians(M, J, D, sol, batch, h=0.002):
+    """iLQR's linearised contact dynamics of one semi-implicit step at the
+    solution `sol` of that step (forward-mode IFT, eq. 15): with
+    v_{t+1} = v_t + h a*(a0 = M^{-1} tau_t, aref = -b J v_t - k pen),
+      B_t = d v_{t+1} / d tau_t = h H^{-1}       (directions M^{-1} e_j of a0),
+      A_t = d v_{t+1} / d v_t = I + h H^{-1} J^T D_A (-b J)
+                                                 (directions -b J e_j of aref),
+    all 2n columns from one cs_ift_jvp call.  Shapes M [B,n,n], J [B,m,n],
+    D [B,m]; returns (A_t, B_t), each [B, n, n]."""
+    Bn, m, n = J.shape
+    Minv = torch.linalg.inv(M)
+    da0 = torch.zeros(Bn, 2 * n, n, dtype=M.dtype, device=M.device)
+    daref = torch.zeros(Bn, 2 * n, m, dtype=M.dtype, device=M.device)
+    da0[:, :n, :] = Minv.transpose(1, 2)                    # row j: column j of M^{-1}
+    daref[:, n:, :] = (-synth.B_DAMP * J).transpose(1, 2)   # row j: -b J e_j
+    da = solver.ift_jvp(batch, sol, M.contiguous(), J.contiguous(), D.contiguous(), 2 * n,
+                        da0.reshape(-1), daref.reshape(-1)).reshape(Bn, 2 * n, n)
+    eye = torch.eye(n, dtype=M.dtype, device=M.device).expand(Bn, n, n)
+    B_t = h * da[:, :n, :].transpose(1, 2)
+    A_t = eye + h * da[:, n:, :].transpose(1, 2)
+    return A_t, B_t

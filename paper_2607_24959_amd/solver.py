@@ -185,6 +185,24 @@ def ift_vjp(batch: Batch, sol: Solution, M, J, a0, aref, D, abar,
     return out
 
 
+def ift_jvp(batch: Batch, sol: Solution, M, J, D, k: int, da0=None, daref=None, out=None):
+    """Directional derivatives of the solution for k tangent directions per
+    instance (eq. 15): da0 [k * total_n] (instance i's k x n block at k off_n[i]),
+    daref [k * total_m] (k x m at k off_m[i]), either None.  Returns da
+    [k * total_n] in the same layout."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("D", D)):
+        batch.check(name, t, s[name])
+    batch.check("da0", da0, k * s["a0"], required=False)
+    batch.check("daref", daref, k * s["aref"], required=False)
+    if out is None:
+        out = torch.empty(max(k * s["a0"], 1), dtype=batch.dtype, device=M.device)
+    rc = N.ift_jvp(batch.desc, _vp(sol.state), sol.state.numel(), _vp(M), _vp(J), _vp(D), int(k),
+                   _vp(da0), _vp(daref), _vp(out), _stream(M.device))
+    N.check(rc, "cs_ift_jvp")
+    return out
+
+
 def unrolled_record(batch: Batch, M, J, a0, aref, D, *, K=10, tol=1e-5, tape=None):
     """Run the K-step solve and record its trace.  Returns dict(a, status, iters, tape)."""
     s = batch.sizes()
