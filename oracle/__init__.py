@@ -8,8 +8,9 @@ generator.
 ``oracle.c`` (compiled to ``liboracle.so`` by :func:`build`) holds the
 method: Newton steps with QR solves and an exact sort-and-scan line search
 (Sec. III-B, eqs. 6, 9, 10), the IFT adjoint VJP (Sec. III-C, eq. 17) and
-the unrolled-trace VJP, and the IFT Jacobian-vector products (eq. 15, forward
-mode).  ``brute.py`` pins the forward result by active-set
+the unrolled-trace VJP, the IFT Jacobian-vector products (eq. 15, forward
+mode), and a nonlinear conjugate-gradient forward solve for the same
+minimiser.  ``brute.py`` pins the forward result by active-set
 enumeration; ``fd.py`` pins the gradients by central finite differences.
 """
 from __future__ import annotations
@@ -83,6 +84,10 @@ def lib():
                                                 _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                                 _Opt(_dp), i]
         L.oracle_ift_jvp_batch.argtypes = pk + [_dp, _dp, _dp, _u8, i, _Opt(_dp), _Opt(_dp), _dp, i]
+        L.oracle_forward_cg.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8,
+                                        C.POINTER(i), C.POINTER(i)]
+        L.oracle_forward_cg_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8, _i32,
+                                                   _i32, i]
         L.oracle_unrolled_vjp_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp,
                                                      _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                                      _Opt(_dp), _i32, _i32, i]
@@ -120,6 +125,20 @@ def forward(M, J, a0, aref, D, a_init=None, max_iter=10, tol=1e-10, trace=False)
         k = it.value
         out.update(alphas=al[:k], A=tA[:k, :m].astype(bool), Ap=tAp[:k, :m].astype(bool))
     return out
+
+
+def forward_cg(M, J, a0, aref, D, max_iter=200, tol=1e-10):
+    """Solve one instance by preconditioned nonlinear CG with the exact line
+    search.  Returns dict(a, active, iters, status)."""
+    M, J, a0, aref, D = map(_f64, (M, J, a0, aref, D))
+    n, m = a0.shape[0], aref.shape[0]
+    J = J.reshape(m, n)
+    a = np.empty(n)
+    act = np.empty(max(m, 1), dtype=np.uint8)
+    it, st = C.c_int(0), C.c_int(0)
+    lib().oracle_forward_cg(n, m, M, J, a0, aref, D, max_iter, tol, a, act, C.byref(it),
+                            C.byref(st))
+    return dict(a=a, active=act[:m].astype(bool), iters=it.value, status=st.value)
 
 
 def ift_vjp(M, J, a0, aref, D, a, abar, active=None):
@@ -213,6 +232,15 @@ class Packed:
         st = np.zeros(self.B, dtype=np.int32)
         lib().oracle_forward_batch(*self._pk(), self.M, self.J, self.a0, self.aref, self.D,
                                    max_iter, tol, a, act, it, st, threads)
+        return dict(a=a, active=act, iters=it, status=st)
+
+    def forward_cg(self, max_iter=200, tol=1e-10, threads=0):
+        a = self._buf("n")
+        act = np.zeros(max(int(self.off_m[-1]), 1), dtype=np.uint8)
+        it = np.zeros(self.B, dtype=np.int32)
+        st = np.zeros(self.B, dtype=np.int32)
+        lib().oracle_forward_cg_batch(*self._pk(), self.M, self.J, self.a0, self.aref, self.D,
+                                      max_iter, tol, a, act, it, st, threads)
         return dict(a=a, active=act, iters=it, status=st)
 
     def ift_vjp(self, a, active, abar=None, threads=0, outputs=("a0", "aref", "J", "D", "M")):

@@ -31,6 +31,11 @@
  *   ||a_k - a_{k-1}||_inf <= tol * (1 + ||a_k||_inf)  and  A(a_k) = A(a_{k-1}).
  * At most max_iter steps are taken; the returned active set and residual are
  * those of the returned iterate.
+ *
+ * A second forward solver, preconditioned nonlinear conjugate gradients with
+ * the same exact line search (oracle_forward_cg), reaches the same minimiser
+ * by another path (Sec. III-B names Newton and nonlinear CG as the two
+ * solvers; eqs. 11-14: the derivative does not depend on which).
  */
 #include <math.h>
 #include <stdint.h>
@@ -320,6 +325,93 @@ int oracle_forward(int n, int m, const double *M, const double *J, const double 
     free(r); free(q); free(F); free(negF); free(p); free(H); free(Ap); free(Aprev);
     return 0;
 }
+
+/* Forward solve by preconditioned nonlinear conjugate gradients (a second
+ * solver for the same minimiser; Sec. III-B: any update a - P F with
+ * nonsingular P shares the root and its derivative, eqs. 11-14):
+ *   z_k = M^{-1} F_k (M preconditions),
+ *   p_k = -z_k + beta_k p_{k-1},  beta_k = max(0, F_k . (z_k - z_{k-1}) / (F_{k-1} . z_{k-1}))
+ *   (Polak-Ribiere, restarted (beta = 0) at k = 0, when the active set changed,
+ *   and whenever p_k is not a descent direction),
+ *   a_{k+1} = a_k + alpha_k p_k with the exact line search of the Newton solver.
+ * Converged when ||F|| <= tol tr(M), or when the active set has been the same
+ * for the last n steps (a full conjugate-gradient cycle on one quadratic
+ * piece) and the last step was small, ||step||_inf <= tol (1 + ||a||_inf).
+ * Outputs as oracle_forward. */
+int oracle_forward_cg(int n, int m, const double *M, const double *J, const double *a0,
+                      const double *aref, const double *D, int max_iter, double tol,
+                      double *a, unsigned char *active, int *iters, int *status) {
+    size_t nn = (size_t)n * n, mn = (size_t)m * n;
+    *iters = 0;
+    if (!all_finite(nn, M) || !all_finite(mn, J) || !all_finite(n, a0) ||
+        !all_finite(m, aref) || !all_finite(m, D)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) active[i] = 0;
+        *status = ST_NONFINITE;
+        return 0;
+    }
+    if (!is_spd(n, M)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) active[i] = 0;
+        *status = ST_NOTSPD;
+        return 0;
+    }
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *r = (double *)malloc(sizeof(double) * mm);
+    double *q = (double *)malloc(sizeof(double) * mm);
+    double *F = (double *)malloc(sizeof(double) * n1);
+    double *z = (double *)malloc(sizeof(double) * n1);
+    double *zprev = (double *)malloc(sizeof(double) * n1);
+    double *p = (double *)calloc(n1, sizeof(double));
+    unsigned char *Ap = (unsigned char *)malloc(mm);
+    unsigned char *Aprev = (unsigned char *)malloc(mm);
+    for (int j = 0; j < n; ++j) a[j] = a0[j];
+    int st = ST_MAXITER, run = 0;
+    double step_inf = -1.0, fz_prev = 0.0;
+    for (int k = 0;; ++k) {
+        if (k > 0) memcpy(Aprev, active, m);
+        eval_residual(n, m, M, J, a0, aref, D, a, r, active, F);
+        int same = k > 0 && (m == 0 || memcmp(Aprev, active, m) == 0);
+        run = same ? run + 1 : 0;
+        double trM = 0.0;
+        for (int j = 0; j < n; ++j) trM += M[j * n + j];
+        if (sqrt(dot(n, F, F)) <= tol * trM ||
+            (run >= n && step_inf >= 0.0 && step_inf <= tol * (1.0 + inf_norm(n, a)))) {
+            st = ST_CONVERGED;
+            break;
+        }
+        if (k == max_iter) { st = ST_MAXITER; break; }
+        qr_solve(n, M, F, z);
+        double fz = dot(n, F, z), beta = 0.0;
+        if (k > 0 && same && fz_prev > 0.0) {
+            double num = 0.0;
+            for (int j = 0; j < n; ++j) num += F[j] * (z[j] - zprev[j]);
+            beta = fmax(0.0, num / fz_prev);
+        }
+        for (int j = 0; j < n; ++j) p[j] = -z[j] + beta * p[j];
+        if (dot(n, F, p) >= 0.0)
+            for (int j = 0; j < n; ++j) p[j] = -z[j];
+        double alpha = exact_line_search(n, m, M, J, a0, D, a, p, r, q, Ap, NULL);
+        step_inf = 0.0;
+        for (int j = 0; j < n; ++j) {
+            a[j] += alpha * p[j];
+            step_inf = fmax(step_inf, fabs(alpha * p[j]));
+        }
+        memcpy(zprev, z, sizeof(double) * n);
+        fz_prev = fz;
+        *iters = k + 1;
+    }
+    *status = st;
+    free(r); free(q); free(F); free(z); free(zprev); free(p); free(Ap); free(Aprev);
+    return 0;
+}
+
+void oracle_forward_cg_batch(int B, const int32_t *nv, const int32_t *nrows,
+                             const int64_t *off_nn, const int64_t *off_mn, const int64_t *off_n,
+                             const int64_t *off_m, const double *M, const double *J,
+                             const double *a0, const double *aref, const double *D,
+                             int max_iter, double tol, double *a, unsigned char *active,
+                             int32_t *iters, int32_t *status, int threads);
 
 /* IFT VJP at the returned solution (eq. 17, pyramidal rows):
  *   H(A*)^T lambda = abar,  sigma = J lambda,
@@ -646,6 +738,24 @@ void oracle_forward_batch(int B, const int32_t *nv, const int32_t *nrows,
         oracle_forward(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], a0 + off_n[b],
                        aref + off_m[b], D + off_m[b], NULL, max_iter, tol, a + off_n[b],
                        active + off_m[b], &it, &st, NULL, NULL, NULL);
+        iters[b] = it;
+        status[b] = st;
+    }
+}
+
+void oracle_forward_cg_batch(int B, const int32_t *nv, const int32_t *nrows,
+                             const int64_t *off_nn, const int64_t *off_mn, const int64_t *off_n,
+                             const int64_t *off_m, const double *M, const double *J,
+                             const double *a0, const double *aref, const double *D,
+                             int max_iter, double tol, double *a, unsigned char *active,
+                             int32_t *iters, int32_t *status, int threads) {
+    set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < B; ++b) {
+        int it = 0, st = 0;
+        oracle_forward_cg(nv[b], nrows[b], M + off_nn[b], J + off_mn[b], a0 + off_n[b],
+                          aref + off_m[b], D + off_m[b], max_iter, tol, a + off_n[b],
+                          active + off_m[b], &it, &st);
         iters[b] = it;
         status[b] = st;
     }
