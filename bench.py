@@ -342,12 +342,13 @@ def serving(rates=(2000, 5000, 10000, 20000, 50000), n_requests=10000, warmup=10
 
 
 N_REPLAYS = 20
+CG_CAPS = (600, 20000)   # CG steps are heavy-tailed: a practical cap, and one where all converge
 
 
 SCHEDULES = ("sequential", "vjp_overlap", "two_chains")
 
 
-def capture_steps(bufs, batch, steps, K, tol, schedule):
+def capture_steps(bufs, batch, steps, K, tol, schedule, method="newton"):
     """HIP graph of `steps` steps (forward at cap K + IFT VJP, batch i % R at
     step i), in one of three schedules:
       sequential  -- one stream, one launch after another;
@@ -387,7 +388,7 @@ def capture_steps(bufs, batch, steps, K, tol, schedule):
                 fl.wait_event(last_vjp[j])
             with torch.cuda.stream(fl):
                 solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K,
-                               tol=tol, out=sol)
+                               tol=tol, out=sol, method=method)
             if vl is not fl:
                 ef = torch.cuda.Event()
                 ef.record(fl)
@@ -429,7 +430,7 @@ def replay_median(g, reps=N_REPLAYS):
                                    "replays": reps}
 
 
-def kernel_times(bufs, batch, steps, K, tol):
+def kernel_times(bufs, batch, steps, K, tol, method="newton"):
     """Eager sequential pass of the same steps with HIP events around every
     launch on the launch stream: mean forward and VJP kernel ms."""
     import torch
@@ -441,7 +442,7 @@ def kernel_times(bufs, batch, steps, K, tol):
         t, sol, grads = bufs[i % R]
         evs[i][0].record()
         solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=tol,
-                       out=sol)
+                       out=sol, method=method)
         evs[i][1].record()
         solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
         evs[i][2].record()
@@ -484,19 +485,19 @@ def rotation(s, state_bytes):
     return R + (R % 2), per_batch
 
 
-def ift_line(bufs, batch, steps, K, tol, schedules=SCHEDULES, s=4):
+def ift_line(bufs, batch, steps, K, tol, schedules=SCHEDULES, s=4, method="newton"):
     """One throughput line: a graph of `steps` steps at cap K in each schedule,
     median of replays each; the line's value is the fastest schedule's.  Also
     per-kernel times, solver statistics and the forward's roofline position."""
     per = {}
     for sch in schedules:
-        g, keep = capture_steps(bufs, batch, steps, K, tol, sch)
+        g, keep = capture_steps(bufs, batch, steps, K, tol, sch, method)
         ms_s, spread_s = replay_median(g)
         del g, keep
         per[sch] = {"ms_per_step": ms_s / steps, "replay_spread": spread_s}
     best = min(per, key=lambda k: per[k]["ms_per_step"])
     ms, spread = per[best]["ms_per_step"] * steps, per[best]["replay_spread"]
-    t_fwd, t_vjp = kernel_times(bufs, batch, steps, K, tol)
+    t_fwd, t_vjp = kernel_times(bufs, batch, steps, K, tol, method)
     # the eager pass above left batches 0 .. steps-1 solved at cap K
     stats, act, it = solve_stats(bufs[:min(steps, len(bufs))], batch, B, M_ROWS)
     fwd_b, vjp_b = algorithmic_bytes(NV, M_ROWS, s)
@@ -641,6 +642,19 @@ def main():
                  f"{conv['solver']['converged_frac']:.4f}")
         out["fp64_line"] = fp64_line(args.steps, dev)
         progress("FP64 line done")
+        # the other solver for the same minimiser: nonlinear CG forward + the
+        # same IFT VJP
+        out["cg_lines"] = []
+        for cap in CG_CAPS:
+            cg = ift_line(bufs, batch, args.steps, cap, TOL, ("sequential",), method="cg")
+            del cg["kernels"]["forward_tflops"], cg["kernels"]["forward_flops_per_launch"]
+            cg["workload"] = (f"as the headline, nonlinear CG forward (cap {cap} CG steps, "
+                              "tol 1e-5) + IFT VJP")
+            cg["newton_converged_over_cg"] = conv["value"] / cg["value"]
+            out["cg_lines"].append(cg)
+            progress(f"CG forward cap {cap}: {cg['value']:.4g} solves/s, converged "
+                     f"{cg['solver']['converged_frac']:.4f}, mean CG steps "
+                     f"{cg['solver']['mean_iters']:.1f}")
         # back to the headline state for what follows
         for i in range(R):
             t, sol, grads = bufs[i]

@@ -109,7 +109,8 @@ typedef struct cs_batch {
 
 typedef struct cs_solver_params {
     int32_t max_iter;  /* cap on Newton steps (>= 0); the unrolled VJP takes exactly this K */
-    int32_t flags;     /* 0, or for cs_unrolled_vjp one of CS_UNROLLED_RECORD / _REPLAY */
+    int32_t flags;     /* 0; for cs_forward 0 or CS_FORWARD_CG; for cs_unrolled_vjp
+                        * 0, CS_UNROLLED_RECORD or CS_UNROLLED_REPLAY */
     double tol;        /* stopping tolerance (>= 0), see cs_forward */
 } cs_solver_params;
 
@@ -123,6 +124,24 @@ typedef struct cs_solver_params {
  * forward pass to the backward pass. */
 #define CS_UNROLLED_RECORD 1
 #define CS_UNROLLED_REPLAY 2
+
+/* cs_forward solver (cs_solver_params.flags).  0: Newton steps.
+ * CS_FORWARD_CG: preconditioned nonlinear conjugate gradients for the same
+ * minimiser (Sec. III-B names Newton and nonlinear CG as the two solvers; by
+ * eqs. 11-14 the IFT derivative depends on the root only, so cs_ift_vjp and
+ * cs_ift_jvp take its state unchanged).  Directions p_k = -z_k + beta_k p_{k-1},
+ * z = M^{-1} F, Polak-Ribiere beta_k = max(0, F_k . (z_k - z_{k-1}) /
+ * (F_{k-1} . z_{k-1})), restarted when the active set changes or p_k is not a
+ * descent direction; the same exact line search.  Converged when
+ * ||F|| <= tol tr(M) or sqrt(F . M^{-1} F) <= tol sqrt(tr(M)) (1 + ||a||_inf);
+ * since L is M-strongly convex (H >= M), the second test bounds the distance
+ * to the minimiser, ||a - a*||_M <= sqrt(F . M^{-1} F).  max_iter caps CG
+ * steps, which a solve needs many more of than Newton steps.  The iterate and
+ * every sum are FP64 for either dtype (FP32 storage: the a written is the FP64
+ * iterate rounded, then refined as the Newton solve's is).  The state holds
+ * the factor of H(A) at the returned iterate.  SMALL family only (batches it
+ * supports; CS_EUNSUPPORTED otherwise). */
+#define CS_FORWARD_CG 4
 
 /* Bytes of the `state` buffer cs_forward writes and cs_ift_vjp reads: the
  * Cholesky factor of H(A*) as a packed lower triangle per instance (n (n+1)/2
@@ -145,6 +164,7 @@ size_t cs_unrolled_tape_bytes(const cs_batch *batch, int32_t K);
  * ||a_k - a_{k-1}||_inf <= tol (1 + ||a_k||_inf), and left the active set
  * unchanged, A(a_k) = A(a_{k-1}); at most max_iter steps are taken.  M is
  * read as symmetric (the SMALL family reads its lower triangle only).
+ * params->flags = CS_FORWARD_CG selects the conjugate-gradient solver instead.
  * Writes a_out [n per instance], state (factor of H at the returned iterate and
  * its active set), status [B] (CS_ST_* bits) and, if non-NULL, iters [B]
  * (steps taken).  a_init, iters may be NULL. */

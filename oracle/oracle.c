@@ -334,10 +334,12 @@ int oracle_forward(int n, int m, const double *M, const double *J, const double 
  *   (Polak-Ribiere, restarted (beta = 0) at k = 0, when the active set changed,
  *   and whenever p_k is not a descent direction),
  *   a_{k+1} = a_k + alpha_k p_k with the exact line search of the Newton solver.
- * Converged when ||F|| <= tol tr(M), or when the active set has been the same
- * for the last n steps (a full conjugate-gradient cycle on one quadratic
- * piece) and the last step was small, ||step||_inf <= tol (1 + ||a||_inf).
- * Outputs as oracle_forward. */
+ * Converged when ||F|| <= tol tr(M) (the Newton rule's gradient test), or when
+ *   sqrt(F . M^{-1} F) <= tol sqrt(tr(M)) (1 + ||a||_inf).
+ * The second test bounds the distance to the minimiser: L is M-strongly convex
+ * (its curvature is H >= M everywhere), so ||a - a*||_M <= sqrt(F . M^{-1} F).
+ * The Newton rule's small-step test is not used: a short CG step says little
+ * about the distance to the root.  Outputs as oracle_forward. */
 int oracle_forward_cg(int n, int m, const double *M, const double *J, const double *a0,
                       const double *aref, const double *D, int max_iter, double tol,
                       double *a, unsigned char *active, int *iters, int *status) {
@@ -366,23 +368,21 @@ int oracle_forward_cg(int n, int m, const double *M, const double *J, const doub
     unsigned char *Ap = (unsigned char *)malloc(mm);
     unsigned char *Aprev = (unsigned char *)malloc(mm);
     for (int j = 0; j < n; ++j) a[j] = a0[j];
-    int st = ST_MAXITER, run = 0;
-    double step_inf = -1.0, fz_prev = 0.0;
+    int st = ST_MAXITER;
+    double fz_prev = 0.0, trM = 0.0;
+    for (int j = 0; j < n; ++j) trM += M[j * n + j];
     for (int k = 0;; ++k) {
         if (k > 0) memcpy(Aprev, active, m);
         eval_residual(n, m, M, J, a0, aref, D, a, r, active, F);
         int same = k > 0 && (m == 0 || memcmp(Aprev, active, m) == 0);
-        run = same ? run + 1 : 0;
-        double trM = 0.0;
-        for (int j = 0; j < n; ++j) trM += M[j * n + j];
+        qr_solve(n, M, F, z);
+        double fz = dot(n, F, z), beta = 0.0;
         if (sqrt(dot(n, F, F)) <= tol * trM ||
-            (run >= n && step_inf >= 0.0 && step_inf <= tol * (1.0 + inf_norm(n, a)))) {
+            sqrt(fmax(fz, 0.0)) <= tol * sqrt(trM) * (1.0 + inf_norm(n, a))) {
             st = ST_CONVERGED;
             break;
         }
         if (k == max_iter) { st = ST_MAXITER; break; }
-        qr_solve(n, M, F, z);
-        double fz = dot(n, F, z), beta = 0.0;
         if (k > 0 && same && fz_prev > 0.0) {
             double num = 0.0;
             for (int j = 0; j < n; ++j) num += F[j] * (z[j] - zprev[j]);
@@ -392,11 +392,7 @@ int oracle_forward_cg(int n, int m, const double *M, const double *J, const doub
         if (dot(n, F, p) >= 0.0)
             for (int j = 0; j < n; ++j) p[j] = -z[j];
         double alpha = exact_line_search(n, m, M, J, a0, D, a, p, r, q, Ap, NULL);
-        step_inf = 0.0;
-        for (int j = 0; j < n; ++j) {
-            a[j] += alpha * p[j];
-            step_inf = fmax(step_inf, fabs(alpha * p[j]));
-        }
+        for (int j = 0; j < n; ++j) a[j] += alpha * p[j];
         memcpy(zprev, z, sizeof(double) * n);
         fz_prev = fz;
         *iters = k + 1;

@@ -18,6 +18,7 @@ ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_NOTSPD, ST_LSFAIL, ST_BADDESC = 1, 2,
 NV_MAX, NROWS_MAX = 128, 4096
 STATIC_TAPE_BYTES = 64 << 20
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
+UNROLLED_RECORD, UNROLLED_REPLAY, FORWARD_CG = 1, 2, 4
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",

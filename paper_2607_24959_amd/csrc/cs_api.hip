@@ -134,7 +134,9 @@ size_t tape_bytes(const HostBatch &hb, int K) {
 int check_params(const cs_solver_params *p, bool unrolled = false) {
     if (!p) return CS_EINVAL;
     if (p->max_iter < 0 || p->max_iter > kMaxIterCap) return CS_EINVAL;
-    if (unrolled ? (p->flags < 0 || p->flags > CS_UNROLLED_REPLAY) : p->flags != 0) return CS_EINVAL;
+    if (unrolled ? (p->flags < 0 || p->flags > CS_UNROLLED_REPLAY)
+                 : (p->flags != 0 && p->flags != CS_FORWARD_CG))
+        return CS_EINVAL;
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) return CS_EINVAL;
     return CS_OK;
 }
@@ -207,6 +209,16 @@ int forward_t(const HostBatch &hb, const cs_solver_params *p, const void *M, con
     uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
     const int fam = choose_family(hb);
     if (fam < 0) return fam;
+    if (p->flags == CS_FORWARD_CG) {
+        // the conjugate-gradient forward exists in the SMALL family only
+        if (fam != FAM_SMALL) return CS_EUNSUPPORTED;
+        return cs::launch_small_forward_cg<T>(hb.bv, hb.nmax, hb.mmax, p->max_iter, (T)p->tol,
+                                              (const T *)M, (const T *)J, (const T *)a0,
+                                              (const T *)aref, (const T *)D, (const T *)a_init,
+                                              (T *)a_out, fac, mask, status, iters, stream) == 0
+                   ? CS_OK
+                   : CS_EHIP;
+    }
     const int rc = forward_launch<T>(hb, fam, p, M, J, a0, aref, D, a_init, a_out, fac, mask,
                                      status, iters, stream);
     if (rc != CS_OK) return rc;

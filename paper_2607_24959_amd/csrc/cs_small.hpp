@@ -563,6 +563,183 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
     return st;
 }
 
+// The same minimiser by preconditioned nonlinear conjugate gradients (Sec.
+// III-B names it as the other solver; eqs. 11-14: the IFT derivative depends
+// on the root only).  Directions p_k = -z_k + beta_k p_{k-1} with z = M^{-1} F
+// (M is factored once) and Polak-Ribiere beta_k = max(0, F_k . (z_k -
+// z_{k-1}) / (F_{k-1} . z_{k-1})), restarted (beta = 0) when the active set
+// changed or p_k is not a descent direction; every step takes the exact line
+// search of the Newton solve.  Each step costs two passes over J (r and q)
+// instead of the Newton step's J^T D J assembly and Cholesky factorisation.
+//
+// The iterate, directions and every sum are FP64 whatever the storage type:
+// CG takes hundreds to thousands of steps, each building on the last, and in
+// FP32 the gradient's rounding (M (a - a0) and J^T w nearly cancel at the
+// root) stalls it short of the FP32 Newton solve's accuracy.  The
+// preconditioner solve z = M^{-1} F runs in the storage type (any fixed SPD
+// preconditioner leaves the minimiser unchanged).
+//
+// Converged when ||F|| <= tol tr(M) (the Newton rule's gradient test) or
+// F . M^{-1} F <= tol^2 tr(M) (1 + ||a||_inf)^2: L is M-strongly convex (its
+// curvature H >= M everywhere), so ||a - a*||_M <= sqrt(F . M^{-1} F) and the
+// second test bounds the distance to the minimiser.  The Newton rule's
+// small-step test is not used: a short CG step says little about the distance
+// to the root.  On return a holds the iterate rounded to T and H the factor of
+// H(A) at it (the state the IFT VJP reads), assembled once.
+template <typename T, int NP, int R>
+__device__ inline int small_solve_cg(const SmallInst<T, NP, R> &S, int max_iter, T tol,
+                                     T (&a)[NP], T (&H)[Tri<NP>::NE], T (&inv)[NP],
+                                     bool (&act)[R], int &iters) {
+    typedef double C;
+    constexpr int NE = Tri<NP>::NE;
+    iters = 0;
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) act[jj] = false;
+    T Lm[NE], invm[NP];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) Lm[e] = S.Ml[e];
+    if (!reg_cholesky<T, NP>(Lm, invm)) return ST_NOTSPD;
+    C trM = C(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) trM += C(S.Ml[Tri<NP>::idx(j, j)]);
+    trM -= C(NP - S.n);
+    auto mv = [&](const C (&v)[NP], C (&out)[NP]) {   // M v, FP64 sums
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            C t = C(0);
+#pragma unroll
+            for (int l = 0; l < NP; ++l)
+                t += as_f64_here(S.Ml[l <= j ? Tri<NP>::idx(j, l) : Tri<NP>::idx(l, j)]) * v[l];
+            out[j] = t;
+        }
+    };
+    C x[NP], p[NP], zprev[NP], Dc[R];
+    C fz_prev = C(0);
+    int st = 0, lsfail = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        x[j] = C(a[j]);
+        p[j] = C(0);
+        zprev[j] = C(0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) Dc[jj] = C(S.D[jj]);
+    for (int k = 0;; ++k) {
+        C d[NP], Md[NP], F[NP], r[R], wr[R];
+        bool changed = false;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) d[j] = x[j] - C(S.a0[j]);
+        mv(d, Md);
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            C t = C(0);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) t += as_f64_here(S.J[jj][j]) * x[j];
+            r[jj] = t - C(S.aref[jj]);
+            const bool an = r[jj] < C(0);
+            changed |= an != act[jj];
+            act[jj] = an;
+            wr[jj] = an ? Dc[jj] * r[jj] : C(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            C t = C(0);
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) t += as_f64_here(S.J[jj][j]) * wr[jj];
+            F[j] = Md[j] + gsum16(t);
+        }
+        const bool same = (k > 0) && gsum16(changed ? C(1) : C(0)) == C(0);
+        C z[NP];
+        {
+            T Ft[NP], zt[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) Ft[j] = T(F[j]);
+            reg_chol_solve<T, NP>(Lm, invm, Ft, zt);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) z[j] = C(zt[j]);
+        }
+        C g2 = C(0), fz = C(0), xnorm = C(0), beta = C(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            g2 += F[j] * F[j];
+            fz += F[j] * z[j];
+            xnorm = fmax(xnorm, fabs(x[j]));
+        }
+        const C gtol = C(tol) * trM, dtol = C(tol) * (C(1) + xnorm);
+        if (g2 <= gtol * gtol || fz <= dtol * dtol * trM) {
+            st = ST_CONVERGED;
+            break;
+        }
+        if (k == max_iter) { st = ST_MAXITER; break; }
+        if (same && fz_prev > C(0)) {
+            C num = C(0);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) num += F[j] * (z[j] - zprev[j]);
+            beta = fmax(C(0), num / fz_prev);
+        }
+        C fp = C(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            p[j] = -z[j] + beta * p[j];
+            fp += F[j] * p[j];
+        }
+        if (fp >= C(0)) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) p[j] = -z[j];
+        }
+        C q[R];
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            C t = C(0);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) t += as_f64_here(S.J[jj][j]) * p[j];
+            q[jj] = t;
+        }
+        C Mp[NP];
+        mv(p, Mp);
+        C c0 = C(0), b0 = C(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            c0 += p[j] * Mp[j];
+            b0 += Mp[j] * d[j];
+        }
+        uint32_t bits;
+        C cpiece;
+        int fail;
+        const C alpha = small_line_search<false, C, R>(r, q, Dc, c0, b0, bits, cpiece, fail);
+        lsfail |= fail;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            x[j] += alpha * p[j];
+            zprev[j] = z[j];
+        }
+        fz_prev = fz;
+        iters = k + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) a[j] = T(x[j]);
+    if (st & (ST_CONVERGED | ST_MAXITER)) {
+        // H(A) at the returned iterate (eq. 9), factored for the saved state
+        T tj[R][NP];
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) tj[jj][j] = (act[jj] ? S.D[jj] : T(0)) * S.J[jj][j];
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+#pragma unroll
+            for (int l = 0; l <= j; ++l) {
+                T t = T(0);
+#pragma unroll
+                for (int jj = 0; jj < R; ++jj) t += tj[jj][j] * S.J[jj][l];
+                H[Tri<NP>::idx(j, l)] = S.Ml[Tri<NP>::idx(j, l)] + gsum16(t);
+            }
+        if (!reg_cholesky<T, NP>(H, inv)) st = ST_NOTSPD;
+    }
+    if (lsfail) st |= ST_LSFAIL;
+    return st;
+}
+
 // Final refinement of an FP32 solve that met the stopping rule: one Newton
 // step on the converged active set with the gradient F(a) = M (a - a0) +
 // J^T (D o A o (J a - aref)) (eq. 6) formed in FP64 and the step solved with
@@ -598,8 +775,10 @@ __device__ inline void small_refine(const SmallInst<T, NP, R> &S, T (&a)[NP],
     for (int j = 0; j < NP; ++j) a[j] = T(C(a[j]) + C(d[j]));
 }
 
-template <typename T, int NP, int R>
-__global__ __launch_bounds__(256, 2) void k_forward_small(
+// Newton: two workgroups per CU (256 VGPRs a lane); the FP64-arithmetic CG
+// solve keeps more live state and takes one (512).
+template <typename T, int NP, int R, bool CG = false>
+__global__ __launch_bounds__(256, CG ? 1 : 2) void k_forward_small(
     BatchView bv, int nb_inst, int max_iter, T tol, const T *__restrict__ gM,
     const T *__restrict__ gJ, const T *__restrict__ ga0, const T *__restrict__ garef,
     const T *__restrict__ gD, const T *__restrict__ gainit, T *__restrict__ gaout,
@@ -632,8 +811,11 @@ __global__ __launch_bounds__(256, 2) void k_forward_small(
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) act[jj] = false;
     } else {
-        st = small_solve<false, T, NP, R>(S, max_iter, tol, a, H, inv, act, iters,
-                                          StepTape<T>{nullptr, nullptr, 0, 0, 0});
+        if constexpr (CG)
+            st = small_solve_cg<T, NP, R>(S, max_iter, tol, a, H, inv, act, iters);
+        else
+            st = small_solve<false, T, NP, R>(S, max_iter, tol, a, H, inv, act, iters,
+                                              StepTape<T>{nullptr, nullptr, 0, 0, 0});
         if constexpr (sizeof(T) == 4) {
             if (st & ST_CONVERGED) small_refine<T, NP, R>(S, a, H, inv, act);
         }
@@ -1109,6 +1291,23 @@ int launch_small_forward(const BatchView &bv, int nmax, int mmax, int max_iter, 
                        tol, M, J, a0, aref, D, a_init, a_out, fac, mask, status, iters);
     if constexpr (sizeof(T) == 4) { CS_SMALL_F32_12(CS_CALL_FWD) } else { CS_SMALL_F64(CS_CALL_FWD) }
 #undef CS_CALL_FWD
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// The conjugate-gradient forward (small_solve_cg) in the same kernel shell.
+template <typename T>
+int launch_small_forward_cg(const BatchView &bv, int nmax, int mmax, int max_iter, T tol,
+                            const T *M, const T *J, const T *a0, const T *aref, const T *D,
+                            const T *a_init, T *a_out, T *fac, uint8_t *mask, int32_t *status,
+                            int32_t *iters, hipStream_t stream) {
+    const int np = small_np(nmax), rr = small_r(mmax);
+    const int nb = bv.B;
+    const dim3 grid((nb + 15) / 16), block(256);
+#define CS_CALL_FWD_CG(NPV, RV)                                                               \
+    hipLaunchKernelGGL((k_forward_small<T, NPV, RV, true>), grid, block, 0, stream, bv, nb,    \
+                       max_iter, tol, M, J, a0, aref, D, a_init, a_out, fac, mask, status, iters);
+    if constexpr (sizeof(T) == 4) { CS_SMALL_F32_12(CS_CALL_FWD_CG) } else { CS_SMALL_F64(CS_CALL_FWD_CG) }
+#undef CS_CALL_FWD_CG
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

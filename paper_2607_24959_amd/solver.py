@@ -144,7 +144,12 @@ class Solution:
 
 
 def forward(batch: Batch, M, J, a0, aref, D, *, max_iter=10, tol=1e-5, a_init=None,
-            out: Optional[Solution] = None) -> Solution:
+            out: Optional[Solution] = None, method: str = "newton") -> Solution:
+    """Forward solve; method "newton" (Newton steps) or "cg" (nonlinear
+    conjugate gradients, SMALL-family batches only), both with the exact line
+    search.  max_iter caps the steps of the chosen method."""
+    if method not in ("newton", "cg"):
+        raise ValueError(f"unknown method {method!r}")
     s = batch.sizes()
     for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D)):
         batch.check(name, t, s[name])
@@ -159,7 +164,7 @@ def forward(batch: Batch, M, J, a0, aref, D, *, max_iter=10, tol=1e-5, a_init=No
     batch.check("a_out", out.a, s["a"])
     if out.state.numel() < batch.state_bytes():
         raise ValueError("state buffer too small")
-    p = N.CsSolverParams(int(max_iter), 0, float(tol))
+    p = N.CsSolverParams(int(max_iter), N.FORWARD_CG if method == "cg" else 0, float(tol))
     rc = N.forward(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), _vp(a_init),
                    _vp(out.a), _vp(out.state), out.state.numel(), _vp(out.status), _vp(out.iters),
                    _stream(a0.device))
@@ -217,7 +222,7 @@ def unrolled_record(batch: Batch, M, J, a0, aref, D, *, K=10, tol=1e-5, tape=Non
                status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
                iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device), tape=tape, K=K,
                tol=tol)
-    p = N.CsSolverParams(int(K), 1, float(tol))
+    p = N.CsSolverParams(int(K), N.UNROLLED_RECORD, float(tol))
     rc = N.unrolled_vjp(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), None,
                         _vp(out["a"]), None, None, None, None, None, _vp(tape), tape.numel(),
                         _vp(out["status"]), _vp(out["iters"]), _stream(a0.device))
@@ -232,7 +237,7 @@ def unrolled_replay(batch: Batch, rec, M, J, a0, aref, D, abar,
     for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D), ("abar", abar)):
         batch.check(name, t, s[name])
     g = tuple(torch.empty_like(x) for x in (a0, aref, J, D, M))
-    p = N.CsSolverParams(int(rec["K"]), 2, float(rec["tol"]))
+    p = N.CsSolverParams(int(rec["K"]), N.UNROLLED_REPLAY, float(rec["tol"]))
     tape = rec["tape"]
     rc = N.unrolled_vjp(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), _vp(abar),
                         None, *(_vp(t) for t in g), _vp(tape), tape.numel(), _vp(rec["status"]),

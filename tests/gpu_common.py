@@ -19,10 +19,11 @@ def np64(t):
     return t.detach().to("cpu", torch.float64).numpy()
 
 
-def gpu_uniform(b: synth.UniformBatch, dtype, max_iter, tol, vjp=True, order=None, path=0):
+def gpu_uniform(b: synth.UniformBatch, dtype, max_iter, tol, vjp=True, order=None, path=0,
+                method="newton"):
     batch = solver.Batch.uniform(b.B, b.n, b.m, dtype, order=order, path=path)
     t = {k: dev(getattr(b, k), dtype) for k in KEYS + ("abar",)}
-    sol = solver.forward(batch, *(t[k] for k in KEYS), max_iter=max_iter, tol=tol)
+    sol = solver.forward(batch, *(t[k] for k in KEYS), max_iter=max_iter, tol=tol, method=method)
     out = dict(a=sol.a, status=sol.status, iters=sol.iters, state=sol.state)
     if vjp:
         g = solver.ift_vjp(batch, sol, *(t[k] for k in KEYS), t["abar"])
@@ -105,7 +106,7 @@ def _few(flags):
     return flags.mean() < 0.01 if flags.size >= 200 else flags.sum() <= 2
 
 
-def gpu_packed(pb, dtype, max_iter, tol, path=0, plan=False, vjp=True):
+def gpu_packed(pb, dtype, max_iter, tol, path=0, plan=False, vjp=True, method="newton"):
     """Forward (+ IFT VJP) of a packed batch through the C ABI; flat host arrays."""
     from paper_2607_24959_amd import batching
     npd = np.float32 if dtype == torch.float32 else np.float64
@@ -117,7 +118,8 @@ def gpu_packed(pb, dtype, max_iter, tol, path=0, plan=False, vjp=True):
         sol = runner.forward(*(t[k] for k in KEYS), max_iter=max_iter, tol=tol)
         g = runner.ift_vjp(sol, *(t[k] for k in KEYS), t["abar"]) if vjp else None
     else:
-        sol = solver.forward(batch, *(t[k] for k in KEYS), max_iter=max_iter, tol=tol)
+        sol = solver.forward(batch, *(t[k] for k in KEYS), max_iter=max_iter, tol=tol,
+                             method=method)
         g = solver.ift_vjp(batch, sol, *(t[k] for k in KEYS), t["abar"]) if vjp else None
     torch.cuda.synchronize()
     out = dict(a=np64(sol.a).ravel(), status=sol.status.cpu().numpy(), iters=sol.iters.cpu().numpy(),

@@ -92,6 +92,9 @@ def test_argument_validation_before_launch():
     assert _fwd(_desc(B=-1)) == N.CS_EINVAL
     assert _fwd(_desc(), N.CsSolverParams(-1, 0, 1e-5)) == N.CS_EINVAL
     assert _fwd(_desc(), N.CsSolverParams(10, 1, 1e-5)) == N.CS_EINVAL
+    assert _fwd(_desc(), N.CsSolverParams(10, 3, 1e-5)) == N.CS_EINVAL
+    assert _fwd(_desc(), N.CsSolverParams(10, N.FORWARD_CG | 1, 1e-5)) == N.CS_EINVAL
+    assert _fwd(_desc(dtype=7), N.CsSolverParams(10, N.FORWARD_CG, 1e-5)) == N.CS_EINVAL
     assert _fwd(_desc(), N.CsSolverParams(10, 0, float("nan"))) == N.CS_EINVAL
     assert _fwd(_desc(), N.CsSolverParams(10, 0, -1.0)) == N.CS_EINVAL
     assert _fwd(_desc(), state_nbytes=16) == N.CS_ENOSPC
