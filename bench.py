@@ -323,6 +323,58 @@ def ilqr_jacobians(reps=20):
                          "unit": "TFLOP/s (FP64 vector)", "frac": flops / (ms / 1e3) / 78.6e12}}
 
 
+def rollout_line(B_=1024, n=18, nc=32, horizon=50, reps=5):
+    """The differentiation workload (B=1024, nv=18, 32 contacts, h=0.002,
+    horizon 50, FP64, loss ||v_T - v_goal||^2): the gradient w.r.t. tau by
+    the fused rollout (forward and backward through time in one cs_rollout
+    launch; keeping each step's factor, or recomputing it) against the
+    layered rollout (one forward launch per step, autograd backward with one
+    IFT VJP launch per step).  Median of `reps` timed runs each (HIP events,
+    one untimed run first)."""
+    import torch
+    from paper_2607_24959_amd import rollout as R
+    P = R.make_rollout_problem(B_, n, nc, horizon, seed=20260727)
+
+    def fused(recompute):
+        return lambda: R.fused_loss_grad(P["M"], P["J"], P["D"], P["pen"], P["v0"], P["tau"],
+                                         P["v_goal"], max_iter=60, tol=1e-12, recompute=recompute)
+
+    def layered():
+        tau = P["tau"].clone().requires_grad_(True)
+        v = R.rollout(P["M"], P["J"], P["D"], P["pen"], P["v0"], tau, max_iter=60, tol=1e-12)
+        ((v - P["v_goal"]) ** 2).sum().backward()
+        return tau.grad
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(max(e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3))
+        return float(np.median(ms)), out
+
+    t_store, o = timed(fused(False))
+    t_rec, _ = timed(fused(True))
+    t_lay, g_lay = timed(layered)
+    e = ((o["tau_bar"] - g_lay).transpose(0, 1).flatten(1).norm(dim=1) /
+         g_lay.transpose(0, 1).flatten(1).norm(dim=1)).max().item()
+    return {"workload": f"rollout gradient, B={B_}, nv={n}, {nc} contacts, horizon {horizon}, "
+                        "h=0.002, FP64, tol 1e-12",
+            "fused_ms": t_store, "fused_recompute_ms": t_rec, "layered_ms": t_lay,
+            "fused_speedup": t_lay / t_store,
+            "rollouts_per_s": B_ / (t_store / 1e3),
+            "newton_steps_per_solve": float(o["iters"].double().mean().item()) / horizon,
+            "converged_frac": float(((o["status"] & 1) != 0).double().mean().item()),
+            "max_rel_diff_vs_layered": e}
+
+
 def serving(rates=(2000, 5000, 10000, 20000, 50000), n_requests=10000, warmup=1000,
             budget_bytes=256 * 2 ** 20):
     """Poisson streams of 6-step MPC windows (nv in {3,9,18}, contacts U{0..64},
@@ -679,6 +731,9 @@ def main():
         progress("uneven batch done")
         out["ilqr_jacobians"] = ilqr_jacobians()
         progress("iLQR Jacobians done")
+        out["rollout"] = rollout_line()
+        progress(f"fused rollout: {out['rollout']['fused_ms']:.3g} ms vs layered "
+                 f"{out['rollout']['layered_ms']:.3g} ms")
         out["serving"] = serving(rates, n_requests=args.serve_requests,
                                  warmup=max(1, args.serve_requests // 10))
     if not args.no_cpu:

@@ -238,6 +238,54 @@ int cs_unrolled_vjp_static(const cs_batch *batch, const cs_solver_params *params
                            void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *Mbar,
                            int32_t *status, int32_t *iters, void *stream);
 
+/* Whole rollouts through the solve in one launch (Sec. IV-A: a
+ * semi-implicit trajectory v_{t+1} = v_t + h a_t, a_t the contact solve's
+ * solution; Sec. III-C, eq. 17: each solve's adjoint; Sec. IV-B: the forward's
+ * states kept for, or recomputed in, the backward).  Per instance and step
+ * t = 0 .. horizon-1, with M, J, D fixed over the horizon:
+ *   a0_t = M^{-1} tau_t,   aref_t = -b_damp J v_t + c,   a_t = solve (as
+ *   cs_forward: Newton, exact line search, the same stopping rule, starting
+ *   at a0_t),   v_{t+1} = v_t + h a_t.
+ * The backward, from v-bar_T (given, or 2 (v_T - v_goal), the gradient of
+ * ||v_T - v_goal||^2), runs t = horizon-1 .. 0:
+ *   lambda_t = H_t^{-1} (h v-bar_{t+1}),  tau-bar_t = lambda_t,
+ *   v-bar_t = v-bar_{t+1} - b_damp J^T (D o A_t o J lambda_t),
+ * and writes tau-bar and v-bar_0.  flags: CS_ROLLOUT_FORWARD and/or
+ * CS_ROLLOUT_BACKWARD (both: one launch for the loss gradient), and
+ * CS_ROLLOUT_RECOMPUTE to keep only each step's active set (m bytes) and
+ * rebuild H_t = M + J^T diag(D o A_t) J in the backward instead of keeping
+ * its factor.  A BACKWARD-only call reads the workspace and status a FORWARD
+ * call with the same inputs and flags left, and needs vbar_T.  Layouts:
+ * M [n x n], J [m x n] row-major, D and c [m], v0, v_goal, vbar_T, v_T,
+ * v0_bar [n] at the batch's offsets; tau and tau_bar step-major,
+ * [horizon][total_n].  c may be NULL (zero).  status [B] (required): the
+ * CS_ST_* bits of every step OR-ed, CONVERGED only when every step
+ * converged; iters [B] (may be NULL): Newton steps over the horizon.  n <= 32
+ * per instance and J resident in LDS (m n + 3 n^2 + 5 m values within
+ * 160 KiB), else CS_EUNSUPPORTED.  Workspace: cs_rollout_workspace_bytes. */
+typedef struct cs_rollout_params {
+    int32_t horizon;   /* steps T >= 1 */
+    int32_t flags;     /* CS_ROLLOUT_FORWARD | CS_ROLLOUT_BACKWARD [| CS_ROLLOUT_RECOMPUTE] */
+    int32_t max_iter;  /* Newton steps per solve (>= 0) */
+    int32_t reserved;  /* 0 */
+    double tol;        /* stopping tolerance of each solve (>= 0) */
+    double h;          /* time step */
+    double b_damp;     /* damping of the reference acceleration */
+} cs_rollout_params;
+#define CS_ROLLOUT_FORWARD 1
+#define CS_ROLLOUT_BACKWARD 2
+#define CS_ROLLOUT_RECOMPUTE 4
+
+/* Workspace bytes for cs_rollout: per step, the factors of H_t (omitted with
+ * CS_ROLLOUT_RECOMPUTE) and the active sets.  0 on invalid arguments. */
+size_t cs_rollout_workspace_bytes(const cs_batch *batch, const cs_rollout_params *params);
+
+int cs_rollout(const cs_batch *batch, const cs_rollout_params *params, const void *M,
+               const void *J, const void *D, const void *c, const void *v0, const void *tau,
+               const void *v_goal, const void *vbar_T, void *v_T, void *tau_bar, void *v0_bar,
+               void *workspace, size_t workspace_bytes, int32_t *status, int32_t *iters,
+               void *stream);
+
 /* Name of an error code. */
 const char *cs_strerror(int code);
 

@@ -19,8 +19,10 @@ NV_MAX, NROWS_MAX = 128, 4096
 STATIC_TAPE_BYTES = 64 << 20
 PATH_AUTO, PATH_TEAM, PATH_SMALL, PATH_CHUNK, PATH_WAVE = 0, 1, 2, 3, 4
 UNROLLED_RECORD, UNROLLED_REPLAY, FORWARD_CG = 1, 2, 4
+ROLLOUT_FORWARD, ROLLOUT_BACKWARD, ROLLOUT_RECOMPUTE = 1, 2, 4
 
-EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static", "cs_state_bytes",
+EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static",
+            "cs_rollout", "cs_rollout_workspace_bytes", "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
             "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
 
@@ -42,6 +44,12 @@ class CsBatch(C.Structure):
 
 class CsSolverParams(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("flags", C.c_int32), ("tol", C.c_double)]
+
+
+class CsRolloutParams(C.Structure):
+    _fields_ = [("horizon", C.c_int32), ("flags", C.c_int32), ("max_iter", C.c_int32),
+                ("reserved", C.c_int32), ("tol", C.c_double), ("h", C.c_double),
+                ("b_damp", C.c_double)]
 
 
 class CsServeTable(C.Structure):
@@ -92,6 +100,11 @@ def lib():
         L.cs_ift_vjp.argtypes = [pb, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.cs_ift_jvp.restype = C.c_int
         L.cs_ift_jvp.argtypes = [pb, vp, sz, vp, vp, vp, i32, vp, vp, vp, vp]
+        prp = C.POINTER(CsRolloutParams)
+        L.cs_rollout_workspace_bytes.restype = sz
+        L.cs_rollout_workspace_bytes.argtypes = [pb, prp]
+        L.cs_rollout.restype = C.c_int
+        L.cs_rollout.argtypes = [pb, prp] + [vp] * 12 + [sz, vp, vp, vp]
         L.cs_unrolled_vjp.restype = C.c_int
         L.cs_unrolled_vjp.argtypes = [pb, pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                       sz, vp, vp, vp]
@@ -147,6 +160,16 @@ def ift_vjp(batch, state, state_nbytes, M, J, a0, aref, D, a, abar, a0bar, arefb
 def ift_jvp(batch, state, state_nbytes, M, J, D, k, da0, daref, da, stream):
     return lib().cs_ift_jvp(C.byref(batch), state, state_nbytes, M, J, D, int(k), da0, daref, da,
                             stream)
+
+
+def rollout_workspace_bytes(batch, params):
+    return lib().cs_rollout_workspace_bytes(C.byref(batch), C.byref(params))
+
+
+def rollout(batch, params, M, J, D, c, v0, tau, v_goal, vbar_T, v_T, tau_bar, v0_bar, ws, ws_nbytes,
+            status, iters, stream):
+    return lib().cs_rollout(C.byref(batch), C.byref(params), M, J, D, c, v0, tau, v_goal, vbar_T,
+                            v_T, tau_bar, v0_bar, ws, ws_nbytes, status, iters, stream)
 
 
 def unrolled_vjp(batch, params, M, J, a0, aref, D, abar, a_out, a0bar, arefbar, Jbar, Dbar, Mbar,

@@ -13,6 +13,7 @@
 #include "cs_chunk.hpp"
 #include "cs_generic.hpp"
 #include "cs_jvp.hpp"
+#include "cs_rollout.hpp"
 #include "cs_small.hpp"
 #include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
@@ -383,6 +384,63 @@ int unrolled_t(const HostBatch &hb, const cs_solver_params *p, int mode, const v
     return launch_status();
 }
 
+int rollout_check(const HostBatch &hb, const cs_rollout_params *p) {
+    if (!p) return CS_EINVAL;
+    if (p->horizon < 1 || p->max_iter < 0 || p->max_iter > kMaxIterCap || p->reserved != 0)
+        return CS_EINVAL;
+    const int known = CS_ROLLOUT_FORWARD | CS_ROLLOUT_BACKWARD | CS_ROLLOUT_RECOMPUTE;
+    if ((p->flags & ~known) || !(p->flags & (CS_ROLLOUT_FORWARD | CS_ROLLOUT_BACKWARD)))
+        return CS_EINVAL;
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol) || !std::isfinite(p->h) ||
+        !std::isfinite(p->b_damp))
+        return CS_EINVAL;
+    (void)hb;
+    return CS_OK;
+}
+
+size_t rollout_step_bytes(const HostBatch &hb, bool recompute, size_t *mask_off) {
+    const size_t fac = recompute ? 0 : align256(hb.s * factor_elems(hb));
+    if (mask_off) *mask_off = fac;
+    return fac + align256((size_t)hb.tot_m);
+}
+
+template <typename T>
+int rollout_t(const HostBatch &hb, const cs_rollout_params *p, const void *M, const void *J,
+              const void *D, const void *c, const void *v0, const void *tau, const void *v_goal,
+              const void *vbar_T, void *v_T, void *tau_bar, void *v0_bar, void *ws,
+              int32_t *status, int32_t *iters, hipStream_t stream) {
+    cs::RolloutArgs<T> g;
+    g.M = (const T *)M;
+    g.J = (const T *)J;
+    g.D = (const T *)D;
+    g.cref = (const T *)c;
+    g.v0 = (const T *)v0;
+    g.tau = (const T *)tau;
+    g.vgoal = (const T *)v_goal;
+    g.vbarT = (const T *)vbar_T;
+    g.vT = (T *)v_T;
+    g.taubar = (T *)tau_bar;
+    g.v0bar = (T *)v0_bar;
+    g.ws = (uint8_t *)ws;
+    g.recompute = (p->flags & CS_ROLLOUT_RECOMPUTE) != 0;
+    size_t moff = 0;
+    g.ws_step = (int64_t)rollout_step_bytes(hb, g.recompute, &moff);
+    g.mask_off = (int64_t)moff;
+    g.status = status;
+    g.iters = iters;
+    g.tot_n = hb.tot_n;
+    g.horizon = p->horizon;
+    g.max_iter = p->max_iter;
+    g.fwd = (p->flags & CS_ROLLOUT_FORWARD) != 0;
+    g.bwd = (p->flags & CS_ROLLOUT_BACKWARD) != 0;
+    g.tol = (T)p->tol;
+    g.h = (T)p->h;
+    g.bdamp = (T)p->b_damp;
+    return cs::launch_rollout<T>(hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, stream) == 0 ? CS_OK
+                                                                                    : CS_EHIP;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -477,6 +535,39 @@ int cs_ift_jvp(const cs_batch *batch, const void *state, size_t state_bytes_give
                                        (const double *)M, (const double *)J, (const double *)D,
                                        (const double *)da0, (const double *)daref, (double *)da, s);
     return r == 0 ? CS_OK : CS_EHIP;
+}
+
+size_t cs_rollout_workspace_bytes(const cs_batch *batch, const cs_rollout_params *params) {
+    HostBatch hb;
+    if (describe(batch, hb) != CS_OK || rollout_check(hb, params) != CS_OK) return 0;
+    return (size_t)params->horizon *
+           rollout_step_bytes(hb, (params->flags & CS_ROLLOUT_RECOMPUTE) != 0, nullptr);
+}
+
+int cs_rollout(const cs_batch *batch, const cs_rollout_params *params, const void *M,
+               const void *J, const void *D, const void *c, const void *v0, const void *tau,
+               const void *v_goal, const void *vbar_T, void *v_T, void *tau_bar, void *v0_bar,
+               void *workspace, size_t workspace_bytes, int32_t *status, int32_t *iters,
+               void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = rollout_check(hb, params)) != CS_OK) return rc;
+    if (hb.B == 0) return CS_OK;
+    const bool fwd = params->flags & CS_ROLLOUT_FORWARD, bwd = params->flags & CS_ROLLOUT_BACKWARD;
+    if (!M || !status || !workspace) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !D)) return CS_EINVAL;
+    if (fwd && (!v0 || !tau || !v_T)) return CS_EINVAL;
+    if (bwd && (!tau_bar || !v0_bar)) return CS_EINVAL;
+    if (bwd && !vbar_T && !(fwd && v_goal)) return CS_EINVAL;
+    if (workspace_bytes < cs_rollout_workspace_bytes(batch, params)) return CS_ENOSPC;
+    if (!cs::rollout_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hb.dtype == CS_F32)
+        return rollout_t<float>(hb, params, M, J, D, c, v0, tau, v_goal, vbar_T, v_T, tau_bar,
+                                v0_bar, workspace, status, iters, s);
+    return rollout_t<double>(hb, params, M, J, D, c, v0, tau, v_goal, vbar_T, v_T, tau_bar, v0_bar,
+                             workspace, status, iters, s);
 }
 
 int cs_unrolled_vjp(const cs_batch *batch, const cs_solver_params *params, const void *M,

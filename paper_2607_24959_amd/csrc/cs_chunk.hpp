@@ -746,6 +746,11 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     if ((tid & 63) == 0) L.Ln[tid >> 6] = cntw;
                 }
                 if (__syncthreads_or(k == 0 && nonfin)) { st = ST_NONFINITE; break; }
+                // H depends on the active set only: when it is unchanged the
+                // previous step's factor (still in L.H / L.diag) is H's, and
+                // the step needs only J^T w from the gathered rows
+                const bool same = !__syncthreads_or(changed);
+                const bool reuse = k > 0 && same;
                 {
                     int off[NT / 64], total = 0;
 #pragma unroll
@@ -755,13 +760,14 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     }
                     const int ncha = (total + CR - 1) / CR;
                     for (int c = 0; c < ncha; ++c) {
-                        ch_gather<NT>(J, n, ldj, c, total, off, cap, fused, L);
-                        if (!fused) cs.add_chunk(ldj, L.Jc, L.Wr);
-                        acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Wc, L.Lc);
+                        ch_gather<NT>(J, n, ldj, c, total, off, cap, fused && !reuse, L);
+                        if (!fused || reuse) cs.add_chunk(ldj, L.Jc, L.Wr);
+                        if (!reuse) acc.add_chunk(ldj, L.Jc, L.Wc, L.Lr, L.Wc, L.Lc);
                     }
                 }
-                const bool same = !__syncthreads_or(changed);
-                if constexpr (sizeof(T) == 4) {
+                if (reuse) {
+                    cs.finish(n, ldj, L.Jc, L.u, L.F);
+                } else if constexpr (sizeof(T) == 4) {
                     if (fused) {
                         acc.store_hf(n, ldh, Mk, L.H, L.u, L.F);
                         __syncthreads();
@@ -784,7 +790,7 @@ __global__ __launch_bounds__(NT) void k_forward_chunk(
                     g2 = v1[0];
                 }
                 const T anorm = team_max<NT>(an, L.red);
-                if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) { st = ST_NOTSPD; break; }
+                if (!reuse && !team_cholesky<NT>(L.H, L.diag, n, ldh, L.Jc)) { st = ST_NOTSPD; break; }
                 if (sqrt(g2) <= tol * trM ||
                     (k > 0 && step_inf >= T(0) && same && step_inf <= tol * (T(1) + anorm))) {
                     st = ST_CONVERGED;

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import torch
 
+from . import _native as N
 from . import solver, synth
 from .autograd import contact_solve
 
@@ -69,3 +70,82 @@ def step_jacobians(M, J, D, sol, batch, h=0.002):
     B_t = h * da[:, :n, :].transpose(1, 2)
     A_t = eye + h * da[:, n:, :].transpose(1, 2)
     return A_t, B_t
+
+
+# ------------------------------------------------------------------ fused rollout
+#
+# The same rollout as `rollout`, forward and backward each in one launch of
+# cs_rollout (J, M and M's factor stay on chip for the whole horizon).
+
+def _fused_call(batch, flags, max_iter, tol, h, M, J, D, c, v0, tau, v_goal=None, vbar_T=None,
+                ws=None, status=None, iters=None, v_T=None, recompute=False):
+    T_h = tau.shape[0]
+    p = N.CsRolloutParams(int(T_h), int(flags | (N.ROLLOUT_RECOMPUTE if recompute else 0)),
+                          int(max_iter), 0, float(tol), float(h), float(synth.B_DAMP))
+    need = N.rollout_workspace_bytes(batch.desc, p)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=M.device)
+    if status is None:
+        status = torch.empty(batch.B, dtype=torch.int32, device=M.device)
+    if iters is None:
+        iters = torch.empty(batch.B, dtype=torch.int32, device=M.device)
+    fwd, bwd = bool(flags & N.ROLLOUT_FORWARD), bool(flags & N.ROLLOUT_BACKWARD)
+    if fwd and v_T is None:
+        v_T = torch.empty_like(v0)
+    tau_bar = torch.empty_like(tau) if bwd else None
+    v0_bar = torch.empty(batch.B, M.shape[-1], dtype=M.dtype, device=M.device) if bwd else None
+    vp = solver._vp
+    rc = N.rollout(batch.desc, p, vp(M), vp(J), vp(D), vp(c), vp(v0), vp(tau), vp(v_goal),
+                   vp(vbar_T), vp(v_T), vp(tau_bar), vp(v0_bar), vp(ws), ws.numel(), vp(status),
+                   vp(iters), solver._stream(M.device))
+    N.check(rc, "cs_rollout")
+    return dict(v_T=v_T, tau_bar=tau_bar, v0_bar=v0_bar, ws=ws, status=status, iters=iters)
+
+
+def _fused_inputs(M, J, D, pen, v0, tau):
+    B, m, n = J.shape
+    c = (-synth.K_SPRING * torch.repeat_interleave(pen, synth.ROWS_PER_CONTACT, dim=-1)).contiguous()
+    batch = solver.Batch.uniform(B, n, m, M.dtype, device=M.device)
+    return batch, M.contiguous(), J.contiguous(), D.contiguous(), c, v0.contiguous(), tau.contiguous()
+
+
+def _default_tol(dtype):
+    return 1e-12 if dtype == torch.float64 else 1e-5
+
+
+class _FusedRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, M, J, D, pen, v0, tau, h, max_iter, tol, recompute):
+        batch, Mc, Jc, Dc, c, v0c, tauc = _fused_inputs(M, J, D, pen, v0, tau)
+        out = _fused_call(batch, N.ROLLOUT_FORWARD, max_iter, tol, h, Mc, Jc, Dc, c, v0c, tauc,
+                          recompute=recompute)
+        ctx.batch, ctx.args = batch, (max_iter, tol, h, recompute)
+        ctx.save_for_backward(Mc, Jc, Dc, c, tauc, out["ws"], out["status"])
+        ctx.mark_non_differentiable(out["status"])
+        return out["v_T"], out["status"]
+
+    @staticmethod
+    def backward(ctx, gv, _gst):
+        Mc, Jc, Dc, c, tauc, ws, status = ctx.saved_tensors
+        max_iter, tol, h, recompute = ctx.args
+        out = _fused_call(ctx.batch, N.ROLLOUT_BACKWARD, max_iter, tol, h, Mc, Jc, Dc, c, None, tauc,
+                          vbar_T=gv.contiguous(), ws=ws, status=status, recompute=recompute)
+        return None, None, None, None, out["v0_bar"], out["tau_bar"], None, None, None, None
+
+
+def fused_rollout(M, J, D, pen, v0, tau, *, h=0.002, max_iter=50, tol=None, recompute=False):
+    """v_T of the rollout `rollout` computes, from one cs_rollout launch; its
+    backward (w.r.t. tau and v0) is one more launch.  Returns (v_T, status)."""
+    tol = _default_tol(M.dtype) if tol is None else tol
+    return _FusedRollout.apply(M, J, D, pen, v0, tau, float(h), int(max_iter), float(tol),
+                               bool(recompute))
+
+
+def fused_loss_grad(M, J, D, pen, v0, tau, v_goal, *, h=0.002, max_iter=50, tol=None,
+                    recompute=False):
+    """Forward, loss ||v_T - v_goal||^2 and its gradient w.r.t. tau and v0 in
+    ONE launch.  Returns dict(v_T, tau_bar, v0_bar, status, iters)."""
+    tol = _default_tol(M.dtype) if tol is None else tol
+    batch, Mc, Jc, Dc, c, v0c, tauc = _fused_inputs(M, J, D, pen, v0, tau)
+    return _fused_call(batch, N.ROLLOUT_FORWARD | N.ROLLOUT_BACKWARD, max_iter, tol, h, Mc, Jc, Dc,
+                       c, v0c, tauc, v_goal=v_goal.contiguous(), recompute=recompute)

@@ -146,3 +146,27 @@ def test_static_tape_entry_rejects_before_any_launch():
     for flags in (1, 2):
         p = N.CsSolverParams(10, flags, 1e-5)
         assert N.unrolled_vjp_static(b.desc, p, *args) == N.CS_EINVAL
+
+
+def test_rollout_workspace_and_argument_validation():
+    """cs_rollout_workspace_bytes: per step, the factors (256-aligned) then the
+    active sets (256-aligned), or the active sets alone when recomputing;
+    invalid parameters give 0 bytes and CS_EINVAL before any launch."""
+    b = solver.Batch.uniform(4, 6, 8, torch.float64, device="cpu")
+    al = lambda x: (x + 255) // 256 * 256
+    P = lambda T, flags, **kw: N.CsRolloutParams(T, flags, kw.get("max_iter", 20), kw.get("res", 0),
+                                                 kw.get("tol", 1e-12), 0.002, 100.0)
+    step = al(8 * 4 * 21) + al(4 * 8)
+    assert N.rollout_workspace_bytes(b.desc, P(3, 3)) == 3 * step
+    assert N.rollout_workspace_bytes(b.desc, P(3, 1)) == 3 * step
+    assert N.rollout_workspace_bytes(b.desc, P(3, 7)) == 3 * al(4 * 8)
+    for bad in (P(0, 3), P(3, 0), P(3, 8), P(3, 4), P(3, 3, max_iter=-1), P(3, 3, res=1),
+                P(3, 3, tol=float("nan"))):
+        assert N.rollout_workspace_bytes(b.desc, bad) == 0
+        rc = N.rollout(b.desc, bad, *([None] * 11), None, 0, None, None, None)
+        assert rc == N.CS_EINVAL
+    # required pointers are checked before any launch
+    ws = C.c_void_p(1)
+    rc = N.rollout(b.desc, P(3, 1), None, None, None, None, None, None, None, None, None, None,
+                   None, ws, 1 << 20, None, None, None)
+    assert rc == N.CS_EINVAL
