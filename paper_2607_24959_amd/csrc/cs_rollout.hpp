@@ -83,6 +83,44 @@ __device__ inline void ro_tri(int e, int &j, int &l) {
     l = e - j * (j + 1) / 2;
 }
 
+// H's lower triangle (row stride n) = M + sum over the listed rows of
+// D_i J_ij J_il: thread tid owns entries tid + RO_NT k, k < E, and walks the
+// rows once for all of them (independent accumulators, every load of a row
+// issued together).
+template <int E, typename T>
+__device__ inline void ro_assemble(int n, int ne, int ldj, int cnt, const int *list, const T *Dv,
+                                   const T *Js, const T *Ms, T *H) {
+    const int tid = threadIdx.x;
+    int jo[E], lo[E];
+    T s[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int e = min(tid + RO_NT * k, ne - 1);   // clamped: every read in bounds
+        int j, l;
+        ro_tri(e, j, l);
+        jo[k] = j;
+        lo[k] = l;
+        s[k] = T(0);
+    }
+#pragma unroll 2
+    for (int c = 0; c < cnt; ++c) {
+        const int i = list[c];
+        const T d = Dv[i];
+        const T *Jr = Js + i * ldj;
+        T x[E], y[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            x[k] = Jr[jo[k]];
+            y[k] = Jr[lo[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) s[k] += (d * x[k]) * y[k];
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+        if (tid + RO_NT * k < ne) H[jo[k] * n + lo[k]] = Ms[jo[k] * n + lo[k]] + s[k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int nmax, int mmax,
                                                    RolloutArgs<T> g) {
@@ -162,15 +200,16 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
         };
         // H = M + J^T diag(D o A) J over the listed rows (eq. 9), lower triangle
         auto assemble = [&](int cnt) {
-            for (int e = tid; e < ne; e += NT) {
-                int j, l;
-                ro_tri(e, j, l);
-                T s = Ms[j * n + l];
-                for (int c = 0; c < cnt; ++c) {
-                    const int i = list[c];
-                    s += Dv[i] * Js[i * ldj + j] * Js[i * ldj + l];
-                }
-                H[j * n + l] = s;
+            switch ((ne + NT - 1) / NT) {   // entries per thread, 1 .. 9 for n <= 32
+                case 1: ro_assemble<1>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 2: ro_assemble<2>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 3: ro_assemble<3>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 4: ro_assemble<4>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 5: ro_assemble<5>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 6: ro_assemble<6>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 7: ro_assemble<7>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                case 8: ro_assemble<8>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
+                default: ro_assemble<9>(n, ne, ldj, cnt, list, Dv, Js, Ms, H); break;
             }
             __syncthreads();
         };
@@ -215,6 +254,7 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                     bool changed = false;
                     for (int i = tid; i < m; i += NT) {
                         T s = T(0);
+#pragma unroll 8
                         for (int j = 0; j < n; ++j) s += Js[i * ldj + j] * a[j];
                         const T ri = s - ar[i];
                         r[i] = ri;
@@ -259,6 +299,7 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                     team_chol_solve<NT>(H, dh, y, p, n, n);
                     for (int i = tid; i < m; i += NT) {
                         T s = T(0);
+#pragma unroll 8
                         for (int j = 0; j < n; ++j) s += Js[i * ldj + j] * p[j];
                         q[i] = s;
                     }
