@@ -9,21 +9,21 @@ synthetic inputs) that their working set exceeds twice the 256 MB last-level
 
 The K timed steps are captured once into a HIP graph; the value is the median
 over 20 timed replays of that graph (each replay exactly K steps, bracketed by
-synchronisation; one untimed replay first).  In the headline graph each
-batch's VJP runs on a second stream once its forward is done, overlapping the
-next batch's forward (sequential: one stream, one launch after another; both
-reported).
-An eager sequential pass over the same K steps with HIP events around every
-launch gives the per-kernel durations behind the dominant kernel's roofline
-position.
+synchronisation; one untimed replay first), in the fastest of three schedules
+(one stream; each VJP on a second stream overlapping the next forward; two
+independent chains of batches on two streams).  Graphs of the K forwards
+alone and of the K VJPs alone, timed the same way, give the per-kernel
+durations behind the dominant kernel's roofline position.
 
 Also in the same line: the same workload with a cap (K = 40) at which every
 instance converges, so the IFT is evaluated at the tolerance-converged root
 the paper's derivative is defined at; the FP64 path at the same shape; the
-unrolled-trace gradient at K = 10 (the library's fused trace kernels, timed
-from a graph like the IFT path, and plain reverse-mode AD of the same solve by
-PyTorch autograd); the K sweep with memory; the uneven batch; the serving
-streams; and the FP64 oracle timed on the host cores on bounded samples.
+nonlinear-CG forward feeding the same VJP; the unrolled-trace gradient at
+K = 10 (the library's fused trace kernels, timed from a graph like the IFT
+path, and plain reverse-mode AD of the same solve by PyTorch autograd); the K
+sweep with memory; the uneven batch; the iLQR step Jacobians; the fused
+rollout gradient; the serving streams; and the FP64 oracle timed on the host
+cores on bounded samples.
 """
 from __future__ import annotations
 
@@ -483,24 +483,34 @@ def replay_median(g, reps=N_REPLAYS):
 
 
 def kernel_times(bufs, batch, steps, K, tol, method="newton"):
-    """Eager sequential pass of the same steps with HIP events around every
-    launch on the launch stream: mean forward and VJP kernel ms."""
+    """Per-kernel durations on the launch stream: one HIP graph of the `steps`
+    forwards alone (back to back on one stream) and one of the `steps` IFT
+    VJPs alone, each timed like the throughput line (HIP events around the
+    replay, median of replays); the mean launch is the replay time / steps.
+    Leaves batches 0 .. steps-1 solved at cap K."""
     import torch
     from paper_2607_24959_amd import solver
     R = len(bufs)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    for i in range(steps):
-        t, sol, grads = bufs[i % R]
-        evs[i][0].record()
-        solver.forward(batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=tol,
-                       out=sol, method=method)
-        evs[i][1].record()
-        solver.ift_vjp(batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads)
-        evs[i][2].record()
-    torch.cuda.synchronize()
-    t_fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    t_vjp = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+
+    def graph(fn):
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()   # default priority
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st), torch.cuda.graph(g, stream=st):
+            for i in range(steps):
+                fn(*bufs[i % R])
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        return g, st
+
+    gf, sf = graph(lambda t, sol, grads: solver.forward(
+        batch, t["M"], t["J"], t["a0"], t["aref"], t["D"], max_iter=K, tol=tol, out=sol,
+        method=method))
+    t_fwd = replay_median(gf)[0] / steps
+    gv, sv = graph(lambda t, sol, grads: solver.ift_vjp(
+        batch, sol, t["M"], t["J"], t["a0"], t["aref"], t["D"], t["abar"], out=grads))
+    t_vjp = replay_median(gv)[0] / steps
+    del gf, gv, sf, sv
     return t_fwd, t_vjp
 
 
@@ -550,7 +560,7 @@ def ift_line(bufs, batch, steps, K, tol, schedules=SCHEDULES, s=4, method="newto
     best = min(per, key=lambda k: per[k]["ms_per_step"])
     ms, spread = per[best]["ms_per_step"] * steps, per[best]["replay_spread"]
     t_fwd, t_vjp = kernel_times(bufs, batch, steps, K, tol, method)
-    # the eager pass above left batches 0 .. steps-1 solved at cap K
+    # the forward graph above left batches 0 .. steps-1 solved at cap K
     stats, act, it = solve_stats(bufs[:min(steps, len(bufs))], batch, B, M_ROWS)
     fwd_b, vjp_b = algorithmic_bytes(NV, M_ROWS, s)
     flops = float(np.sum(forward_flops(NV, M_ROWS, act, it)))
@@ -582,7 +592,7 @@ def main():
                     help="skip the converging, FP64, K-sweep, uneven and serving lines")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
-    ap.add_argument("--section", choices=("uneven", "serving"),
+    ap.add_argument("--section", choices=("uneven", "serving", "rollout"),
                     help="only run this workload (for profiling) and print its JSON")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -590,6 +600,9 @@ def main():
     rates = tuple(int(x) for x in args.serve_rates.split(","))
     if args.section == "uneven":
         print(json.dumps(uneven(reps=5)), flush=True)
+        return
+    if args.section == "rollout":
+        print(json.dumps(rollout_line(reps=3)), flush=True)
         return
     if args.section == "serving":
         print(json.dumps(serving(rates, n_requests=args.serve_requests,
@@ -653,8 +666,8 @@ def main():
                            "and host time; one untimed replay first), in the fastest of three "
                            "schedules (one stream; VJPs on a second stream overlapping the next "
                            "forward; two independent chains of batches on two streams); "
-                           "per-kernel durations from an eager sequential pass with HIP events "
-                           "around every launch"},
+                           "per-kernel durations from graphs of the forwards alone and of the VJPs "
+                           "alone (HIP events around the replay, median of replays, / steps)"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
