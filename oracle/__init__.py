@@ -84,6 +84,13 @@ def lib():
                                                 _Opt(_dp), _Opt(_dp), _Opt(_dp), _Opt(_dp),
                                                 _Opt(_dp), i]
         L.oracle_ift_jvp_batch.argtypes = pk + [_dp, _dp, _dp, _u8, i, _Opt(_dp), _Opt(_dp), _dp, i]
+        L.oracle_ell_block.argtypes = [_dp, d, d, d, _dp, _dp, C.POINTER(d)]
+        L.oracle_ell_block.restype = i
+        L.oracle_ell_objective.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_ell_objective.restype = d
+        L.oracle_forward_ell.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8,
+                                         C.POINTER(i), C.POINTER(i)]
+        L.oracle_ift_vjp_ell.argtypes = [i, i] + [_dp] * 16
         L.oracle_forward_cg.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8,
                                         C.POINTER(i), C.POINTER(i)]
         L.oracle_forward_cg_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8, _i32,
@@ -139,6 +146,55 @@ def forward_cg(M, J, a0, aref, D, max_iter=200, tol=1e-10):
     lib().oracle_forward_cg(n, m, M, J, a0, aref, D, max_iter, tol, a, act, C.byref(it),
                             C.byref(st))
     return dict(a=a, active=act[:m].astype(bool), iters=it.value, status=st.value)
+
+
+def ell_block(u, dn, dt, mu):
+    """One contact of the round cone at u (3): (zone, w = ds/du, G = d2s/du2, s)."""
+    u = _f64(u)
+    w = np.empty(3)
+    G = np.empty(9)
+    sv = C.c_double(0.0)
+    z = lib().oracle_ell_block(u, float(dn), float(dt), float(mu), w, G, C.byref(sv))
+    return z, w, G.reshape(3, 3), sv.value
+
+
+def ell_objective(M, J, a0, aref, dn, dt, mu, a):
+    """L(a) and F(a) with the round cone."""
+    M, J, a0, aref, dn, dt, mu, a = map(_f64, (M, J, a0, aref, dn, dt, mu, a))
+    n, nc = a0.shape[0], dn.shape[0]
+    F = np.empty(n)
+    Lv = lib().oracle_ell_objective(n, nc, M, J.reshape(3 * nc, n), a0, aref, dn, dt, mu, a, F)
+    return Lv, F
+
+
+def forward_ell(M, J, a0, aref, dn, dt, mu, max_iter=60, tol=1e-12):
+    """Round-cone forward solve.  Returns dict(a, zone, iters, status)."""
+    M, J, a0, aref, dn, dt, mu = map(_f64, (M, J, a0, aref, dn, dt, mu))
+    n, nc = a0.shape[0], dn.shape[0]
+    a = np.empty(n)
+    zone = np.empty(max(nc, 1), dtype=np.uint8)
+    it, st = C.c_int(0), C.c_int(0)
+    lib().oracle_forward_ell(n, nc, M, J.reshape(3 * nc, n), a0, aref, dn, dt, mu, max_iter, tol,
+                             a, zone, C.byref(it), C.byref(st))
+    return dict(a=a, zone=zone[:nc].copy(), iters=it.value, status=st.value)
+
+
+def ift_vjp_ell(M, J, a0, aref, dn, dt, mu, a, abar):
+    """Round-cone IFT VJP at a.  Returns dict(a0, aref, J, dn, dt, mu, M)."""
+    M, J, a0, aref, dn, dt, mu, a, abar = map(_f64, (M, J, a0, aref, dn, dt, mu, a, abar))
+    n, nc = a0.shape[0], dn.shape[0]
+    m = 3 * nc
+    out = dict(a0=np.empty(n), aref=np.empty(max(m, 1)), J=np.empty(max(m * n, 1)),
+               dn=np.empty(max(nc, 1)), dt=np.empty(max(nc, 1)), mu=np.empty(max(nc, 1)),
+               M=np.empty(n * n))
+    lib().oracle_ift_vjp_ell(n, nc, M, J.reshape(m, n), a0, aref, dn, dt, mu, a, abar, out["a0"],
+                             out["aref"], out["J"], out["dn"], out["dt"], out["mu"], out["M"])
+    out["aref"] = out["aref"][:m]
+    out["J"] = out["J"][:m * n].reshape(m, n)
+    out["M"] = out["M"].reshape(n, n)
+    for k in ("dn", "dt", "mu"):
+        out[k] = out[k][:nc]
+    return out
 
 
 def ift_vjp(M, J, a0, aref, D, a, abar, active=None):

@@ -705,6 +705,304 @@ double oracle_line_search(int n, int m, const double *M, const double *J, const 
 /* packed batches: instance i uses off_*[i]; OpenMP over instances      */
 /* ------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------ */
+/* elliptic (round) Coulomb cone                                        */
+/* ------------------------------------------------------------------ */
+/*
+ * Contact c owns rows 3c (normal), 3c+1, 3c+2 (tangential) of J and aref; its
+ * regularisation weights are R^{-1} = diag(dn, dt, dt) (D = 1/R per row, the
+ * two tangential rows sharing one weight) and its friction coefficient mu
+ * (Sec. III-A, eqs. 2, 3 and 5).  The dual of K = {l_N >= 0, |l_T| <= mu l_N}
+ * is K* = {z_N >= mu |z_T|}, and
+ *   s_c(u) = min over z in K* of 1/2 (u - z)^T R^{-1} (u - z).
+ * In the scaled coordinates x = (sqrt(dn) u_N, sqrt(dt) u_T) the weighted
+ * projection is the Euclidean projection onto the second-order cone
+ * {x_N >= mh |x_T|}, mh = mu sqrt(dn / dt).  With nn = x_N, t = |x_T|:
+ *   zone 0 (inside):  nn >= mh t            s = 0;
+ *   zone 2 (polar):   mh nn + t <= 0        s = 1/2 (nn^2 + t^2)  (all three rows act);
+ *   zone 1 (between): s = 1/2 (mh t - nn)^2 / (1 + mh^2)  (distance to the cone's edge).
+ * ell_block returns s, w = ds/du (3) and G = d^2 s / du^2 (3 x 3, row-major).
+ */
+static int ell_block(const double *u, double dn, double dt, double mu, double *w, double *G,
+                     double *sval) {
+    const double sn = sqrt(dn), st = sqrt(dt), mh = mu * sn / st;
+    const double nn = sn * u[0], x1 = st * u[1], x2 = st * u[2];
+    const double t = sqrt(x1 * x1 + x2 * x2);
+    double gh[3] = {0, 0, 0}, Gh[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, sv = 0.0;
+    int zone;
+    if (nn >= mh * t) {
+        zone = 0;
+    } else if (mh * nn + t <= 0.0) {
+        zone = 2;
+        sv = 0.5 * (nn * nn + t * t);
+        gh[0] = nn; gh[1] = x1; gh[2] = x2;
+        Gh[0] = Gh[4] = Gh[8] = 1.0;
+    } else {
+        zone = 1;   /* t > 0 here */
+        const double k = 1.0 + mh * mh, h = mh * t - nn;
+        const double e[3] = {-1.0, mh * x1 / t, mh * x2 / t};
+        sv = 0.5 * h * h / k;
+        for (int i = 0; i < 3; ++i) gh[i] = h / k * e[i];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Gh[3 * i + j] = e[i] * e[j] / k;
+        /* curvature of t: (I - tau tau^T) / t on the tangential block */
+        const double c = h * mh / (k * t), t1 = x1 / t, t2 = x2 / t;
+        Gh[4] += c * (1.0 - t1 * t1);
+        Gh[5] += c * (-t1 * t2);
+        Gh[7] += c * (-t1 * t2);
+        Gh[8] += c * (1.0 - t2 * t2);
+    }
+    const double S[3] = {sn, st, st};
+    for (int i = 0; i < 3; ++i) {
+        w[i] = S[i] * gh[i];
+        for (int j = 0; j < 3; ++j) G[3 * i + j] = S[i] * Gh[3 * i + j] * S[j];
+    }
+    if (sval) *sval = sv;
+    return zone;
+}
+
+/* F = M (a - a0) + J^T w (eq. 6 with the round cone), the zones and the
+ * contact blocks (w: m values, G: 9 per contact) at a; returns L(a). */
+static double ell_eval(int n, int nc, const double *M, const double *J, const double *a0,
+                       const double *aref, const double *dn, const double *dt, const double *mu,
+                       const double *a, double *u, double *w, double *G, unsigned char *zone,
+                       double *F) {
+    const int m = 3 * nc;
+    double *d = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    matvec(m, n, J, a, u);
+    for (int i = 0; i < m; ++i) u[i] -= aref[i];
+    double Lv = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double sv;
+        zone[c] = (unsigned char)ell_block(u + 3 * c, dn[c], dt[c], mu[c], w + 3 * c, G + 9 * c, &sv);
+        Lv += sv;
+    }
+    matvec(n, n, M, d, F);
+    Lv += 0.5 * dot(n, d, F);
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += J[(size_t)i * n + j] * w[i];
+        F[j] += s;
+    }
+    free(d);
+    return Lv;
+}
+
+/* H = M + sum_c J_c^T G_c J_c (eq. 9 with 3 x 3 blocks) */
+static void ell_assemble_H(int n, int nc, const double *M, const double *J, const double *G,
+                           double *H) {
+    memcpy(H, M, sizeof(double) * (size_t)n * n);
+    for (int c = 0; c < nc; ++c)
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                const double g = G[9 * c + 3 * r + q];
+                if (g == 0.0) continue;
+                const double *Jr = J + (size_t)(3 * c + r) * n, *Jq = J + (size_t)(3 * c + q) * n;
+                for (int j = 0; j < n; ++j)
+                    for (int l = 0; l < n; ++l) H[(size_t)j * n + l] += Jr[j] * g * Jq[l];
+            }
+}
+
+/* Exact line search along p: phi(alpha) = L(a + alpha p) is convex and C^1
+ * (piecewise C^2), so its minimiser is the root of the increasing phi'.  The
+ * root is bracketed (doubling from alpha = 1), then found by Newton steps on
+ * phi' kept inside the bracket (bisection otherwise) until the bracket stops
+ * shrinking. */
+static double ell_line_search(int n, int nc, const double *M, const double *J, const double *a0,
+                              const double *aref, const double *dn, const double *dt,
+                              const double *mu, const double *a, const double *p) {
+    const int m = 3 * nc;
+    int mm = m > 0 ? m : 1;
+    double *u0 = (double *)malloc(sizeof(double) * mm), *q = (double *)malloc(sizeof(double) * mm);
+    double *Mp = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *d = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    matvec(m, n, J, a, u0);
+    for (int i = 0; i < m; ++i) u0[i] -= aref[i];
+    matvec(m, n, J, p, q);
+    matvec(n, n, M, p, Mp);
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    const double c0 = dot(n, p, Mp), b0 = dot(n, Mp, d);
+    /* phi'(al) and phi''(al) */
+    double lo = 0.0, hi = -1.0, al = 1.0;
+    double best = 0.0;
+    for (int it = 0; it < 400; ++it) {
+        double g = c0 * al + b0, h = c0;
+        for (int c = 0; c < nc; ++c) {
+            double uu[3], w[3], G[9];
+            for (int r = 0; r < 3; ++r) uu[r] = u0[3 * c + r] + al * q[3 * c + r];
+            ell_block(uu, dn[c], dt[c], mu[c], w, G, NULL);
+            for (int r = 0; r < 3; ++r) {
+                g += w[r] * q[3 * c + r];
+                for (int s2 = 0; s2 < 3; ++s2) h += q[3 * c + r] * G[3 * r + s2] * q[3 * c + s2];
+            }
+        }
+        best = al;
+        if (g == 0.0) break;
+        if (g < 0.0) lo = al; else hi = al;
+        if (hi >= 0.0 && hi - lo <= 4e-16 * hi) break;
+        double nx = al - g / h;
+        if (!(nx > lo && (hi < 0.0 || nx < hi))) nx = hi < 0.0 ? 2.0 * al : 0.5 * (lo + hi);
+        if (nx == al) break;
+        al = nx;
+    }
+    free(u0); free(q); free(Mp); free(d);
+    return best;
+}
+
+/* Forward solve with the round cone: Newton steps p = -H^{-1} F with the
+ * exact line search; the stopping rule of oracle_forward with the zone
+ * pattern in place of the active set.  Outputs a (n), zone (nc), iters,
+ * status. */
+int oracle_forward_ell(int n, int nc, const double *M, const double *J, const double *a0,
+                       const double *aref, const double *dn, const double *dt, const double *mu,
+                       int max_iter, double tol, double *a, unsigned char *zone, int *iters,
+                       int *status) {
+    const int m = 3 * nc;
+    *iters = 0;
+    if (!all_finite((size_t)n * n, M) || !all_finite((size_t)m * n, J) || !all_finite(n, a0) ||
+        !all_finite(m, aref) || !all_finite(nc, dn) || !all_finite(nc, dt) || !all_finite(nc, mu)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int c = 0; c < nc; ++c) zone[c] = 0;
+        *status = ST_NONFINITE;
+        return 0;
+    }
+    if (!is_spd(n, M)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int c = 0; c < nc; ++c) zone[c] = 0;
+        *status = ST_NOTSPD;
+        return 0;
+    }
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1, nc1 = nc > 0 ? nc : 1;
+    double *u = (double *)malloc(sizeof(double) * mm), *w = (double *)malloc(sizeof(double) * mm);
+    double *G = (double *)malloc(sizeof(double) * 9 * nc1), *F = (double *)malloc(sizeof(double) * n1);
+    double *H = (double *)malloc(sizeof(double) * n1 * n1), *p = (double *)malloc(sizeof(double) * n1);
+    double *mf = (double *)malloc(sizeof(double) * n1);
+    unsigned char *zprev = (unsigned char *)malloc(nc1);
+    for (int j = 0; j < n; ++j) a[j] = a0[j];
+    double step_inf = -1.0;
+    int st = ST_MAXITER;
+    for (int k = 0;; ++k) {
+        if (k > 0) memcpy(zprev, zone, nc);
+        ell_eval(n, nc, M, J, a0, aref, dn, dt, mu, a, u, w, G, zone, F);
+        const int same = k > 0 && (nc == 0 || memcmp(zprev, zone, nc) == 0);
+        if (converged(n, M, F, step_inf, same, a, tol)) { st = ST_CONVERGED; break; }
+        if (k == max_iter) { st = ST_MAXITER; break; }
+        ell_assemble_H(n, nc, M, J, G, H);
+        for (int j = 0; j < n; ++j) mf[j] = -F[j];
+        qr_solve(n, H, mf, p);
+        const double al = ell_line_search(n, nc, M, J, a0, aref, dn, dt, mu, a, p);
+        step_inf = 0.0;
+        for (int j = 0; j < n; ++j) {
+            a[j] += al * p[j];
+            step_inf = fmax(step_inf, fabs(al * p[j]));
+        }
+        *iters = k + 1;
+    }
+    *status = st;
+    free(u); free(w); free(G); free(F); free(H); free(p); free(mf); free(zprev);
+    return 0;
+}
+
+/* IFT VJP with the round cone (eq. 17): H lambda = abar with H = M + sum_c
+ * J_c^T G_c J_c at a; sigma = J lambda;
+ *   a0bar = M^T lambda,  arefbar_c = G_c sigma_c,  Jbar = -(w lambda^T + arefbar a^T),
+ *   Mbar = -lambda (a - a0)^T,  theta_bar = -sigma_c . dw_c/dtheta for theta in
+ *   (dn_c, dt_c, mu_c), dw/dtheta at fixed u (w = S g(S u, mh), S = diag(sqrt dn,
+ *   sqrt dt, sqrt dt), mh = mu sqrt(dn / dt)).  Any output may be NULL. */
+int oracle_ift_vjp_ell(int n, int nc, const double *M, const double *J, const double *a0,
+                       const double *aref, const double *dn, const double *dt, const double *mu,
+                       const double *a, const double *abar, double *a0bar, double *arefbar,
+                       double *Jbar, double *dnbar, double *dtbar, double *mubar, double *Mbar) {
+    const int m = 3 * nc;
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1, nc1 = nc > 0 ? nc : 1;
+    double *u = (double *)malloc(sizeof(double) * mm), *w = (double *)malloc(sizeof(double) * mm);
+    double *G = (double *)malloc(sizeof(double) * 9 * nc1), *F = (double *)malloc(sizeof(double) * n1);
+    double *H = (double *)malloc(sizeof(double) * n1 * n1), *lam = (double *)malloc(sizeof(double) * n1);
+    double *sg = (double *)malloc(sizeof(double) * mm), *ab = (double *)malloc(sizeof(double) * mm);
+    unsigned char *zone = (unsigned char *)malloc(nc1);
+    ell_eval(n, nc, M, J, a0, aref, dn, dt, mu, a, u, w, G, zone, F);
+    ell_assemble_H(n, nc, M, J, G, H);
+    qr_solve(n, H, abar, lam);   /* H is symmetric */
+    matvec(m, n, J, lam, sg);
+    for (int c = 0; c < nc; ++c)
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int q = 0; q < 3; ++q) s += G[9 * c + 3 * r + q] * sg[3 * c + q];
+            ab[3 * c + r] = s;
+        }
+    if (a0bar) matvec_t(n, n, M, lam, a0bar);
+    if (arefbar) memcpy(arefbar, ab, sizeof(double) * m);
+    if (Jbar)
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) Jbar[(size_t)i * n + j] = -(w[i] * lam[j] + ab[i] * a[j]);
+    if (Mbar)
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) Mbar[(size_t)j * n + l] = -lam[j] * (a[l] - a0[l]);
+    for (int c = 0; c < nc; ++c) {
+        /* dw/dtheta at fixed u, theta = (dn, dt, mu) */
+        const double sn = sqrt(dn[c]), st = sqrt(dt[c]), mh = mu[c] * sn / st;
+        const double *uc = u + 3 * c;
+        const double x[3] = {sn * uc[0], st * uc[1], st * uc[2]};
+        double gh[3], Gh[9], S[3] = {sn, st, st};
+        /* g and its Jacobian in scaled coordinates: from the unscaled block */
+        for (int i = 0; i < 3; ++i) {
+            gh[i] = w[3 * c + i] / S[i];
+            for (int j = 0; j < 3; ++j) Gh[3 * i + j] = G[9 * c + 3 * i + j] / (S[i] * S[j]);
+        }
+        double dgm[3] = {0, 0, 0};   /* dg/dmh */
+        if (zone[c] == 1) {
+            const double t = sqrt(x[1] * x[1] + x[2] * x[2]), k = 1.0 + mh * mh, h = mh * t - x[0];
+            const double e[3] = {-1.0, mh * x[1] / t, mh * x[2] / t};
+            const double f = t / k - 2.0 * mh * h / (k * k);
+            dgm[0] = f * e[0];
+            dgm[1] = f * e[1] + h / k * x[1] / t;
+            dgm[2] = f * e[2] + h / k * x[2] / t;
+        }
+        /* theta = dn: dS = diag(1/(2 sn), 0, 0), dmh = mu / (2 sn st)
+         * theta = dt: dS = diag(0, 1/(2 st), 1/(2 st)), dmh = -mu sn / (2 st^3)
+         * theta = mu: dS = 0, dmh = sn / st */
+        double dS[3][3] = {{0.5 / sn, 0, 0}, {0, 0.5 / st, 0.5 / st}, {0, 0, 0}};
+        double dmh[3] = {mu[c] / (2.0 * sn * st), -mu[c] * sn / (2.0 * st * st * st), sn / st};
+        double out[3];
+        for (int th = 0; th < 3; ++th) {
+            double dx[3], dw[3];
+            for (int i = 0; i < 3; ++i) dx[i] = dS[th][i] * uc[i];
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) s += Gh[3 * i + j] * dx[j];
+                dw[i] = dS[th][i] * gh[i] + S[i] * (s + dgm[i] * dmh[th]);
+            }
+            out[th] = -(sg[3 * c] * dw[0] + sg[3 * c + 1] * dw[1] + sg[3 * c + 2] * dw[2]);
+        }
+        if (dnbar) dnbar[c] = out[0];
+        if (dtbar) dtbar[c] = out[1];
+        if (mubar) mubar[c] = out[2];
+    }
+    free(u); free(w); free(G); free(F); free(H); free(lam); free(sg); free(ab); free(zone);
+    return 0;
+}
+
+/* s_c, w_c, G_c and the zone of one contact (for the pins) */
+int oracle_ell_block(const double *u, double dn, double dt, double mu, double *w, double *G,
+                     double *sval) {
+    return ell_block(u, dn, dt, mu, w, G, sval);
+}
+
+/* L(a) with the round cone (for the pins) */
+double oracle_ell_objective(int n, int nc, const double *M, const double *J, const double *a0,
+                            const double *aref, const double *dn, const double *dt,
+                            const double *mu, const double *a, double *F) {
+    const int m = 3 * nc;
+    int mm = m > 0 ? m : 1, nc1 = nc > 0 ? nc : 1;
+    double *u = (double *)malloc(sizeof(double) * mm), *w = (double *)malloc(sizeof(double) * mm);
+    double *G = (double *)malloc(sizeof(double) * 9 * nc1);
+    unsigned char *zone = (unsigned char *)malloc(nc1);
+    const double Lv = ell_eval(n, nc, M, J, a0, aref, dn, dt, mu, a, u, w, G, zone, F);
+    free(u); free(w); free(G); free(zone);
+    return Lv;
+}
+
 static void set_threads(int threads) {
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);

@@ -236,3 +236,64 @@ CONFIGS = {
     # serving: 6-step MPC windows, nv in {3,9,18}, nc ~ U{0..64}
     "serve_mpc6": dict(nv_choices=(3, 9, 18), nc_max=64, window=6),
 }
+
+
+# ------------------------------------------------------------------ round cone
+#
+# Elliptic-cone instances: per contact the three rows J_n, J_t1, J_t2 as drawn
+# above (no pyramid edges), mu_c ~ U[0.5, 1], R_N ~ logU[1e-4, 1e-2] per
+# contact with D_N = 1 / R_N and the tangential weight D_T = D_N (equal normal
+# and frictional impedance), aref = -b J v - k pen on the normal row and -b J v
+# on the tangential rows.  Same PCG64 stream order as uniform_batch with the
+# per-contact R in place of the per-row one.
+
+@dataclass
+class EllipticBatch:
+    n: int
+    nc: int
+    M: np.ndarray      # [B, n, n]
+    J: np.ndarray      # [B, 3 nc, n]: rows (N, T1, T2) per contact
+    a0: np.ndarray
+    aref: np.ndarray   # [B, 3 nc]
+    dn: np.ndarray     # [B, nc]
+    dt: np.ndarray     # [B, nc]
+    mu: np.ndarray     # [B, nc]
+    abar: np.ndarray
+
+    @property
+    def B(self):
+        return self.M.shape[0]
+
+    @property
+    def m(self):
+        return 3 * self.nc
+
+    def astype(self, dtype):
+        kw = {k: getattr(self, k).astype(dtype) for k in
+              ("M", "J", "a0", "aref", "dn", "dt", "mu", "abar")}
+        return EllipticBatch(n=self.n, nc=self.nc, **kw)
+
+    def rounded(self, dtype):
+        return self.astype(dtype).astype(np.float64)
+
+
+def elliptic_batch(B: int, n: int, nc: int, seed: int, a0_var: float = 10.0) -> EllipticBatch:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = rng.standard_normal((B, n, n))
+    sd = math.sqrt(1.0 / n)
+    Jn = rng.normal(0.0, sd, (B, nc, n))
+    Jt1 = rng.normal(0.0, sd, (B, nc, n))
+    Jt2 = rng.normal(0.0, sd, (B, nc, n))
+    mu = rng.uniform(0.5, 1.0, (B, nc))
+    pen = rng.uniform(0.0, 0.01, (B, nc))
+    R = np.exp(rng.uniform(math.log(1e-4), math.log(1e-2), (B, nc)))
+    v = rng.standard_normal((B, n))
+    a0 = rng.normal(0.0, math.sqrt(a0_var), (B, n))
+    abar = rng.standard_normal((B, n))
+    M = np.einsum("bij,bkj->bik", L, L) / n + np.eye(n)[None]
+    J = np.stack([Jn, Jt1, Jt2], axis=-2).reshape(B, 3 * nc, n)
+    pos = np.stack([pen, np.zeros_like(pen), np.zeros_like(pen)], axis=-1).reshape(B, 3 * nc)
+    aref = -B_DAMP * np.einsum("bij,bj->bi", J, v) - K_SPRING * pos
+    return EllipticBatch(n=n, nc=nc, M=np.ascontiguousarray(M), J=np.ascontiguousarray(J),
+                         a0=a0, aref=np.ascontiguousarray(aref), dn=1.0 / R, dt=1.0 / R,
+                         mu=mu, abar=abar)
