@@ -323,6 +323,69 @@ def ilqr_jacobians(reps=20):
                          "unit": "TFLOP/s (FP64 vector)", "frac": flops / (ms / 1e3) / 78.6e12}}
 
 
+def ell_line(steps=20, K=40, tol=1e-5):
+    """The round (elliptic) cone at the headline's shape: B=4096, nv=9, 16
+    contacts (48 rows: normal + two tangential per contact), FP32 storage
+    (FP64 arithmetic), cap K=40 at which every instance converges, forward +
+    IFT VJP; rotating batches over twice the MALL, a graph of `steps` steps,
+    median of replays; per-kernel times from graphs of one kernel kind."""
+    import torch
+    from paper_2607_24959_amd import solver, synth
+    nc, m = NC, 3 * NC
+    batch = solver.Batch.uniform(B, NV, m, torch.float32)
+    per_batch = B * 4 * (NV * NV + m * NV + 2 * NV + m + 3 * nc) + batch.state_bytes()
+    R = max(8, math.ceil(2 * MALL_BYTES / per_batch) + 1)
+    R += R % 2
+    keys = ("M", "J", "a0", "aref", "dn", "dt", "mu")
+    bufs = []
+    for r in range(R):
+        eb = synth.elliptic_batch(B, NV, nc, 20260725 + 500 + r).astype(np.float32)
+        t = {k: torch.from_numpy(np.ascontiguousarray(getattr(eb, k))).cuda()
+             for k in keys + ("abar",)}
+        sol = solver.forward_ell(batch, *(t[k] for k in keys), max_iter=K, tol=tol)
+        gr = solver.ift_vjp_ell(batch, sol, *(t[k] for k in keys), t["abar"])
+        bufs.append((t, sol, gr))
+    torch.cuda.synchronize()
+
+    def fwd(t, sol, gr):
+        solver.forward_ell(batch, *(t[k] for k in keys), max_iter=K, tol=tol, out=sol)
+
+    def vjp(t, sol, gr):
+        solver.ift_vjp_ell(batch, sol, *(t[k] for k in keys), t["abar"], out=gr)
+
+    def graph(fns):
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st), torch.cuda.graph(g, stream=st):
+            for i in range(steps):
+                for fn in fns:
+                    fn(*bufs[i % R])
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        return g, st
+
+    g, st = graph((fwd, vjp))
+    ms, spread = replay_median(g)
+    gf, sf = graph((fwd,))
+    t_f = replay_median(gf)[0] / steps
+    gv, sv = graph((vjp,))
+    t_v = replay_median(gv)[0] / steps
+    stat = np.concatenate([b[1].status.cpu().numpy() for b in bufs[:steps]])
+    its = np.concatenate([b[1].iters.cpu().numpy() for b in bufs[:steps]])
+    z = batch.zones(bufs[0][1])
+    del g, gf, gv, st, sf, sv
+    return {"workload": f"round cone, uniform batch B={B}, nv={NV}, {nc} contacts ({m} rows), "
+                        f"FP32 storage (FP64 arithmetic), cap K={K}, tol {tol}, forward + IFT VJP",
+            "value": B * steps / (ms / 1e3), "unit": "solves/s", "ms_per_step": ms / steps,
+            "replay_spread": spread, "rotating_batches": R,
+            "kernels": {"forward_ms": t_f, "ift_vjp_ms": t_v},
+            "solver": {"converged_frac": float(np.mean((stat & 1) != 0)),
+                       "lsfail_count": int(np.sum((stat & 16) != 0)),
+                       "mean_iters": float(its.mean()), "max_iters": int(its.max()),
+                       "zone_fractions": [float(np.mean(z == k)) for k in (0, 1, 2)]}}
+
+
 def rollout_line(B_=1024, n=18, nc=32, horizon=50, reps=5):
     """The differentiation workload (B=1024, nv=18, 32 contacts, h=0.002,
     horizon 50, FP64, loss ||v_T - v_goal||^2): the gradient w.r.t. tau by
@@ -592,7 +655,7 @@ def main():
                     help="skip the converging, FP64, K-sweep, uneven and serving lines")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
-    ap.add_argument("--section", choices=("uneven", "serving", "rollout"),
+    ap.add_argument("--section", choices=("uneven", "serving", "rollout", "elliptic"),
                     help="only run this workload (for profiling) and print its JSON")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -600,6 +663,9 @@ def main():
     rates = tuple(int(x) for x in args.serve_rates.split(","))
     if args.section == "uneven":
         print(json.dumps(uneven(reps=5)), flush=True)
+        return
+    if args.section == "elliptic":
+        print(json.dumps(ell_line(args.steps)), flush=True)
         return
     if args.section == "rollout":
         print(json.dumps(rollout_line(reps=3)), flush=True)
@@ -744,6 +810,9 @@ def main():
         progress("uneven batch done")
         out["ilqr_jacobians"] = ilqr_jacobians()
         progress("iLQR Jacobians done")
+        out["elliptic"] = ell_line(args.steps)
+        progress(f"round cone: {out['elliptic']['value']:.4g} solves/s, converged "
+                 f"{out['elliptic']['solver']['converged_frac']:.4f}")
         out["rollout"] = rollout_line()
         progress(f"fused rollout: {out['rollout']['fused_ms']:.3g} ms vs layered "
                  f"{out['rollout']['layered_ms']:.3g} ms")

@@ -286,6 +286,41 @@ int cs_rollout(const cs_batch *batch, const cs_rollout_params *params, const voi
                void *workspace, size_t workspace_bytes, int32_t *status, int32_t *iters,
                void *stream);
 
+/* Round (elliptic) Coulomb cone (Sec. III-A, eqs. 2, 3, 5): contact c of an
+ * instance owns rows 3c (normal) and 3c+1, 3c+2 (tangential) of J and aref, so
+ * every instance's row count is a multiple of 3 (a packed instance that is
+ * not gets CS_ST_BADDESC; a uniform batch, CS_EINVAL); dn, dt and mu hold one
+ * value per contact, instance i's at off_m[i] / 3 (uniform: i m / 3):
+ * R^{-1} = diag(dn, dt, dt) > 0 and mu >= 0.  The contact's regulariser is the
+ * R^{-1}-weighted squared distance of u_c = J_c a - aref_c to the dual cone
+ * {z_N >= mu |z_T|}; with x = (sqrt(dn) u_N, sqrt(dt) u_T), mh = mu sqrt(dn/dt),
+ * nn = x_N, t = |x_T| it is 0 where nn >= mh t (zone 0), (nn^2 + t^2) / 2
+ * where mh nn + t <= 0 (zone 2), (mh t - nn)^2 / (2 (1 + mh^2)) otherwise
+ * (zone 1), with closed-form gradient w_c and 3 x 3 Hessian block G_c.
+ * cs_forward_ell: Newton steps with H = M + sum_c J_c^T G_c J_c and the exact
+ * line search (the root of phi', found by safeguarded Newton steps), the
+ * stopping rule of cs_forward with the zone pattern in place of the active set;
+ * params->flags must be 0.  The state layout is cs_forward's: the factor of H
+ * at the returned iterate, then per row one byte, the contact's zone in its
+ * normal row's byte (0 in the tangential rows').  Arithmetic in FP64 for both
+ * dtypes.  n <= 32 and J resident in LDS (within 160 KiB), else
+ * CS_EUNSUPPORTED. */
+int cs_forward_ell(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                   const void *J, const void *a0, const void *aref, const void *dn, const void *dt,
+                   const void *mu, const void *a_init, void *a_out, void *state,
+                   size_t state_bytes, int32_t *status, int32_t *iters, void *stream);
+
+/* IFT VJP with the round cone (eq. 17) at the solution cs_forward_ell returned,
+ * with its zones and factor: H lambda = abar, sigma = J lambda,
+ *   a0bar = M^T lambda, arefbar_c = G_c sigma_c, Jbar = -(w lambda^T + arefbar a^T),
+ *   Mbar = -lambda (a - a0)^T,  (dn, dt, mu)bar_c = -sigma_c . dw_c/d(dn, dt, mu)
+ * (at fixed u_c).  Every output may be NULL.  Layouts as cs_forward_ell. */
+int cs_ift_vjp_ell(const cs_batch *batch, const void *state, size_t state_bytes,
+                   const void *M, const void *J, const void *a0, const void *aref, const void *dn,
+                   const void *dt, const void *mu, const void *a, const void *abar, void *a0bar,
+                   void *arefbar, void *Jbar, void *dnbar, void *dtbar, void *mubar, void *Mbar,
+                   void *stream);
+
 /* Name of an error code. */
 const char *cs_strerror(int code);
 

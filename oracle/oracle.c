@@ -49,6 +49,7 @@
 #define ST_MAXITER 2
 #define ST_NONFINITE 4
 #define ST_NOTSPD 8
+#define ST_LSFAIL 16
 
 /* ------------------------------------------------------------------ */
 /* small dense helpers (row-major)                                      */
@@ -806,12 +807,14 @@ static void ell_assemble_H(int n, int nc, const double *M, const double *J, cons
 
 /* Exact line search along p: phi(alpha) = L(a + alpha p) is convex and C^1
  * (piecewise C^2), so its minimiser is the root of the increasing phi'.  The
- * root is bracketed (doubling from alpha = 1), then found by Newton steps on
- * phi' kept inside the bracket (bisection otherwise) until the bracket stops
- * shrinking. */
+ * root is bracketed by doubling from alpha = 1; then Newton steps on phi' are
+ * taken while they stay inside the bracket and the step before last shrank at
+ * least by half (else the bracket is bisected), until phi' = 0, the bracket is
+ * within rounding of its upper end, or a step no longer moves alpha.  *fail is
+ * set when 200 evaluations do not get there. */
 static double ell_line_search(int n, int nc, const double *M, const double *J, const double *a0,
                               const double *aref, const double *dn, const double *dt,
-                              const double *mu, const double *a, const double *p) {
+                              const double *mu, const double *a, const double *p, int *fail) {
     const int m = 3 * nc;
     int mm = m > 0 ? m : 1;
     double *u0 = (double *)malloc(sizeof(double) * mm), *q = (double *)malloc(sizeof(double) * mm);
@@ -823,10 +826,9 @@ static double ell_line_search(int n, int nc, const double *M, const double *J, c
     matvec(n, n, M, p, Mp);
     for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
     const double c0 = dot(n, p, Mp), b0 = dot(n, Mp, d);
-    /* phi'(al) and phi''(al) */
-    double lo = 0.0, hi = -1.0, al = 1.0;
-    double best = 0.0;
-    for (int it = 0; it < 400; ++it) {
+    double lo = 0.0, hi = -1.0, al = 1.0, best = 1.0, dxold = INFINITY, dx = INFINITY;
+    *fail = 1;
+    for (int it = 0; it < 200; ++it) {
         double g = c0 * al + b0, h = c0;
         for (int c = 0; c < nc; ++c) {
             double uu[3], w[3], G[9];
@@ -838,13 +840,24 @@ static double ell_line_search(int n, int nc, const double *M, const double *J, c
             }
         }
         best = al;
-        if (g == 0.0) break;
+        if (g == 0.0) { *fail = 0; break; }
         if (g < 0.0) lo = al; else hi = al;
-        if (hi >= 0.0 && hi - lo <= 4e-16 * hi) break;
-        double nx = al - g / h;
-        if (!(nx > lo && (hi < 0.0 || nx < hi))) nx = hi < 0.0 ? 2.0 * al : 0.5 * (lo + hi);
-        if (nx == al) break;
-        al = nx;
+        if (hi < 0.0) {   /* no upper end yet */
+            al *= 2.0;
+            continue;
+        }
+        if (hi - lo <= 4e-16 * hi) { *fail = 0; break; }
+        const double nx = al - g / h;
+        double step;
+        if (nx > lo && nx < hi && fabs(nx - al) < 0.5 * fabs(dxold)) {
+            step = nx - al;
+        } else {
+            step = 0.5 * (lo + hi) - al;
+        }
+        dxold = dx;
+        dx = step;
+        if (al + step == al) { *fail = 0; break; }
+        al += step;
     }
     free(u0); free(q); free(Mp); free(d);
     return best;
@@ -881,7 +894,7 @@ int oracle_forward_ell(int n, int nc, const double *M, const double *J, const do
     unsigned char *zprev = (unsigned char *)malloc(nc1);
     for (int j = 0; j < n; ++j) a[j] = a0[j];
     double step_inf = -1.0;
-    int st = ST_MAXITER;
+    int st = ST_MAXITER, lsfail = 0;
     for (int k = 0;; ++k) {
         if (k > 0) memcpy(zprev, zone, nc);
         ell_eval(n, nc, M, J, a0, aref, dn, dt, mu, a, u, w, G, zone, F);
@@ -891,7 +904,9 @@ int oracle_forward_ell(int n, int nc, const double *M, const double *J, const do
         ell_assemble_H(n, nc, M, J, G, H);
         for (int j = 0; j < n; ++j) mf[j] = -F[j];
         qr_solve(n, H, mf, p);
-        const double al = ell_line_search(n, nc, M, J, a0, aref, dn, dt, mu, a, p);
+        int fl = 0;
+        const double al = ell_line_search(n, nc, M, J, a0, aref, dn, dt, mu, a, p, &fl);
+        lsfail |= fl;
         step_inf = 0.0;
         for (int j = 0; j < n; ++j) {
             a[j] += al * p[j];
@@ -899,7 +914,7 @@ int oracle_forward_ell(int n, int nc, const double *M, const double *J, const do
         }
         *iters = k + 1;
     }
-    *status = st;
+    *status = st | (lsfail ? ST_LSFAIL : 0);
     free(u); free(w); free(G); free(F); free(H); free(p); free(mf); free(zprev);
     return 0;
 }

@@ -22,7 +22,8 @@ UNROLLED_RECORD, UNROLLED_REPLAY, FORWARD_CG = 1, 2, 4
 ROLLOUT_FORWARD, ROLLOUT_BACKWARD, ROLLOUT_RECOMPUTE = 1, 2, 4
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static",
-            "cs_rollout", "cs_rollout_workspace_bytes", "cs_state_bytes",
+            "cs_rollout", "cs_rollout_workspace_bytes", "cs_forward_ell", "cs_ift_vjp_ell",
+            "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
             "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
 
@@ -100,6 +101,10 @@ def lib():
         L.cs_ift_vjp.argtypes = [pb, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.cs_ift_jvp.restype = C.c_int
         L.cs_ift_jvp.argtypes = [pb, vp, sz, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.cs_forward_ell.restype = C.c_int
+        L.cs_forward_ell.argtypes = [pb, pp] + [vp] * 10 + [sz, vp, vp, vp]
+        L.cs_ift_vjp_ell.restype = C.c_int
+        L.cs_ift_vjp_ell.argtypes = [pb, vp, sz] + [vp] * 17
         prp = C.POINTER(CsRolloutParams)
         L.cs_rollout_workspace_bytes.restype = sz
         L.cs_rollout_workspace_bytes.argtypes = [pb, prp]
@@ -160,6 +165,18 @@ def ift_vjp(batch, state, state_nbytes, M, J, a0, aref, D, a, abar, a0bar, arefb
 def ift_jvp(batch, state, state_nbytes, M, J, D, k, da0, daref, da, stream):
     return lib().cs_ift_jvp(C.byref(batch), state, state_nbytes, M, J, D, int(k), da0, daref, da,
                             stream)
+
+
+def forward_ell(batch, params, M, J, a0, aref, dn, dt, mu, a_init, a_out, state, state_nbytes,
+                status, iters, stream):
+    return lib().cs_forward_ell(C.byref(batch), C.byref(params), M, J, a0, aref, dn, dt, mu, a_init,
+                                a_out, state, state_nbytes, status, iters, stream)
+
+
+def ift_vjp_ell(batch, state, state_nbytes, M, J, a0, aref, dn, dt, mu, a, abar, a0bar, arefbar,
+                Jbar, dnbar, dtbar, mubar, Mbar, stream):
+    return lib().cs_ift_vjp_ell(C.byref(batch), state, state_nbytes, M, J, a0, aref, dn, dt, mu, a,
+                                abar, a0bar, arefbar, Jbar, dnbar, dtbar, mubar, Mbar, stream)
 
 
 def rollout_workspace_bytes(batch, params):

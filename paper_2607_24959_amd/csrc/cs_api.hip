@@ -14,6 +14,7 @@
 #include "cs_generic.hpp"
 #include "cs_jvp.hpp"
 #include "cs_rollout.hpp"
+#include "cs_ell.hpp"
 #include "cs_small.hpp"
 #include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
@@ -534,6 +535,91 @@ int cs_ift_jvp(const cs_batch *batch, const void *state, size_t state_bytes_give
                                        static_cast<const double *>(state), mask,
                                        (const double *)M, (const double *)J, (const double *)D,
                                        (const double *)da0, (const double *)daref, (double *)da, s);
+    return r == 0 ? CS_OK : CS_EHIP;
+}
+
+int cs_forward_ell(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                   const void *J, const void *a0, const void *aref, const void *dn, const void *dt,
+                   const void *mu, const void *a_init, void *a_out, void *state,
+                   size_t state_bytes_given, int32_t *status, int32_t *iters, void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = check_params(params)) != CS_OK) return rc;
+    if (params->flags != 0) return CS_EINVAL;
+    if (!hb.packed && batch->nrows_uniform % 3 != 0) return CS_EINVAL;
+    if (hb.B == 0) return CS_OK;
+    if (!M || !a0 || !a_out || !state || !status) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !dn || !dt || !mu)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    if (!cs::ell_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
+    auto go = [&](auto tag) {
+        typedef decltype(tag) T;
+        cs::ElArgs<T> g = {};
+        g.M = (const T *)M;
+        g.J = (const T *)J;
+        g.a0 = (const T *)a0;
+        g.aref = (const T *)aref;
+        g.dn = (const T *)dn;
+        g.dt = (const T *)dt;
+        g.mu = (const T *)mu;
+        g.ainit = (const T *)a_init;
+        g.aout = (T *)a_out;
+        g.fac = (T *)state;
+        g.mask = mask;
+        g.status = status;
+        g.iters = iters;
+        g.max_iter = params->max_iter;
+        g.tol = params->tol;
+        return cs::launch_ell<T>(false, hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, s);
+    };
+    const int r = hb.dtype == CS_F32 ? go(float()) : go(double());
+    return r == 0 ? CS_OK : CS_EHIP;
+}
+
+int cs_ift_vjp_ell(const cs_batch *batch, const void *state, size_t state_bytes_given,
+                   const void *M, const void *J, const void *a0, const void *aref, const void *dn,
+                   const void *dt, const void *mu, const void *a, const void *abar, void *a0bar,
+                   void *arefbar, void *Jbar, void *dnbar, void *dtbar, void *mubar, void *Mbar,
+                   void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if (!hb.packed && batch->nrows_uniform % 3 != 0) return CS_EINVAL;
+    if (hb.B == 0) return CS_OK;
+    if (!state || !M || !a0 || !a || !abar) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !dn || !dt || !mu)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    if (!cs::ell_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *mask = static_cast<uint8_t *>(const_cast<void *>(state)) +
+                    align256(hb.s * factor_elems(hb));
+    auto go = [&](auto tag) {
+        typedef decltype(tag) T;
+        cs::ElArgs<T> g = {};
+        g.M = (const T *)M;
+        g.J = (const T *)J;
+        g.a0 = (const T *)a0;
+        g.aref = (const T *)aref;
+        g.dn = (const T *)dn;
+        g.dt = (const T *)dt;
+        g.mu = (const T *)mu;
+        g.a = (const T *)a;
+        g.abar = (const T *)abar;
+        g.fac = (T *)const_cast<void *>(state);
+        g.mask = mask;
+        g.a0bar = (T *)a0bar;
+        g.arefbar = (T *)arefbar;
+        g.Jbar = (T *)Jbar;
+        g.dnbar = (T *)dnbar;
+        g.dtbar = (T *)dtbar;
+        g.mubar = (T *)mubar;
+        g.Mbar = (T *)Mbar;
+        return cs::launch_ell<T>(true, hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, s);
+    };
+    const int r = hb.dtype == CS_F32 ? go(float()) : go(double());
     return r == 0 ? CS_OK : CS_EHIP;
 }
 

@@ -116,6 +116,12 @@ class Batch:
         o = self.mask_offset()
         return sol.state[o:o + self.total_m].cpu().numpy().astype(bool)
 
+    def zones(self, sol) -> np.ndarray:
+        """Round cone: each contact's zone (0, 1, 2) from the state written by
+        cs_forward_ell (host copy, flat, off_m / 3 layout)."""
+        o = self.mask_offset()
+        return sol.state[o:o + self.total_m].cpu().numpy()[0::3].copy()
+
     def tape_bytes(self, K: int) -> int:
         return N.tape_bytes(self.desc, K)
 
@@ -187,6 +193,49 @@ def ift_vjp(batch: Batch, sol: Solution, M, J, a0, aref, D, abar,
                    _vp(aref), _vp(D), _vp(sol.a), _vp(abar), *(_vp(t) for t in out),
                    _stream(a0.device))
     N.check(rc, "cs_ift_vjp")
+    return out
+
+
+def forward_ell(batch: Batch, M, J, a0, aref, dn, dt, mu, *, max_iter=60, tol=1e-5,
+                a_init=None, out: Optional[Solution] = None) -> Solution:
+    """Round-cone forward solve (cs_forward_ell): rows (N, T1, T2) per contact,
+    dn, dt, mu one value per contact (total_m / 3 each)."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref)):
+        batch.check(name, t, s[name])
+    ncon = s["aref"] // 3
+    for name, t in (("dn", dn), ("dt", dt), ("mu", mu)):
+        batch.check(name, t, ncon)
+    batch.check("a_init", a_init, s["a0"], required=False)
+    if out is None:
+        out = Solution(
+            a=torch.empty_like(a0),
+            state=torch.empty(max(batch.state_bytes(), 1), dtype=torch.uint8, device=a0.device),
+            status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
+            iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device))
+    p = N.CsSolverParams(int(max_iter), 0, float(tol))
+    rc = N.forward_ell(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(dn), _vp(dt), _vp(mu),
+                       _vp(a_init), _vp(out.a), _vp(out.state), out.state.numel(), _vp(out.status),
+                       _vp(out.iters), _stream(a0.device))
+    N.check(rc, "cs_forward_ell")
+    return out
+
+
+def ift_vjp_ell(batch: Batch, sol: Solution, M, J, a0, aref, dn, dt, mu, abar, out=None):
+    """Round-cone IFT VJP (cs_ift_vjp_ell).  Returns dict(a0, aref, J, dn, dt, mu, M)
+    (`out`, when given, is filled and returned)."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("abar", abar)):
+        batch.check(name, t, s[name])
+    if out is None:
+        out = dict(a0=torch.empty_like(a0), aref=torch.empty_like(aref), J=torch.empty_like(J),
+                   dn=torch.empty_like(dn), dt=torch.empty_like(dt), mu=torch.empty_like(mu),
+                   M=torch.empty_like(M))
+    rc = N.ift_vjp_ell(batch.desc, _vp(sol.state), sol.state.numel(), _vp(M), _vp(J), _vp(a0),
+                       _vp(aref), _vp(dn), _vp(dt), _vp(mu), _vp(sol.a), _vp(abar), _vp(out["a0"]),
+                       _vp(out["aref"]), _vp(out["J"]), _vp(out["dn"]), _vp(out["dt"]),
+                       _vp(out["mu"]), _vp(out["M"]), _stream(a0.device))
+    N.check(rc, "cs_ift_vjp_ell")
     return out
 
 

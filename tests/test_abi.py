@@ -170,3 +170,19 @@ def test_rollout_workspace_and_argument_validation():
     rc = N.rollout(b.desc, P(3, 1), None, None, None, None, None, None, None, None, None, None,
                    None, ws, 1 << 20, None, None, None)
     assert rc == N.CS_EINVAL
+
+
+def test_round_cone_entry_points_validate_before_launch():
+    """Rows not a multiple of 3 in a uniform batch, flags != 0 and missing
+    pointers are CS_EINVAL; a short state buffer is CS_ENOSPC -- all before any
+    launch."""
+    b = solver.Batch.uniform(4, 6, 10, torch.float64, device="cpu")
+    p = N.CsSolverParams(10, 0, 1e-10)
+    one = C.c_void_p(1)
+    assert N.forward_ell(b.desc, p, *([one] * 10), 1 << 20, one, None, None) == N.CS_EINVAL
+    b3 = solver.Batch.uniform(4, 6, 12, torch.float64, device="cpu")
+    assert N.forward_ell(b3.desc, N.CsSolverParams(10, 4, 1e-10), *([one] * 10), 1 << 20, one,
+                         None, None) == N.CS_EINVAL
+    assert N.forward_ell(b3.desc, p, None, *([one] * 9), 1 << 20, one, None, None) == N.CS_EINVAL
+    assert N.forward_ell(b3.desc, p, *([one] * 10), 16, one, None, None) == N.CS_ENOSPC
+    assert N.ift_vjp_ell(b.desc, one, 1 << 20, *([one] * 9), *([None] * 7), None) == N.CS_EINVAL
