@@ -806,12 +806,15 @@ static void ell_assemble_H(int n, int nc, const double *M, const double *J, cons
 }
 
 /* Exact line search along p: phi(alpha) = L(a + alpha p) is convex and C^1
- * (piecewise C^2), so its minimiser is the root of the increasing phi'.  The
- * root is bracketed by doubling from alpha = 1; then Newton steps on phi' are
- * taken while they stay inside the bracket and the step before last shrank at
- * least by half (else the bracket is bisected), until phi' = 0, the bracket is
- * within rounding of its upper end, or a step no longer moves alpha.  *fail is
- * set when 200 evaluations do not get there. */
+ * (piecewise C^2), so its minimiser is the root of the increasing phi'.  From
+ * alpha = 1: Newton steps on phi' while no upper end of the bracket is known;
+ * then Newton steps that stay inside the bracket and at least halve the step
+ * before last, else a secant step on the bracket's ends (bisection instead
+ * when the bracket is not at most half as wide as two evaluations before, or
+ * the secant point falls outside); until
+ * phi' = 0, |phi'| is at its rounding level (1e-13 of the sum of its terms'
+ * magnitudes), the bracket is within rounding of its upper end, or a step no
+ * longer moves alpha.  *fail is set when 100 evaluations do not get there. */
 static double ell_line_search(int n, int nc, const double *M, const double *J, const double *a0,
                               const double *aref, const double *dn, const double *dt,
                               const double *mu, const double *a, const double *p, int *fail) {
@@ -826,38 +829,52 @@ static double ell_line_search(int n, int nc, const double *M, const double *J, c
     matvec(n, n, M, p, Mp);
     for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
     const double c0 = dot(n, p, Mp), b0 = dot(n, Mp, d);
-    double lo = 0.0, hi = -1.0, al = 1.0, best = 1.0, dxold = INFINITY, dx = INFINITY;
+    /* phi'(0) from the blocks at u0 */
+    double glo = b0;
+    for (int c = 0; c < nc; ++c) {
+        double w[3], G[9];
+        ell_block(u0 + 3 * c, dn[c], dt[c], mu[c], w, G, NULL);
+        for (int r = 0; r < 3; ++r) glo += w[r] * q[3 * c + r];
+    }
+    double lo = 0.0, hi = -1.0, ghi = 0.0, al = 1.0, best = 1.0, dxold = INFINITY, dx = INFINITY;
+    double wid1 = INFINITY, wid2 = INFINITY;
     *fail = 1;
-    for (int it = 0; it < 200; ++it) {
-        double g = c0 * al + b0, h = c0;
+    for (int it = 0; it < 100; ++it) {
+        double g = c0 * al + b0, h = c0, sabs = fabs(c0 * al) + fabs(b0);
         for (int c = 0; c < nc; ++c) {
             double uu[3], w[3], G[9];
             for (int r = 0; r < 3; ++r) uu[r] = u0[3 * c + r] + al * q[3 * c + r];
             ell_block(uu, dn[c], dt[c], mu[c], w, G, NULL);
+            double wq = 0.0;
             for (int r = 0; r < 3; ++r) {
-                g += w[r] * q[3 * c + r];
+                wq += w[r] * q[3 * c + r];
                 for (int s2 = 0; s2 < 3; ++s2) h += q[3 * c + r] * G[3 * r + s2] * q[3 * c + s2];
             }
+            g += wq;
+            sabs += fabs(wq);
         }
         best = al;
         if (g == 0.0) { *fail = 0; break; }
-        if (g < 0.0) lo = al; else hi = al;
-        if (hi < 0.0) {   /* no upper end yet */
-            al *= 2.0;
-            continue;
-        }
-        if (hi - lo <= 4e-16 * hi) { *fail = 0; break; }
-        const double nx = al - g / h;
-        double step;
-        if (nx > lo && nx < hi && fabs(nx - al) < 0.5 * fabs(dxold)) {
-            step = nx - al;
+        if (g < 0.0) { lo = al; glo = g; } else { hi = al; ghi = g; }
+        if (fabs(g) <= 1e-13 * sabs) { *fail = 0; break; }
+        double nx = al - g / h;
+        if (hi < 0.0) {
+            if (!(nx > al)) nx = 2.0 * al;
         } else {
-            step = 0.5 * (lo + hi) - al;
+            const double wid = hi - lo;
+            if (wid <= 4e-16 * hi) { *fail = 0; break; }
+            const int slow = wid > 0.5 * wid2;
+            wid2 = wid1;
+            wid1 = wid;
+            if (!(nx > lo && nx < hi && fabs(nx - al) < 0.5 * fabs(dxold))) {
+                nx = lo - glo * (hi - lo) / (ghi - glo);
+                if (slow || !(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+            }
         }
         dxold = dx;
-        dx = step;
-        if (al + step == al) { *fail = 0; break; }
-        al += step;
+        dx = nx - al;
+        if (nx == al) { *fail = 0; break; }
+        al = nx;
     }
     free(u0); free(q); free(Mp); free(d);
     return best;

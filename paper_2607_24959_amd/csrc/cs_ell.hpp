@@ -35,7 +35,7 @@ constexpr int EL_NMAX = 32;
 
 struct ElLayout {
     int ldj;
-    uint32_t J, M, H, dh, vec, rows, K, con, G, list, zone, red, wk, bytes;
+    uint32_t J, M, H, dh, vec, rows, K, con, pre, G, list, zone, red, wk, bytes;
 };
 
 __host__ __device__ inline ElLayout el_layout(int nmax, int mmax, int s) {
@@ -56,6 +56,7 @@ __host__ __device__ inline ElLayout el_layout(int nmax, int mmax, int s) {
     L.rows = take(8ull * 4 * mm);
     L.K = take(8ull * mm * nmax);
     L.con = take(8ull * 3 * nc);
+    L.pre = take(8ull * 4 * nc);
     L.G = take(8ull * 6 * nc);
     L.list = take(4ull * nc);
     L.zone = take(nc);
@@ -65,11 +66,26 @@ __host__ __device__ inline ElLayout el_layout(int nmax, int mmax, int s) {
     return L;
 }
 
+// A contact's constants: sqrt(dn), sqrt(dt), mh = mu sqrt(dn / dt) and
+// 1 / (1 + mh^2), formed once per solve.
+struct ElCon {
+    double sn, st, mh, ik;
+};
+
+__device__ inline ElCon el_con(double dn, double dt, double mu) {
+    ElCon k;
+    k.sn = sqrt(dn);
+    k.st = sqrt(dt);
+    k.mh = mu * k.sn / k.st;
+    k.ik = 1.0 / (1.0 + k.mh * k.mh);
+    return k;
+}
+
 // One contact: zone, w = ds/du (3) and G (upper triangle 00 01 02 11 12 22).
 // `force_zone` >= 0 evaluates that zone's formulas instead of classifying.
-__device__ inline int el_block(const double (&u)[3], double dn, double dt, double mu,
-                               double (&w)[3], double (&G)[6], int force_zone = -1) {
-    const double sn = sqrt(dn), st = sqrt(dt), mh = mu * sn / st;
+__device__ inline int el_block(const double (&u)[3], const ElCon &K, double (&w)[3],
+                               double (&G)[6], int force_zone = -1) {
+    const double sn = K.sn, st = K.st, mh = K.mh;
     const double nn = sn * u[0], x1 = st * u[1], x2 = st * u[2];
     const double t = sqrt(x1 * x1 + x2 * x2);
     int zone = force_zone;
@@ -81,13 +97,13 @@ __device__ inline int el_block(const double (&u)[3], double dn, double dt, doubl
         g2 = x2;
         h00 = h11 = h22 = 1.0;
     } else if (zone == 1 && t > 0.0) {
-        const double k = 1.0 + mh * mh, h = mh * t - nn, ik = 1.0 / k;
-        const double t1 = x1 / t, t2 = x2 / t;
+        const double ik = K.ik, h = mh * t - nn, it = 1.0 / t;
+        const double t1 = x1 * it, t2 = x2 * it;
         const double e0 = -1.0, e1 = mh * t1, e2 = mh * t2;
         g0 = h * ik * e0;
         g1 = h * ik * e1;
         g2 = h * ik * e2;
-        const double c = h * mh * ik / t;
+        const double c = h * mh * ik * it;
         h00 = e0 * e0 * ik;
         h01 = e0 * e1 * ik;
         h02 = e0 * e2 * ik;
@@ -128,6 +144,7 @@ template <typename T>
 struct ElCtx {
     T *Js;
     double *Ms, *H, *dh, *vec, *rows, *K, *con, *G, *red, *wk;
+    ElCon *pre;
     int *list;
     uint8_t *zone;
     int ldj, n, m, nc;
@@ -145,6 +162,7 @@ __device__ inline ElCtx<T> el_carve(unsigned char *smem, int nmax, int mmax) {
     c.rows = reinterpret_cast<double *>(smem + Lo.rows);
     c.K = reinterpret_cast<double *>(smem + Lo.K);
     c.con = reinterpret_cast<double *>(smem + Lo.con);
+    c.pre = reinterpret_cast<ElCon *>(smem + Lo.pre);
     c.G = reinterpret_cast<double *>(smem + Lo.G);
     c.list = reinterpret_cast<int *>(smem + Lo.list);
     c.zone = smem + Lo.zone;
@@ -226,6 +244,7 @@ __device__ inline bool el_load(const ElCtx<T> &X, const Inst &I, const T *gM, co
         X.con[3 * c] = double(d1);
         X.con[3 * c + 1] = double(d2);
         X.con[3 * c + 2] = double(f);
+        X.pre[c] = el_con(double(d1), double(d2), double(f));
         bad |= !finite_val(d1) || !finite_val(d2) || !finite_val(f) || !(d1 > T(0)) ||
                !(d2 > T(0)) || f < T(0);
     }
@@ -290,7 +309,7 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                 for (int c = tid; c < nc; c += EL_NT) {
                     const double uc[3] = {u[3 * c], u[3 * c + 1], u[3 * c + 2]};
                     double wc[3], Gc[6];
-                    const int z = el_block(uc, X.con[3 * c], X.con[3 * c + 1], X.con[3 * c + 2], wc, Gc);
+                    const int z = el_block(uc, X.pre[c], wc, Gc);
                     changed |= z != X.zone[c];
                     X.zone[c] = (uint8_t)z;
                     w[3 * c] = wc[0];
@@ -364,43 +383,63 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                     c0 += p[j] * Mp[j];
                     b0 += p[j] * md[j];
                 }
-                // exact line search: the root of phi', bracketed by doubling from
-                // alpha = 1, then Newton steps while they stay inside the bracket
-                // and the step before last shrank at least by half, else bisection
-                double lo = 0.0, hi = -1.0, al = 1.0, best = 1.0, dxold = inf_val<double>(),
-                       dx = inf_val<double>();
+                // exact line search: the root of phi' (the rule of the oracle's
+                // line search): Newton steps while no upper end is known, then
+                // Newton steps inside the bracket that at least halve the step
+                // before last, else a secant step on the bracket, else (the
+                // bracket not halved in two evaluations, or the secant point
+                // outside) bisection
+                double glo;
+                {
+                    double v1[1] = {0.0};
+                    for (int i = tid; i < m; i += EL_NT) v1[0] += w[i] * q[i];
+                    team_sum<EL_NT>(v1, X.red);
+                    glo = b0 + v1[0];
+                }
+                double lo = 0.0, hi = -1.0, ghi = 0.0, al = 1.0, best = 1.0,
+                       dxold = inf_val<double>(), dx = inf_val<double>(),
+                       wid1 = inf_val<double>(), wid2 = inf_val<double>();
                 int fl = 1;
-                for (int it = 0; it < 200; ++it) {
-                    double v2[2] = {0.0, 0.0};
+                for (int it = 0; it < 100; ++it) {
+                    double v3[3] = {0.0, 0.0, 0.0};
                     for (int c = tid; c < nc; c += EL_NT) {
                         const double uc[3] = {u[3 * c] + al * q[3 * c], u[3 * c + 1] + al * q[3 * c + 1],
                                               u[3 * c + 2] + al * q[3 * c + 2]};
                         double wc[3], Gc[6];
-                        el_block(uc, X.con[3 * c], X.con[3 * c + 1], X.con[3 * c + 2], wc, Gc);
+                        el_block(uc, X.pre[c], wc, Gc);
                         const double q0 = q[3 * c], q1 = q[3 * c + 1], q2 = q[3 * c + 2];
-                        v2[0] += wc[0] * q0 + wc[1] * q1 + wc[2] * q2;
-                        v2[1] += q0 * (Gc[0] * q0 + Gc[1] * q1 + Gc[2] * q2) +
+                        const double wq = wc[0] * q0 + wc[1] * q1 + wc[2] * q2;
+                        v3[0] += wq;
+                        v3[1] += q0 * (Gc[0] * q0 + Gc[1] * q1 + Gc[2] * q2) +
                                  q1 * (Gc[1] * q0 + Gc[3] * q1 + Gc[4] * q2) +
                                  q2 * (Gc[2] * q0 + Gc[4] * q1 + Gc[5] * q2);
+                        v3[2] += fabs(wq);
                     }
-                    team_sum<EL_NT>(v2, X.red);
-                    const double gv = c0 * al + b0 + v2[0], hv = c0 + v2[1];
+                    team_sum<EL_NT>(v3, X.red);
+                    const double gv = c0 * al + b0 + v3[0], hv = c0 + v3[1];
+                    const double sabs = fabs(c0 * al) + fabs(b0) + v3[2];
                     best = al;
                     if (gv == 0.0) { fl = 0; break; }
-                    if (gv < 0.0) lo = al; else hi = al;
-                    if (hi < 0.0) {   // no upper end yet
-                        al *= 2.0;
-                        continue;
+                    if (gv < 0.0) { lo = al; glo = gv; } else { hi = al; ghi = gv; }
+                    if (fabs(gv) <= 1e-13 * sabs) { fl = 0; break; }
+                    double nx = al - gv / hv;
+                    if (hi < 0.0) {
+                        if (!(nx > al)) nx = 2.0 * al;
+                    } else {
+                        const double wid = hi - lo;
+                        if (wid <= 4e-16 * hi) { fl = 0; break; }
+                        const bool slow = wid > 0.5 * wid2;
+                        wid2 = wid1;
+                        wid1 = wid;
+                        if (!(nx > lo && nx < hi && fabs(nx - al) < 0.5 * fabs(dxold))) {
+                            nx = lo - glo * (hi - lo) / (ghi - glo);
+                            if (slow || !(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+                        }
                     }
-                    if (hi - lo <= 4e-16 * hi) { fl = 0; break; }
-                    const double nx = al - gv / hv;
-                    const double step = (nx > lo && nx < hi && fabs(nx - al) < 0.5 * fabs(dxold))
-                                            ? nx - al
-                                            : 0.5 * (lo + hi) - al;
                     dxold = dx;
-                    dx = step;
-                    if (al + step == al) { fl = 0; break; }
-                    al += step;
+                    dx = nx - al;
+                    if (nx == al) { fl = 0; break; }
+                    al = nx;
                 }
                 lsfail |= fl;
                 step_inf = 0.0;
@@ -480,7 +519,7 @@ __global__ __launch_bounds__(EL_NT) void k_ift_vjp_ell(BatchView bv, int count, 
         for (int c = tid; c < nc; c += EL_NT) {
             const double uc[3] = {u[3 * c], u[3 * c + 1], u[3 * c + 2]};
             double wc[3], Gc[6];
-            el_block(uc, X.con[3 * c], X.con[3 * c + 1], X.con[3 * c + 2], wc, Gc, X.zone[c]);
+            el_block(uc, X.pre[c], wc, Gc, X.zone[c]);
             w[3 * c] = wc[0];
             w[3 * c + 1] = wc[1];
             w[3 * c + 2] = wc[2];
