@@ -91,6 +91,10 @@ def lib():
         L.oracle_forward_ell.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8,
                                          C.POINTER(i), C.POINTER(i)]
         L.oracle_ift_vjp_ell.argtypes = [i, i] + [_dp] * 16
+        L.oracle_forward_rows.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _u8, _dp, i, d, _dp, _u8,
+                                          C.POINTER(i), C.POINTER(i)]
+        L.oracle_ift_vjp_rows.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, _u8, _dp, _dp, _dp] + \
+            [_dp] * 6
         L.oracle_forward_cg.argtypes = [i, i, _dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8,
                                         C.POINTER(i), C.POINTER(i)]
         L.oracle_forward_cg_batch.argtypes = pk + [_dp, _dp, _dp, _dp, _dp, i, d, _dp, _u8, _i32,
@@ -194,6 +198,38 @@ def ift_vjp_ell(M, J, a0, aref, dn, dt, mu, a, abar):
     out["M"] = out["M"].reshape(n, n)
     for k in ("dn", "dt", "mu"):
         out[k] = out[k][:nc]
+    return out
+
+
+def forward_rows(M, J, a0, aref, D, kind, floss, max_iter=60, tol=1e-12):
+    """Mixed rows (kind 0 one-sided, 1 equality, 2 friction loss with bound floss).
+    Returns dict(a, zone, iters, status); zone per row: 0 no force, 1 quadratic,
+    2 / 3 saturated at +f / -f."""
+    M, J, a0, aref, D, floss = map(_f64, (M, J, a0, aref, D, floss))
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    n, m = a0.shape[0], aref.shape[0]
+    a = np.empty(n)
+    zone = np.empty(max(m, 1), dtype=np.uint8)
+    it, st = C.c_int(0), C.c_int(0)
+    lib().oracle_forward_rows(n, m, M, J.reshape(m, n) if m else np.zeros((1, n)), a0, aref, D,
+                              kind if m else np.zeros(1, np.uint8), floss, max_iter, tol, a, zone,
+                              C.byref(it), C.byref(st))
+    return dict(a=a, zone=zone[:m].copy(), iters=it.value, status=st.value)
+
+
+def ift_vjp_rows(M, J, a0, aref, D, kind, floss, a, abar):
+    """Mixed-row IFT VJP at a.  Returns dict(a0, aref, J, D, floss, M)."""
+    M, J, a0, aref, D, floss, a, abar = map(_f64, (M, J, a0, aref, D, floss, a, abar))
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    n, m = a0.shape[0], aref.shape[0]
+    out = dict(a0=np.empty(n), aref=np.empty(max(m, 1)), J=np.empty(max(m * n, 1)),
+               D=np.empty(max(m, 1)), floss=np.empty(max(m, 1)), M=np.empty(n * n))
+    lib().oracle_ift_vjp_rows(n, m, M, J.reshape(m, n), a0, aref, D, kind, floss, a, abar,
+                              out["a0"], out["aref"], out["J"], out["D"], out["floss"], out["M"])
+    out["J"] = out["J"][:m * n].reshape(m, n)
+    out["M"] = out["M"].reshape(n, n)
+    for k in ("aref", "D", "floss"):
+        out[k] = out[k][:m]
     return out
 
 

@@ -1035,6 +1035,211 @@ double oracle_ell_objective(int n, int nc, const double *M, const double *J, con
     return Lv;
 }
 
+/* ------------------------------------------------------------------ */
+/* mixed regularised rows: one-sided, equality, friction loss           */
+/* ------------------------------------------------------------------ */
+/*
+ * Row i has a kind (Sec. III-A: the frictional block and "other regularised
+ * constraint rows"):
+ *   0  one-sided (a pyramid edge or a limit):  s_i = 1/2 D_i min(r_i, 0)^2;
+ *   1  equality:                               s_i = 1/2 D_i r_i^2;
+ *   2  friction loss with bound f_i >= 0 (its force saturates at +-f_i):
+ *      s_i = 1/2 D_i r_i^2 for |r_i| <= f_i / D_i, else f_i |r_i| - f_i^2 / (2 D_i).
+ * Each s_i is C^1 and piecewise quadratic in r_i.  Zone codes of a row at r:
+ * 0 no force, 1 quadratic (w = D r, curvature D), 2 saturated at +f (w = f),
+ * 3 saturated at -f (w = -f).
+ */
+static int row_zone(int kind, double r, double D, double f) {
+    if (kind == 0) return r < 0.0 ? 1 : 0;
+    if (kind == 1) return 1;
+    const double d = f / D;
+    if (r > d) return 2;
+    if (r < -d) return 3;
+    return 1;
+}
+
+static double row_w(int zone, double r, double D, double f) {
+    return zone == 1 ? D * r : (zone == 2 ? f : (zone == 3 ? -f : 0.0));
+}
+
+static double row_s(int zone, double r, double D, double f) {
+    if (zone == 1) return 0.5 * D * r * r;
+    if (zone == 2 || zone == 3) return f * fabs(r) - 0.5 * f * f / D;
+    return 0.0;
+}
+
+/* F, zones and L at a; returns L(a) */
+static double rows_eval(int n, int m, const double *M, const double *J, const double *a0,
+                        const double *aref, const double *D, const unsigned char *kind,
+                        const double *fl, const double *a, double *r, unsigned char *zone,
+                        double *w, double *F) {
+    double *d = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    matvec(m, n, J, a, r);
+    double Lv = 0.0;
+    for (int i = 0; i < m; ++i) {
+        r[i] -= aref[i];
+        zone[i] = (unsigned char)row_zone(kind[i], r[i], D[i], fl[i]);
+        w[i] = row_w(zone[i], r[i], D[i], fl[i]);
+        Lv += row_s(zone[i], r[i], D[i], fl[i]);
+    }
+    matvec(n, n, M, d, F);
+    Lv += 0.5 * dot(n, d, F);
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += J[(size_t)i * n + j] * w[i];
+        F[j] += s;
+    }
+    free(d);
+    return Lv;
+}
+
+static int dbl_cmp(const void *x, const void *y) {
+    const double a = *(const double *)x, b = *(const double *)y;
+    return (a > b) - (a < b);
+}
+
+/* Exact line search: phi'(t) = c0 t + b0 + sum_i q_i w_i(r_i + t q_i) is
+ * continuous, increasing and piecewise linear.  Its breakpoints (t > 0 where a
+ * row changes zone) are sorted; on each piece in turn the zones at the
+ * piece's midpoint give the line phi' = c t + b, and the first piece whose
+ * line has its root before the piece's end holds the minimiser. */
+static double rows_line_search(int n, int m, const double *M, const double *J, const double *a0,
+                               const double *D, const unsigned char *kind, const double *fl,
+                               const double *a, const double *p, const double *r) {
+    int mm = m > 0 ? m : 1;
+    double *q = (double *)malloc(sizeof(double) * mm), *bp = (double *)malloc(sizeof(double) * 2 * mm);
+    double *Mp = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *d = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    matvec(m, n, J, p, q);
+    matvec(n, n, M, p, Mp);
+    for (int j = 0; j < n; ++j) d[j] = a[j] - a0[j];
+    const double c0 = dot(n, p, Mp), b0 = dot(n, Mp, d);
+    int nb = 0;
+    for (int i = 0; i < m; ++i) {
+        if (q[i] == 0.0) continue;
+        if (kind[i] == 0) {
+            const double t = -r[i] / q[i];
+            if (t > 0.0) bp[nb++] = t;
+        } else if (kind[i] == 2) {
+            const double dd = fl[i] / D[i];
+            const double t1 = (dd - r[i]) / q[i], t2 = (-dd - r[i]) / q[i];
+            if (t1 > 0.0) bp[nb++] = t1;
+            if (t2 > 0.0) bp[nb++] = t2;
+        }
+    }
+    qsort(bp, (size_t)nb, sizeof(double), dbl_cmp);
+    double lo = 0.0, alpha = 0.0;
+    for (int k = 0; k <= nb; ++k) {
+        const double hi = k < nb ? bp[k] : INFINITY;
+        if (hi <= lo) continue;
+        const double mid = k < nb ? 0.5 * (lo + hi) : lo + 1.0 + fabs(lo);
+        double c = c0, b = b0;
+        for (int i = 0; i < m; ++i) {
+            const int z = row_zone(kind[i], r[i] + mid * q[i], D[i], fl[i]);
+            if (z == 1) { c += D[i] * q[i] * q[i]; b += D[i] * q[i] * r[i]; }
+            else if (z == 2) b += fl[i] * q[i];
+            else if (z == 3) b -= fl[i] * q[i];
+        }
+        alpha = -b / c;
+        if (alpha <= hi) break;
+        lo = hi;
+    }
+    free(q); free(bp); free(Mp); free(d);
+    return alpha;
+}
+
+/* Forward solve with mixed rows: Newton steps with H = M + J^T diag(g) J
+ * (g_i = D_i in zone 1, else 0), the exact line search above, and the stopping
+ * rule of oracle_forward with the zone pattern in place of the active set.
+ * Outputs a, zone (m), iters, status. */
+int oracle_forward_rows(int n, int m, const double *M, const double *J, const double *a0,
+                        const double *aref, const double *D, const unsigned char *kind,
+                        const double *fl, int max_iter, double tol, double *a,
+                        unsigned char *zone, int *iters, int *status) {
+    *iters = 0;
+    if (!all_finite((size_t)n * n, M) || !all_finite((size_t)m * n, J) || !all_finite(n, a0) ||
+        !all_finite(m, aref) || !all_finite(m, D) || !all_finite(m, fl)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) zone[i] = 0;
+        *status = ST_NONFINITE;
+        return 0;
+    }
+    if (!is_spd(n, M)) {
+        for (int j = 0; j < n; ++j) a[j] = NAN;
+        for (int i = 0; i < m; ++i) zone[i] = 0;
+        *status = ST_NOTSPD;
+        return 0;
+    }
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *r = (double *)malloc(sizeof(double) * mm), *w = (double *)malloc(sizeof(double) * mm);
+    double *F = (double *)malloc(sizeof(double) * n1), *H = (double *)malloc(sizeof(double) * n1 * n1);
+    double *p = (double *)malloc(sizeof(double) * n1), *mf = (double *)malloc(sizeof(double) * n1);
+    double *g = (double *)malloc(sizeof(double) * mm);
+    unsigned char *zprev = (unsigned char *)malloc(mm);
+    for (int j = 0; j < n; ++j) a[j] = a0[j];
+    double step_inf = -1.0;
+    int st = ST_MAXITER;
+    for (int k = 0;; ++k) {
+        if (k > 0) memcpy(zprev, zone, m);
+        rows_eval(n, m, M, J, a0, aref, D, kind, fl, a, r, zone, w, F);
+        const int same = k > 0 && (m == 0 || memcmp(zprev, zone, m) == 0);
+        if (converged(n, M, F, step_inf, same, a, tol)) { st = ST_CONVERGED; break; }
+        if (k == max_iter) { st = ST_MAXITER; break; }
+        for (int i = 0; i < m; ++i) g[i] = zone[i] == 1 ? D[i] : 0.0;
+        assemble_H(n, m, M, J, g, zone, H);
+        for (int j = 0; j < n; ++j) mf[j] = -F[j];
+        qr_solve(n, H, mf, p);
+        const double al = rows_line_search(n, m, M, J, a0, D, kind, fl, a, p, r);
+        step_inf = 0.0;
+        for (int j = 0; j < n; ++j) {
+            a[j] += al * p[j];
+            step_inf = fmax(step_inf, fabs(al * p[j]));
+        }
+        *iters = k + 1;
+    }
+    *status = st;
+    free(r); free(w); free(F); free(H); free(p); free(mf); free(g); free(zprev);
+    return 0;
+}
+
+/* IFT VJP with mixed rows (eq. 17) at a: H lambda = abar, sigma = J lambda,
+ *   a0bar = M^T lambda, arefbar_i = g_i sigma_i, Dbar_i = -r_i sigma_i in zone 1
+ *   (0 elsewhere), fbar_i = -sign(r_i) sigma_i in zones 2, 3 (0 elsewhere),
+ *   Jbar = -(w lambda^T + arefbar a^T), Mbar = -lambda (a - a0)^T.
+ * Any output may be NULL. */
+int oracle_ift_vjp_rows(int n, int m, const double *M, const double *J, const double *a0,
+                        const double *aref, const double *D, const unsigned char *kind,
+                        const double *fl, const double *a, const double *abar, double *a0bar,
+                        double *arefbar, double *Jbar, double *Dbar, double *flbar,
+                        double *Mbar) {
+    int mm = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+    double *r = (double *)malloc(sizeof(double) * mm), *w = (double *)malloc(sizeof(double) * mm);
+    double *F = (double *)malloc(sizeof(double) * n1), *H = (double *)malloc(sizeof(double) * n1 * n1);
+    double *lam = (double *)malloc(sizeof(double) * n1), *sg = (double *)malloc(sizeof(double) * mm);
+    double *g = (double *)malloc(sizeof(double) * mm);
+    unsigned char *zone = (unsigned char *)malloc(mm);
+    rows_eval(n, m, M, J, a0, aref, D, kind, fl, a, r, zone, w, F);
+    for (int i = 0; i < m; ++i) g[i] = zone[i] == 1 ? D[i] : 0.0;
+    assemble_H(n, m, M, J, g, zone, H);
+    qr_solve(n, H, abar, lam);
+    matvec(m, n, J, lam, sg);
+    if (a0bar) matvec_t(n, n, M, lam, a0bar);
+    for (int i = 0; i < m; ++i) {
+        const double ab = g[i] * sg[i];
+        if (arefbar) arefbar[i] = ab;
+        if (Dbar) Dbar[i] = zone[i] == 1 ? -r[i] * sg[i] : 0.0;
+        if (flbar) flbar[i] = zone[i] == 2 ? -sg[i] : (zone[i] == 3 ? sg[i] : 0.0);
+        if (Jbar)
+            for (int j = 0; j < n; ++j) Jbar[(size_t)i * n + j] = -(w[i] * lam[j] + ab * a[j]);
+    }
+    if (Mbar)
+        for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) Mbar[(size_t)j * n + l] = -lam[j] * (a[l] - a0[l]);
+    free(r); free(w); free(F); free(H); free(lam); free(sg); free(g); free(zone);
+    return 0;
+}
+
 static void set_threads(int threads) {
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);

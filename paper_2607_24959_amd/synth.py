@@ -297,3 +297,67 @@ def elliptic_batch(B: int, n: int, nc: int, seed: int, a0_var: float = 10.0) -> 
     return EllipticBatch(n=n, nc=nc, M=np.ascontiguousarray(M), J=np.ascontiguousarray(J),
                          a0=a0, aref=np.ascontiguousarray(aref), dn=1.0 / R, dt=1.0 / R,
                          mu=mu, abar=abar)
+
+
+# ------------------------------------------------------------------ mixed rows
+#
+# Pyramid contact rows followed by ne equality rows and nf friction-loss rows
+# (row kinds 0, 1, 2).  Equality and friction-loss rows: J entries ~ N(0, 1/n),
+# R ~ logU[1e-4, 1e-2] (D = 1/R), aref = -b J v (damping only; the equality rows
+# also -k e with a violation e ~ N(0, 0.01^2)); the friction-loss bound
+# f ~ U[0.1, 100] per row (0 on the other rows).  Drawn after the uniform
+# batch's fields from the same stream order, per batch.
+
+KIND_ONE_SIDED, KIND_EQUALITY, KIND_FRICTION_LOSS = 0, 1, 2
+
+
+@dataclass
+class MixedBatch:
+    n: int
+    M: np.ndarray
+    J: np.ndarray
+    a0: np.ndarray
+    aref: np.ndarray
+    D: np.ndarray
+    kind: np.ndarray    # uint8 [B, m]
+    floss: np.ndarray   # [B, m]
+    abar: np.ndarray
+
+    @property
+    def B(self):
+        return self.M.shape[0]
+
+    @property
+    def m(self):
+        return self.J.shape[1]
+
+    def astype(self, dtype):
+        kw = {k: getattr(self, k).astype(dtype) for k in ("M", "J", "a0", "aref", "D", "floss", "abar")}
+        return MixedBatch(n=self.n, kind=self.kind.copy(), **kw)
+
+    def rounded(self, dtype):
+        return self.astype(dtype).astype(np.float64)
+
+
+def mixed_batch(B: int, n: int, nc: int, ne: int, nf: int, seed: int) -> MixedBatch:
+    u = uniform_batch(B, n, nc, seed)
+    rng = np.random.Generator(np.random.PCG64([seed, 1]))
+    sd = math.sqrt(1.0 / n)
+    k = ne + nf
+    Jx = rng.normal(0.0, sd, (B, k, n))
+    R = np.exp(rng.uniform(math.log(1e-4), math.log(1e-2), (B, k)))
+    e = rng.normal(0.0, 0.01, (B, ne))
+    f = rng.uniform(0.1, 100.0, (B, nf))
+    arefx = -B_DAMP * np.einsum("bij,bj->bi", Jx, u.v)
+    arefx[:, :ne] -= K_SPRING * e
+    J = np.concatenate([u.J, Jx], axis=1)
+    aref = np.concatenate([u.aref, arefx], axis=1)
+    D = np.concatenate([u.D, 1.0 / R], axis=1)
+    m = J.shape[1]
+    kind = np.zeros((B, m), np.uint8)
+    kind[:, u.m:u.m + ne] = KIND_EQUALITY
+    kind[:, u.m + ne:] = KIND_FRICTION_LOSS
+    floss = np.zeros((B, m))
+    floss[:, u.m + ne:] = f
+    return MixedBatch(n=n, M=u.M, J=np.ascontiguousarray(J), a0=u.a0, aref=np.ascontiguousarray(aref),
+                      D=np.ascontiguousarray(D), kind=kind, floss=floss, abar=u.abar)
