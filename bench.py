@@ -386,6 +386,70 @@ def ell_line(steps=20, K=40, tol=1e-5):
                        "zone_fractions": [float(np.mean(z == k)) for k in (0, 1, 2)]}}
 
 
+def rows_line(steps=20, K=40, tol=1e-5, ne=4, nf=8):
+    """Mixed rows at the headline's shape: B=4096, nv=9, 16 contacts (64
+    pyramid rows) plus 4 equality and 8 friction-loss rows, FP32 storage (FP64
+    arithmetic), cap K=40, forward + IFT VJP; timed like ell_line."""
+    import torch
+    from paper_2607_24959_amd import solver, synth
+    m = 4 * NC + ne + nf
+    batch = solver.Batch.uniform(B, NV, m, torch.float32)
+    per_batch = B * (4 * (NV * NV + m * NV + 2 * NV + 3 * m) + m) + batch.state_bytes()
+    R = max(8, math.ceil(2 * MALL_BYTES / per_batch) + 1)
+    R += R % 2
+    keys = ("M", "J", "a0", "aref", "D")
+    bufs = []
+    for r in range(R):
+        mb = synth.mixed_batch(B, NV, NC, ne, nf, 20260725 + 700 + r).astype(np.float32)
+        t = {k: torch.from_numpy(np.ascontiguousarray(getattr(mb, k))).cuda()
+             for k in keys + ("floss", "abar")}
+        t["kind"] = torch.from_numpy(np.ascontiguousarray(mb.kind)).cuda()
+        sol = solver.forward_rows(batch, *(t[k] for k in keys), t["kind"], t["floss"], max_iter=K,
+                                  tol=tol)
+        gr = solver.ift_vjp_rows(batch, sol, *(t[k] for k in keys), t["kind"], t["floss"], t["abar"])
+        bufs.append((t, sol, gr))
+    torch.cuda.synchronize()
+
+    def fwd(t, sol, gr):
+        solver.forward_rows(batch, *(t[k] for k in keys), t["kind"], t["floss"], max_iter=K, tol=tol,
+                            out=sol)
+
+    def vjp(t, sol, gr):
+        solver.ift_vjp_rows(batch, sol, *(t[k] for k in keys), t["kind"], t["floss"], t["abar"],
+                            out=gr)
+
+    def graph(fns):
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st), torch.cuda.graph(g, stream=st):
+            for i in range(steps):
+                for fn in fns:
+                    fn(*bufs[i % R])
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+        return g, st
+
+    g, st = graph((fwd, vjp))
+    ms, spread = replay_median(g)
+    gf, sf = graph((fwd,))
+    t_f = replay_median(gf)[0] / steps
+    gv, sv = graph((vjp,))
+    t_v = replay_median(gv)[0] / steps
+    stat = np.concatenate([b[1].status.cpu().numpy() for b in bufs[:steps]])
+    its = np.concatenate([b[1].iters.cpu().numpy() for b in bufs[:steps]])
+    del g, gf, gv, st, sf, sv
+    return {"workload": f"mixed rows, uniform batch B={B}, nv={NV}, {NC} contacts ({4 * NC} pyramid "
+                        f"rows) + {ne} equality + {nf} friction-loss rows, FP32 storage (FP64 "
+                        f"arithmetic), cap K={K}, tol {tol}, forward + IFT VJP",
+            "value": B * steps / (ms / 1e3), "unit": "solves/s", "ms_per_step": ms / steps,
+            "replay_spread": spread, "rotating_batches": R,
+            "kernels": {"forward_ms": t_f, "ift_vjp_ms": t_v},
+            "solver": {"converged_frac": float(np.mean((stat & 1) != 0)),
+                       "lsfail_count": int(np.sum((stat & 16) != 0)),
+                       "mean_iters": float(its.mean()), "max_iters": int(its.max())}}
+
+
 def rollout_line(B_=1024, n=18, nc=32, horizon=50, reps=5):
     """The differentiation workload (B=1024, nv=18, 32 contacts, h=0.002,
     horizon 50, FP64, loss ||v_T - v_goal||^2): the gradient w.r.t. tau by
@@ -655,7 +719,7 @@ def main():
                     help="skip the converging, FP64, K-sweep, uneven and serving lines")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration)")
-    ap.add_argument("--section", choices=("uneven", "serving", "rollout", "elliptic"),
+    ap.add_argument("--section", choices=("uneven", "serving", "rollout", "elliptic", "rows"),
                     help="only run this workload (for profiling) and print its JSON")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -663,6 +727,9 @@ def main():
     rates = tuple(int(x) for x in args.serve_rates.split(","))
     if args.section == "uneven":
         print(json.dumps(uneven(reps=5)), flush=True)
+        return
+    if args.section == "rows":
+        print(json.dumps(rows_line(args.steps)), flush=True)
         return
     if args.section == "elliptic":
         print(json.dumps(ell_line(args.steps)), flush=True)
@@ -813,6 +880,8 @@ def main():
         out["elliptic"] = ell_line(args.steps)
         progress(f"round cone: {out['elliptic']['value']:.4g} solves/s, converged "
                  f"{out['elliptic']['solver']['converged_frac']:.4f}")
+        out["mixed_rows"] = rows_line(args.steps)
+        progress(f"mixed rows: {out['mixed_rows']['value']:.4g} solves/s")
         out["rollout"] = rollout_line()
         progress(f"fused rollout: {out['rollout']['fused_ms']:.3g} ms vs layered "
                  f"{out['rollout']['layered_ms']:.3g} ms")

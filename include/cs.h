@@ -321,6 +321,38 @@ int cs_ift_vjp_ell(const cs_batch *batch, const void *state, size_t state_bytes,
                    void *arefbar, void *Jbar, void *dnbar, void *dtbar, void *mubar, void *Mbar,
                    void *stream);
 
+/* Mixed regularised rows (Sec. III-A's other constraint rows): row i has a
+ * kind (one byte): 0 one-sided (a pyramid edge or a limit), s = D min(r, 0)^2 / 2;
+ * 1 equality, s = D r^2 / 2; 2 friction loss with bound floss_i >= 0 (its force
+ * saturates at +-floss), s = D r^2 / 2 for |r| <= floss / D and
+ * floss |r| - floss^2 / (2 D) beyond (floss is read for kind 2 only; D > 0).
+ * cs_forward_rows: Newton steps with H = M + J^T diag(g) J (g_i = D_i where the
+ * row is in its quadratic zone, else 0), the exact line search (phi' is
+ * piecewise linear), the stopping rule of cs_forward with the zone pattern in
+ * place of the active set; params->flags must be 0.  The state layout is
+ * cs_forward's, each row's byte holding its zone: 0 no force, 1 quadratic,
+ * 2 / 3 saturated at +floss / -floss.  kind [total_m] and floss [total_m] at
+ * off_m.  Arithmetic in FP64 for both dtypes.  n <= 32 and J resident in LDS
+ * (within 160 KiB), else CS_EUNSUPPORTED; a bad kind or D <= 0 gives
+ * CS_ST_NONFINITE. */
+int cs_forward_rows(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                    const void *J, const void *a0, const void *aref, const void *D,
+                    const uint8_t *kind, const void *floss, const void *a_init, void *a_out,
+                    void *state, size_t state_bytes, int32_t *status, int32_t *iters,
+                    void *stream);
+
+/* IFT VJP with mixed rows (eq. 17) at the solution cs_forward_rows returned,
+ * with its zones and factor: H lambda = abar, sigma = J lambda,
+ *   a0bar = M^T lambda, arefbar_i = g_i sigma_i, Dbar_i = -r_i sigma_i (zone 1,
+ *   else 0), flossbar_i = -sigma_i (zone 2), +sigma_i (zone 3), else 0,
+ *   Jbar = -(w lambda^T + arefbar a^T), Mbar = -lambda (a - a0)^T.
+ * Every output may be NULL.  Layouts as cs_forward_rows. */
+int cs_ift_vjp_rows(const cs_batch *batch, const void *state, size_t state_bytes,
+                    const void *M, const void *J, const void *a0, const void *aref, const void *D,
+                    const uint8_t *kind, const void *floss, const void *a, const void *abar,
+                    void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *flossbar, void *Mbar,
+                    void *stream);
+
 /* Name of an error code. */
 const char *cs_strerror(int code);
 

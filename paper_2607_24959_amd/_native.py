@@ -23,6 +23,7 @@ ROLLOUT_FORWARD, ROLLOUT_BACKWARD, ROLLOUT_RECOMPUTE = 1, 2, 4
 
 EXPORTED = ("cs_forward", "cs_ift_vjp", "cs_ift_jvp", "cs_unrolled_vjp", "cs_unrolled_vjp_static",
             "cs_rollout", "cs_rollout_workspace_bytes", "cs_forward_ell", "cs_ift_vjp_ell",
+            "cs_forward_rows", "cs_ift_vjp_rows",
             "cs_state_bytes",
             "cs_unrolled_tape_bytes", "cs_strerror", "cs_version",
             "cs_serve_admit", "cs_serve_pre", "cs_serve_post", "cs_serve_tick")
@@ -105,6 +106,10 @@ def lib():
         L.cs_forward_ell.argtypes = [pb, pp] + [vp] * 10 + [sz, vp, vp, vp]
         L.cs_ift_vjp_ell.restype = C.c_int
         L.cs_ift_vjp_ell.argtypes = [pb, vp, sz] + [vp] * 17
+        L.cs_forward_rows.restype = C.c_int
+        L.cs_forward_rows.argtypes = [pb, pp] + [vp] * 10 + [sz, vp, vp, vp]
+        L.cs_ift_vjp_rows.restype = C.c_int
+        L.cs_ift_vjp_rows.argtypes = [pb, vp, sz] + [vp] * 16
         prp = C.POINTER(CsRolloutParams)
         L.cs_rollout_workspace_bytes.restype = sz
         L.cs_rollout_workspace_bytes.argtypes = [pb, prp]
@@ -177,6 +182,18 @@ def ift_vjp_ell(batch, state, state_nbytes, M, J, a0, aref, dn, dt, mu, a, abar,
                 Jbar, dnbar, dtbar, mubar, Mbar, stream):
     return lib().cs_ift_vjp_ell(C.byref(batch), state, state_nbytes, M, J, a0, aref, dn, dt, mu, a,
                                 abar, a0bar, arefbar, Jbar, dnbar, dtbar, mubar, Mbar, stream)
+
+
+def forward_rows(batch, params, M, J, a0, aref, D, kind, floss, a_init, a_out, state, state_nbytes,
+                 status, iters, stream):
+    return lib().cs_forward_rows(C.byref(batch), C.byref(params), M, J, a0, aref, D, kind, floss,
+                                 a_init, a_out, state, state_nbytes, status, iters, stream)
+
+
+def ift_vjp_rows(batch, state, state_nbytes, M, J, a0, aref, D, kind, floss, a, abar, a0bar,
+                 arefbar, Jbar, Dbar, flossbar, Mbar, stream):
+    return lib().cs_ift_vjp_rows(C.byref(batch), state, state_nbytes, M, J, a0, aref, D, kind, floss,
+                                 a, abar, a0bar, arefbar, Jbar, Dbar, flossbar, Mbar, stream)
 
 
 def rollout_workspace_bytes(batch, params):

@@ -15,6 +15,7 @@
 #include "cs_jvp.hpp"
 #include "cs_rollout.hpp"
 #include "cs_ell.hpp"
+#include "cs_rows.hpp"
 #include "cs_small.hpp"
 #include "cs_vjp_team.hpp"
 #include "cs_wave.hpp"
@@ -618,6 +619,89 @@ int cs_ift_vjp_ell(const cs_batch *batch, const void *state, size_t state_bytes_
         g.mubar = (T *)mubar;
         g.Mbar = (T *)Mbar;
         return cs::launch_ell<T>(true, hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, s);
+    };
+    const int r = hb.dtype == CS_F32 ? go(float()) : go(double());
+    return r == 0 ? CS_OK : CS_EHIP;
+}
+
+int cs_forward_rows(const cs_batch *batch, const cs_solver_params *params, const void *M,
+                    const void *J, const void *a0, const void *aref, const void *D,
+                    const uint8_t *kind, const void *floss, const void *a_init, void *a_out,
+                    void *state, size_t state_bytes_given, int32_t *status, int32_t *iters,
+                    void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if ((rc = check_params(params)) != CS_OK) return rc;
+    if (params->flags != 0) return CS_EINVAL;
+    if (hb.B == 0) return CS_OK;
+    if (!M || !a0 || !a_out || !state || !status) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D || !kind || !floss)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    if (!cs::rows_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *mask = static_cast<uint8_t *>(state) + align256(hb.s * factor_elems(hb));
+    auto go = [&](auto tag) {
+        typedef decltype(tag) T;
+        cs::RwArgs<T> g = {};
+        g.M = (const T *)M;
+        g.J = (const T *)J;
+        g.a0 = (const T *)a0;
+        g.aref = (const T *)aref;
+        g.D = (const T *)D;
+        g.fl = (const T *)floss;
+        g.kind = kind;
+        g.ainit = (const T *)a_init;
+        g.aout = (T *)a_out;
+        g.fac = (T *)state;
+        g.mask = mask;
+        g.status = status;
+        g.iters = iters;
+        g.max_iter = params->max_iter;
+        g.tol = params->tol;
+        return cs::launch_rows<T>(false, hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, s);
+    };
+    const int r = hb.dtype == CS_F32 ? go(float()) : go(double());
+    return r == 0 ? CS_OK : CS_EHIP;
+}
+
+int cs_ift_vjp_rows(const cs_batch *batch, const void *state, size_t state_bytes_given,
+                    const void *M, const void *J, const void *a0, const void *aref, const void *D,
+                    const uint8_t *kind, const void *floss, const void *a, const void *abar,
+                    void *a0bar, void *arefbar, void *Jbar, void *Dbar, void *flossbar, void *Mbar,
+                    void *stream) {
+    HostBatch hb;
+    int rc = describe(batch, hb);
+    if (rc != CS_OK) return rc;
+    if (hb.B == 0) return CS_OK;
+    if (!state || !M || !a0 || !a || !abar) return CS_EINVAL;
+    if (hb.tot_m > 0 && (!J || !aref || !D || !kind || !floss)) return CS_EINVAL;
+    if (state_bytes_given < state_bytes(hb)) return CS_ENOSPC;
+    if (!cs::rows_supported(hb.nmax, hb.mmax, (int)hb.s)) return CS_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *mask = static_cast<uint8_t *>(const_cast<void *>(state)) +
+                    align256(hb.s * factor_elems(hb));
+    auto go = [&](auto tag) {
+        typedef decltype(tag) T;
+        cs::RwArgs<T> g = {};
+        g.M = (const T *)M;
+        g.J = (const T *)J;
+        g.a0 = (const T *)a0;
+        g.aref = (const T *)aref;
+        g.D = (const T *)D;
+        g.fl = (const T *)floss;
+        g.kind = kind;
+        g.a = (const T *)a;
+        g.abar = (const T *)abar;
+        g.fac = (T *)const_cast<void *>(state);
+        g.mask = mask;
+        g.a0bar = (T *)a0bar;
+        g.arefbar = (T *)arefbar;
+        g.Jbar = (T *)Jbar;
+        g.Dbar = (T *)Dbar;
+        g.flbar = (T *)flossbar;
+        g.Mbar = (T *)Mbar;
+        return cs::launch_rows<T>(true, hb.bv, hb.bv.B, hb.nmax, hb.mmax, g, s);
     };
     const int r = hb.dtype == CS_F32 ? go(float()) : go(double());
     return r == 0 ? CS_OK : CS_EHIP;

@@ -239,6 +239,47 @@ def ift_vjp_ell(batch: Batch, sol: Solution, M, J, a0, aref, dn, dt, mu, abar, o
     return out
 
 
+def forward_rows(batch: Batch, M, J, a0, aref, D, kind, floss, *, max_iter=60, tol=1e-5,
+                 a_init=None, out: Optional[Solution] = None) -> Solution:
+    """Mixed-row forward solve (cs_forward_rows): kind (uint8 per row: 0
+    one-sided, 1 equality, 2 friction loss) and floss (the friction bound)
+    at the row offsets."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D), ("floss", floss)):
+        batch.check(name, t, s["D"] if name == "floss" else s[name])
+    if kind.dtype != torch.uint8 or kind.numel() != s["D"] or not kind.is_contiguous():
+        raise ValueError("kind must be a contiguous uint8 tensor with one byte per row")
+    batch.check("a_init", a_init, s["a0"], required=False)
+    if out is None:
+        out = Solution(
+            a=torch.empty_like(a0),
+            state=torch.empty(max(batch.state_bytes(), 1), dtype=torch.uint8, device=a0.device),
+            status=torch.empty(batch.B, dtype=torch.int32, device=a0.device),
+            iters=torch.empty(batch.B, dtype=torch.int32, device=a0.device))
+    p = N.CsSolverParams(int(max_iter), 0, float(tol))
+    rc = N.forward_rows(batch.desc, p, _vp(M), _vp(J), _vp(a0), _vp(aref), _vp(D), _vp(kind),
+                        _vp(floss), _vp(a_init), _vp(out.a), _vp(out.state), out.state.numel(),
+                        _vp(out.status), _vp(out.iters), _stream(a0.device))
+    N.check(rc, "cs_forward_rows")
+    return out
+
+
+def ift_vjp_rows(batch: Batch, sol: Solution, M, J, a0, aref, D, kind, floss, abar, out=None):
+    """Mixed-row IFT VJP (cs_ift_vjp_rows).  Returns dict(a0, aref, J, D, floss, M)."""
+    s = batch.sizes()
+    for name, t in (("M", M), ("J", J), ("a0", a0), ("aref", aref), ("D", D), ("abar", abar)):
+        batch.check(name, t, s[name])
+    if out is None:
+        out = dict(a0=torch.empty_like(a0), aref=torch.empty_like(aref), J=torch.empty_like(J),
+                   D=torch.empty_like(D), floss=torch.empty_like(floss), M=torch.empty_like(M))
+    rc = N.ift_vjp_rows(batch.desc, _vp(sol.state), sol.state.numel(), _vp(M), _vp(J), _vp(a0),
+                        _vp(aref), _vp(D), _vp(kind), _vp(floss), _vp(sol.a), _vp(abar),
+                        _vp(out["a0"]), _vp(out["aref"]), _vp(out["J"]), _vp(out["D"]),
+                        _vp(out["floss"]), _vp(out["M"]), _stream(a0.device))
+    N.check(rc, "cs_ift_vjp_rows")
+    return out
+
+
 def ift_jvp(batch: Batch, sol: Solution, M, J, D, k: int, da0=None, daref=None, out=None):
     """Directional derivatives of the solution for k tangent directions per
     instance (eq. 15): da0 [k * total_n] (instance i's k x n block at k off_n[i]),

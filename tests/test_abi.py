@@ -186,3 +186,15 @@ def test_round_cone_entry_points_validate_before_launch():
     assert N.forward_ell(b3.desc, p, None, *([one] * 9), 1 << 20, one, None, None) == N.CS_EINVAL
     assert N.forward_ell(b3.desc, p, *([one] * 10), 16, one, None, None) == N.CS_ENOSPC
     assert N.ift_vjp_ell(b.desc, one, 1 << 20, *([one] * 9), *([None] * 7), None) == N.CS_EINVAL
+
+
+def test_mixed_rows_entry_points_validate_before_launch():
+    b = solver.Batch.uniform(4, 6, 12, torch.float64, device="cpu")
+    p = N.CsSolverParams(10, 0, 1e-10)
+    one = C.c_void_p(1)
+    assert N.forward_rows(b.desc, N.CsSolverParams(10, 4, 1e-10), *([one] * 10), 1 << 20, one,
+                          None, None) == N.CS_EINVAL
+    assert N.forward_rows(b.desc, p, None, *([one] * 9), 1 << 20, one, None, None) == N.CS_EINVAL
+    assert N.forward_rows(b.desc, p, *([one] * 10), 16, one, None, None) == N.CS_ENOSPC
+    assert N.ift_vjp_rows(b.desc, one, 1 << 20, None, *([one] * 8), *([None] * 6), None) == \
+        N.CS_EINVAL
