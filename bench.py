@@ -46,6 +46,7 @@ K_CONV = 40               # cap at which every instance of the workload converge
 MALL_BYTES = 256 * 2 ** 20
 HBM_PEAK = 8.0e12          # B/s
 FP32_VEC_PEAK = 157.3e12   # flop/s (256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz)
+FP64_VEC_PEAK = 78.6e12    # flop/s (256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz)
 
 
 def progress(msg):
@@ -72,6 +73,25 @@ def forward_flops(n, m, active, iters):
     step = 8 * m * n + 8 * n * n + active * n * (n + 1) + n ** 3 / 3 + 8 * m + 2 * n
     final = 4 * m * n + 2 * n * n + active * n * (n + 1) + n ** 3 / 3
     return iters * step + final
+
+
+def fp64_roofline(kernel, flops, ms):
+    """Roofline position of an FP64-arithmetic kernel: algorithmic flops of one
+    launch over its duration, against the FP64 vector peak."""
+    rate = flops / (ms / 1e3)
+    return {"kernel": kernel, "bound": "alu", "achieved": rate / 1e12, "peak": FP64_VEC_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": rate / FP64_VEC_PEAK, "flops_per_launch": flops}
+
+
+def ell_flops(n, nc, live, iters, ls_evals=5.3):
+    """Algorithmic flops of one round-cone forward: per Newton step the
+    pyramid model's row passes over m = 3 nc rows, K = G J for the live
+    contacts (18 n each), H over their 3 rows (3 live n (n+1)), the Cholesky,
+    and ls_evals line-search evaluations of every contact's block (~60 flops)."""
+    m = 3 * nc
+    step = 8 * m * n + 8 * n * n + 18 * live * n + 3 * live * n * (n + 1) + n ** 3 / 3 + \
+        ls_evals * 60 * nc + 2 * n
+    return iters * step + 4 * m * n + 2 * n * n + 3 * live * n * (n + 1) + n ** 3 / 3
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_uniform_B4096_n9_m64.txt")
@@ -374,8 +394,12 @@ def ell_line(steps=20, K=40, tol=1e-5):
     stat = np.concatenate([b[1].status.cpu().numpy() for b in bufs[:steps]])
     its = np.concatenate([b[1].iters.cpu().numpy() for b in bufs[:steps]])
     z = batch.zones(bufs[0][1])
+    live = (z.reshape(B, nc) != 0).sum(1)
+    it0 = bufs[0][1].iters.cpu().numpy()
+    flops = float(np.sum(ell_flops(NV, nc, live, it0)))
     del g, gf, gv, st, sf, sv
-    return {"workload": f"round cone, uniform batch B={B}, nv={NV}, {nc} contacts ({m} rows), "
+    return {"roofline": fp64_roofline("k_forward_ell<float>", flops, t_f),
+            "workload": f"round cone, uniform batch B={B}, nv={NV}, {nc} contacts ({m} rows), "
                         f"FP32 storage (FP64 arithmetic), cap K={K}, tol {tol}, forward + IFT VJP",
             "value": B * steps / (ms / 1e3), "unit": "solves/s", "ms_per_step": ms / steps,
             "replay_spread": spread, "rotating_batches": R,
@@ -438,8 +462,12 @@ def rows_line(steps=20, K=40, tol=1e-5, ne=4, nf=8):
     t_v = replay_median(gv)[0] / steps
     stat = np.concatenate([b[1].status.cpu().numpy() for b in bufs[:steps]])
     its = np.concatenate([b[1].iters.cpu().numpy() for b in bufs[:steps]])
+    o = batch.mask_offset()
+    zone0 = bufs[0][1].state[o:o + B * m].cpu().numpy().reshape(B, m)
+    flops = float(np.sum(forward_flops(NV, m, (zone0 == 1).sum(1), bufs[0][1].iters.cpu().numpy())))
     del g, gf, gv, st, sf, sv
-    return {"workload": f"mixed rows, uniform batch B={B}, nv={NV}, {NC} contacts ({4 * NC} pyramid "
+    return {"roofline": fp64_roofline("k_forward_rows<float>", flops, t_f),
+            "workload": f"mixed rows, uniform batch B={B}, nv={NV}, {NC} contacts ({4 * NC} pyramid "
                         f"rows) + {ne} equality + {nf} friction-loss rows, FP32 storage (FP64 "
                         f"arithmetic), cap K={K}, tol {tol}, forward + IFT VJP",
             "value": B * steps / (ms / 1e3), "unit": "solves/s", "ms_per_step": ms / steps,
@@ -492,7 +520,20 @@ def rollout_line(B_=1024, n=18, nc=32, horizon=50, reps=5):
     t_lay, g_lay = timed(layered)
     e = ((o["tau_bar"] - g_lay).transpose(0, 1).flatten(1).norm(dim=1) /
          g_lay.transpose(0, 1).flatten(1).norm(dim=1)).max().item()
-    return {"workload": f"rollout gradient, B={B_}, nv={n}, {nc} contacts, horizon {horizon}, "
+    # algorithmic flops of the fused launch: every Newton step of every solve
+    # (forward_flops at the step's average active-row count, read from the
+    # workspace's saved active sets) plus the backward per step (a solve with
+    # the kept factor, J lambda and J^T s: 4 n^2 + 4 m n)
+    m = 4 * nc
+    step_bytes = o["ws"].numel() // horizon
+    masks = o["ws"].view(horizon, step_bytes)[:, step_bytes - ((B_ * m + 255) // 256 * 256):]
+    act = masks[:, :B_ * m].reshape(horizon, B_, m).sum(-1).double().mean(0).cpu().numpy()
+    its = o["iters"].double().cpu().numpy()
+    final = 4 * m * n + 2 * n * n + act * n * (n + 1) + n ** 3 / 3
+    flops = float(np.sum(forward_flops(n, m, act, its) + (horizon - 1) * final +
+                         horizon * (4 * n * n + 4 * m * n)))
+    return {"roofline": fp64_roofline("k_rollout<double>", flops, t_store),
+            "workload": f"rollout gradient, B={B_}, nv={n}, {nc} contacts, horizon {horizon}, "
                         "h=0.002, FP64, tol 1e-12",
             "fused_ms": t_store, "fused_recompute_ms": t_rec, "layered_ms": t_lay,
             "fused_speedup": t_lay / t_store,
