@@ -34,6 +34,34 @@ template <> __device__ inline float gsum16<float>(float v) {
     return v;
 }
 
+// Whether `x` holds in any lane of this lane's 16-lane group: one ballot and a
+// shift, instead of a four-step DPP reduction (every lane of a group shares
+// the group's control flow, so the group's 16 bits are all live or all not).
+__device__ inline bool group_any16(bool x) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(x);
+    return ((m >> (threadIdx.x & 48)) & 0xFFFFull) != 0;
+}
+
+// Two independent 16-lane sums with their DPP steps interleaved, so that each
+// step of one hides the other's wait states (the compiler keeps a loop body's
+// DPP chains in source order).
+__device__ inline void gsum16x2(float &a, float &b) {
+#define CS_GS2(CTRL)                                                                               \
+    {                                                                                              \
+        const float ta = __builtin_bit_cast(                                                       \
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, a), CTRL, 0xF, 0xF, false)); \
+        const float tb = __builtin_bit_cast(                                                       \
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, b), CTRL, 0xF, 0xF, false)); \
+        a += ta;                                                                                   \
+        b += tb;                                                                                   \
+    }
+    CS_GS2(0xB1)
+    CS_GS2(0x4E)
+    CS_GS2(0x141)
+    CS_GS2(0x140)
+#undef CS_GS2
+}
+
 // FP64: the same four DPP steps on the two halves of each value.
 template <int CTRL> __device__ inline double dpp_f64(double v) {
     const long long b = __builtin_bit_cast(long long, v);
@@ -47,6 +75,20 @@ template <> __device__ inline double gsum16<double>(double v) {
     v += dpp_f64<0x141>(v);
     v += dpp_f64<0x140>(v);
     return v;
+}
+__device__ inline void gsum16x2(double &a, double &b) {
+    const double a1 = dpp_f64<0xB1>(a), b1 = dpp_f64<0xB1>(b);
+    a += a1;
+    b += b1;
+    const double a2 = dpp_f64<0x4E>(a), b2 = dpp_f64<0x4E>(b);
+    a += a2;
+    b += b2;
+    const double a3 = dpp_f64<0x141>(a), b3 = dpp_f64<0x141>(b);
+    a += a3;
+    b += b3;
+    const double a4 = dpp_f64<0x140>(a), b4 = dpp_f64<0x140>(b);
+    a += a4;
+    b += b4;
 }
 
 template <typename T> __device__ inline T fast_rsq(T x);
@@ -362,8 +404,9 @@ __device__ inline T small_line_search(const T (&r)[R], const T (&q)[R], const T 
             sb += pa ? dqr[jj] : T(0);
             if constexpr (BITS) bb |= (pa ? 1u : 0u) << jj;
         }
-        c = c0 + gsum16(sc);
-        b = b0 + gsum16(sb);
+        gsum16x2(sc, sb);
+        c = c0 + sc;
+        b = b0 + sb;
         bits = bb;
     };
     T t = T(1), c, b;
@@ -456,7 +499,7 @@ __device__ inline int small_solve(const SmallInst<T, NP, R> &S, int max_iter, T 
             for (int jj = 0; jj < R; ++jj) s += S.J[jj][j] * (wD[jj] * r[jj]);
             F[j] = Md[j] + gsum16(s);
         }
-        const bool same = (k > 0) && gsum16(changed ? T(1) : T(0)) == T(0);
+        const bool same = (k > 0) && !group_any16(changed);
         T g2 = T(0), anorm = T(0);
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
@@ -648,7 +691,7 @@ __device__ inline int small_solve_cg(const SmallInst<T, NP, R> &S, int max_iter,
             for (int jj = 0; jj < R; ++jj) t += as_f64_here(S.J[jj][j]) * wr[jj];
             F[j] = Md[j] + gsum16(t);
         }
-        const bool same = (k > 0) && gsum16(changed ? C(1) : C(0)) == C(0);
+        const bool same = (k > 0) && !group_any16(changed);
         C z[NP];
         {
             T Ft[NP], zt[NP];
