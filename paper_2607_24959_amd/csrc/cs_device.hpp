@@ -147,19 +147,44 @@ template <> __device__ inline double inf_val<double>() { return __builtin_huge_v
 
 template <typename T> __device__ inline bool finite_val(T x) { return __builtin_isfinite(x); }
 
+// Wave-wide sum and max for a fully active wave, every lane receiving the
+// result: DPP within each row of 16 lanes (quad xor 1 and 2, half-row and row
+// mirrors; the value stays in vector registers), then the four row results
+// from lanes 0, 16, 32 and 48 by lane reads.  Fixed order: reproducible.
+template <int CTRL> __device__ inline float dpp_row(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ inline double dpp_row(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline float lane_read(float v, int k) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+}
+__device__ inline double lane_read(double v, int k) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <typename T> __device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_row<0xB1>(v);
+    v += dpp_row<0x4E>(v);
+    v += dpp_row<0x141>(v);
+    v += dpp_row<0x140>(v);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 template <typename T> __device__ inline T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o, 64);
-        v = v > u ? v : u;
-    }
-    return v;
+    auto mx = [](T x, T y) { return x > y ? x : y; };
+    v = mx(v, dpp_row<0xB1>(v));
+    v = mx(v, dpp_row<0x4E>(v));
+    v = mx(v, dpp_row<0x141>(v));
+    v = mx(v, dpp_row<0x140>(v));
+    return mx(mx(lane_read(v, 0), lane_read(v, 16)), mx(lane_read(v, 32), lane_read(v, 48)));
 }
 
 // Sum NV values over the team; every thread receives the totals.
