@@ -593,14 +593,153 @@ __device__ __attribute__((always_inline)) inline void team_chol_solve_lds(int lo
         }
     }
 }
+// 1 / sqrt(x) for a positive, normal pivot: the hardware estimate refined by
+// two Newton steps r <- r + r (1 - x r^2) / 2 in FP64 (quadratic convergence
+// from the estimate's ~2^-22 to rounding level); FP32 takes the estimate.
+__device__ inline double wave_rsq(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+__device__ inline float wave_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Cholesky H = L L^T for a one-wave team (n <= NB <= 64; NB a compile-time
+// bound): lane i holds row i of the lower triangle in registers (rows past n
+// repeat row n-1 and are never read).  Right-looking by columns: the pivot
+// and each column entry L_kj reach every lane by a lane read (a scalar
+// broadcast), so column j costs one reciprocal square root and one FMA per
+// trailing column in every lane, with no LDS traffic and no barrier.  Writes
+// L strictly below the diagonal of H and L_jj to diag[j], the layout of the
+// blocked factor.  Returns false (wave-uniform) when a pivot is not positive
+// (the remaining columns then take pivot 1 and the factor is not used).
+template <int NB, typename T>
+__device__ __attribute__((always_inline)) inline bool wave_cholesky_regs(T *H, T *diag, int n, int ld) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    ld = __builtin_amdgcn_readfirstlane(ld);
+    const int il = opaque_lane((int)threadIdx.x & 63);
+    const T *hr = H + min(il, n - 1) * ld;
+    T h[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) h[k] = k < n ? hr[k] : T(0);
+    bool ok = true;
+    static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        // n again as an opaque scalar per column: the compiler would
+        // otherwise precompute every (k < n) test of the unrolled loops and
+        // hold them all in scalar registers
+        int nj = n;
+        asm volatile("" : "+s"(nj));
+        if (__builtin_expect(j < nj, 1)) {
+            const T d = lane_read(h[j], j);
+            ok = ok && d > T(0);
+            h[j] *= wave_rsq(ok ? d : T(1));   // lane j: sqrt(d); lanes below: L_ij
+            // trailing columns in groups of four (entries of columns >= n are
+            // never read: they may take updates)
+            static_for<0, (NB - j + 2) / 4>([&](auto cc) {
+                constexpr int k0 = j + 1 + 4 * decltype(cc)::value;
+                if (__builtin_expect(k0 < nj, 1)) {
+                    static_for<k0, (k0 + 4 < NB ? k0 + 4 : NB)>([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        h[k] -= h[j] * lane_read(h[j], k);
+                    });
+                }
+            });
+        }
+    });
+    if (il < n) {
+        T *row = H + il * ld;
+        T dl = h[0];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (k < n && k < il) row[k] = h[k];
+            dl = k == il ? h[k] : dl;
+        }
+        diag[il] = dl;
+    }
+    __syncthreads();
+    return ok;
+}
+
+// Solve L L^T x = b with that factor (L strictly below the diagonal of L_,
+// L_jj in diag), one wave, n <= NB: lane i keeps its entry of the running
+// right-hand side in a register and its row (forward) or column (backward)
+// of L in registers, zero where the triangle ends, so every step is one
+// FMA per lane with no lane masks; the solved entry of step j, scaled by
+// 1 / L_jj, comes from lane j by a lane read.  b is only read (b and x may
+// be the same array: one wave reads before it writes); x is written and
+// synchronised.
+template <int NB, typename T>
+__device__ __attribute__((always_inline)) inline void wave_chol_solve_regs(const T *L_, const T *diag, const T *b,
+                                                                           T *x, int n, int ld) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    ld = __builtin_amdgcn_readfirstlane(ld);
+    const int il = opaque_lane((int)threadIdx.x & 63);
+    const int ri = min(il, n - 1);
+    const T rd = T(1) / diag[ri];
+    T v = il < n ? b[ri] : T(0);
+    T l[NB];
+    // forward L y = b: v_i <- v_i - L_ij y_j, y_j = v_j / L_jj
+#pragma unroll
+    for (int k = 0; k < NB; ++k) l[k] = (k < n && k < il) ? L_[ri * ld + k] : T(0);
+    static_for<0, NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        int nj = n;
+        asm volatile("" : "+s"(nj));
+        if (__builtin_expect(j < nj, 1)) v -= l[j] * (lane_read(v, j) * lane_read(rd, j));
+    });
+    v *= rd;
+    // backward L^T x = y: v_i <- v_i - L_ji x_j, x_j = v_j / L_jj
+#pragma unroll
+    for (int k = 0; k < NB; ++k) l[k] = (k < n && k > il) ? L_[k * ld + min(il, k)] : T(0);
+    static_for<0, NB>([&](auto jc) {
+        constexpr int j = NB - 1 - decltype(jc)::value;
+        int nj = n;
+        asm volatile("" : "+s"(nj));
+        if (j < nj) v -= l[j] * (lane_read(v, j) * lane_read(rd, j));
+    });
+    v *= rd;
+    if (il < n) x[il] = v;
+    __syncthreads();
+}
+
+// Dispatch on n (<= 16, <= 32).  Every pointer points into the dynamic LDS;
+// rebuilt from its offset so that the accesses are LDS ones.
+template <typename T>
+__device__ inline bool wave_cholesky(T *H, T *diag, int n, int ld) {
+    H = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(H)));
+    diag = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(diag)));
+    return n <= 16 ? wave_cholesky_regs<16, T>(H, diag, n, ld) : wave_cholesky_regs<32, T>(H, diag, n, ld);
+}
+template <typename T>
+__device__ inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T *x, int n, int ld) {
+    L_ = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(L_)));
+    diag = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(diag)));
+    b = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(b)));
+    x = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(x)));
+    if (n <= 16) wave_chol_solve_regs<16, T>(L_, diag, b, x, n, ld);
+    else wave_chol_solve_regs<32, T>(L_, diag, b, x, n, ld);
+}
+
 // Pointer forms for the callers (all arguments point into the dynamic LDS).
+// A one-wave team (NT = 64, n <= 32) factors and solves in registers; larger
+// teams take the blocked forms.
 template <int NT, typename T>
 __device__ inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
-    return team_cholesky_lds<NT, T>(lds_off(H), lds_off(diag), n, ld, lds_off(work));
+    if constexpr (NT == 64) {
+        (void)work;
+        return wave_cholesky(H, diag, n, ld);
+    } else {
+        return team_cholesky_lds<NT, T>(lds_off(H), lds_off(diag), n, ld, lds_off(work));
+    }
 }
 template <int NT, typename T>
 __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
-    team_chol_solve_lds<NT, T>(lds_off(L), lds_off(diag), lds_off(b), lds_off(x), n, ld);
+    if constexpr (NT == 64) wave_chol_solve(L, diag, b, x, n, ld);
+    else team_chol_solve_lds<NT, T>(lds_off(L), lds_off(diag), lds_off(b), lds_off(x), n, ld);
 }
 template <int NT, typename T>
 __device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
