@@ -614,8 +614,9 @@ __device__ inline float wave_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 // broadcast), so column j costs one reciprocal square root and one FMA per
 // trailing column in every lane, with no LDS traffic and no barrier.  Writes
 // L strictly below the diagonal of H and L_jj to diag[j], the layout of the
-// blocked factor.  Returns false (wave-uniform) when a pivot is not positive
-// (the remaining columns then take pivot 1 and the factor is not used).
+// blocked factor (the diagonal and upper triangle of H take other values).
+// Returns false (wave-uniform) when a pivot is not positive (the remaining
+// columns then take pivot 1 and the factor is not used).
 template <int NB, typename T>
 __device__ __attribute__((always_inline)) inline bool wave_cholesky_regs(T *H, T *diag, int n, int ld) {
     n = __builtin_amdgcn_readfirstlane(n);
@@ -623,8 +624,13 @@ __device__ __attribute__((always_inline)) inline bool wave_cholesky_regs(T *H, T
     const int il = opaque_lane((int)threadIdx.x & 63);
     const T *hr = H + min(il, n - 1) * ld;
     T h[NB];
+    // unconditional loads at clamped (in-bounds) columns, then selects: no
+    // branch between the loads, so they issue back to back
 #pragma unroll
-    for (int k = 0; k < NB; ++k) h[k] = k < n ? hr[k] : T(0);
+    for (int k = 0; k < NB; ++k) {
+        const T t = hr[min(k, n - 1)];
+        h[k] = k < n ? t : T(0);
+    }
     bool ok = true;
     static_for<0, NB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
@@ -638,26 +644,37 @@ __device__ __attribute__((always_inline)) inline bool wave_cholesky_regs(T *H, T
             ok = ok && d > T(0);
             h[j] *= wave_rsq(ok ? d : T(1));   // lane j: sqrt(d); lanes below: L_ij
             // trailing columns in groups of four (entries of columns >= n are
-            // never read: they may take updates)
+            // never read: they may take updates); the four lane reads of a
+            // group go to distinct scalar registers before its FMAs, so they
+            // issue back to back
             static_for<0, (NB - j + 2) / 4>([&](auto cc) {
                 constexpr int k0 = j + 1 + 4 * decltype(cc)::value;
                 if (__builtin_expect(k0 < nj, 1)) {
-                    static_for<k0, (k0 + 4 < NB ? k0 + 4 : NB)>([&](auto kc) {
-                        constexpr int k = decltype(kc)::value;
-                        h[k] -= h[j] * lane_read(h[j], k);
+                    T c[4];
+                    static_for<0, 4>([&](auto kc) {
+                        constexpr int k = k0 + decltype(kc)::value;
+                        c[decltype(kc)::value] = k < NB ? lane_read(h[j], k) : T(0);
+                    });
+                    asm volatile("" ::"s"(c[0]), "s"(c[1]), "s"(c[2]), "s"(c[3]));
+                    static_for<0, 4>([&](auto kc) {
+                        constexpr int k = k0 + decltype(kc)::value;
+                        if constexpr (k < NB) h[k] -= h[j] * c[decltype(kc)::value];
                     });
                 }
             });
         }
     });
+    // whole rows (one exec mask for the lanes of rows < n): entries on and
+    // above the diagonal of H are free storage afterwards (readers take L
+    // strictly below it and L_jj from diag)
+    T dl = h[0];
+#pragma unroll
+    for (int k = 1; k < NB; ++k) dl = k == il ? h[k] : dl;
     if (il < n) {
         T *row = H + il * ld;
-        T dl = h[0];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (k < n && k < il) row[k] = h[k];
-            dl = k == il ? h[k] : dl;
-        }
+        for (int k = 0; k < NB; ++k)
+            if (k < n) row[k] = h[k];
         diag[il] = dl;
     }
     __syncthreads();
