@@ -743,7 +743,9 @@ __device__ inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T
 
 // Pointer forms for the callers (all arguments point into the dynamic LDS).
 // A one-wave team (NT = 64, n <= 32) factors and solves in registers; larger
-// teams take the blocked forms.
+// teams take the blocked forms (a one-wave register solve for them measured
+// faster alone but not inside the larger kernels, whose hot code it pushes
+// past the instruction cache).
 template <int NT, typename T>
 __device__ inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
     if constexpr (NT == 64) {
