@@ -217,12 +217,24 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
         // half-waves taking alternate rows
         auto jt_rows = [&](int cnt, const T *x, int j) {
             const int half = tid >> 5;
-            T s = T(0);
-            if (j < n)
-                for (int c = half; c < cnt; c += 2) {
-                    const int i = list[c];
-                    s += Js[i * ldj + j] * x[i];
+            T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+            if (j < n) {
+                // four rows per round with their own sums: their list and
+                // row loads are in flight together
+                int c = half;
+                for (; c + 6 < cnt; c += 8) {
+                    const int i0 = list[c], i1 = list[c + 2], i2 = list[c + 4], i3 = list[c + 6];
+                    s0 += Js[i0 * ldj + j] * x[i0];
+                    s1 += Js[i1 * ldj + j] * x[i1];
+                    s2 += Js[i2 * ldj + j] * x[i2];
+                    s3 += Js[i3 * ldj + j] * x[i3];
                 }
+                for (; c < cnt; c += 2) {
+                    const int i = list[c];
+                    s0 += Js[i * ldj + j] * x[i];
+                }
+            }
+            const T s = (s0 + s1) + (s2 + s3);
             return s + __shfl_xor(s, 32, 64);
         };
 
@@ -266,7 +278,9 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                     const bool same = !__syncthreads_or(changed) && k > 0;
                     const int cnt = make_list();
                     __syncthreads();
-                    // F = M (a - a0) + J^T (D o A o r)
+                    // F = M (a - a0) + J^T (D o A o r); ||F||^2 and ||a||_inf by
+                    // wave reductions of the lanes' entries
+                    T fj = T(0), aj = T(0);
                     {
                         const int j = tid & 31;
                         const T s = jt_rows(cnt, q, j);
@@ -274,15 +288,14 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                             T md = T(0);
                             for (int l = 0; l < n; ++l) md += Ms[j * n + l] * (a[l] - a0[l]);
                             u[j] = md;
-                            F[j] = md + s;
+                            fj = md + s;
+                            F[j] = fj;
+                            aj = fabs(a[j]);
                         }
                     }
+                    const T g2 = wave_sum(fj * fj);
+                    const T anorm = wave_max(aj);
                     __syncthreads();
-                    T g2 = T(0), anorm = T(0);
-                    for (int j = 0; j < n; ++j) {
-                        g2 += F[j] * F[j];
-                        anorm = fmax(anorm, fabs(a[j]));
-                    }
                     // Newton matrix (kept while the active set is unchanged)
                     if (!same) {
                         assemble(cnt);
@@ -303,24 +316,23 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                         for (int j = 0; j < n; ++j) s += Js[i * ldj + j] * p[j];
                         q[i] = s;
                     }
-                    for (int j = tid; j < n; j += NT) {
+                    // c0 = p^T M p, b0 = p^T M (a - a0) by wave reductions
+                    T pm = T(0), pu = T(0);
+                    if (tid < n) {
                         T s = T(0);
-                        for (int l = 0; l < n; ++l) s += Ms[j * n + l] * p[l];
-                        Mp[j] = s;
+                        for (int l = 0; l < n; ++l) s += Ms[tid * n + l] * p[l];
+                        Mp[tid] = s;
+                        pm = p[tid] * s;
+                        pu = p[tid] * u[tid];
                     }
+                    const T c0 = wave_sum(pm), b0 = wave_sum(pu);
                     __syncthreads();
-                    T c0 = T(0), b0 = T(0);
-                    for (int j = 0; j < n; ++j) {
-                        c0 += p[j] * Mp[j];
-                        b0 += p[j] * u[j];
-                    }
                     uint32_t bits;
                     T cpiece;
                     int fl;
                     const T alpha = team_line_search<NT>(m, r, q, Dv, c0, b0, red, bits, cpiece, fl);
                     lsfail |= fl;
-                    step_inf = T(0);
-                    for (int j = 0; j < n; ++j) step_inf = fmax(step_inf, fabs(alpha * p[j]));
+                    step_inf = wave_max(tid < n ? fabs(alpha * p[tid]) : T(0));
                     __syncthreads();
                     for (int j = tid; j < n; j += NT) a[j] += alpha * p[j];
                     __syncthreads();
