@@ -322,6 +322,7 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                 const int cnt = el_list(X);
                 __syncthreads();
                 // F = M (a - a0) + J^T w over the listed contacts' rows
+                double fj = 0.0, aj = 0.0;
                 {
                     const int j = tid & 31, half = tid >> 5;
                     double s = 0.0;
@@ -336,15 +337,15 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                         double d = 0.0;
                         for (int l = 0; l < n; ++l) d += X.Ms[j * n + l] * (a[l] - a0[l]);
                         md[j] = d;
-                        F[j] = d + s;
+                        fj = d + s;
+                        F[j] = fj;
+                        aj = fabs(a[j]);
                     }
                 }
+                // ||F||^2 and ||a||_inf by wave reductions of the lanes' entries
+                const double g2 = wave_sum(fj * fj);
+                const double anorm = wave_max(aj);
                 __syncthreads();
-                double g2 = 0.0, anorm = 0.0;
-                for (int j = 0; j < n; ++j) {
-                    g2 += F[j] * F[j];
-                    anorm = fmax(anorm, fabs(a[j]));
-                }
                 if (!same) {   // H depends on the zones' blocks: rebuild unless unchanged
                     el_assemble(X, cnt);
                     if (!team_cholesky<EL_NT>(X.H, X.dh, n, n, X.wk)) { st = ST_NOTSPD; break; }
@@ -372,17 +373,17 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                     for (int j = 0; j < n; ++j) s += double(X.Js[i * ldj + j]) * p[j];
                     q[i] = s;
                 }
-                for (int j = tid; j < n; j += EL_NT) {
+                // c0 = p^T M p, b0 = p^T M (a - a0) by wave reductions
+                double pm = 0.0, pu = 0.0;
+                if (tid < n) {
                     double s = 0.0;
-                    for (int l = 0; l < n; ++l) s += X.Ms[j * n + l] * p[l];
-                    Mp[j] = s;
+                    for (int l = 0; l < n; ++l) s += X.Ms[tid * n + l] * p[l];
+                    Mp[tid] = s;
+                    pm = p[tid] * s;
+                    pu = p[tid] * md[tid];
                 }
+                const double c0 = wave_sum(pm), b0 = wave_sum(pu);
                 __syncthreads();
-                double c0 = 0.0, b0 = 0.0;
-                for (int j = 0; j < n; ++j) {
-                    c0 += p[j] * Mp[j];
-                    b0 += p[j] * md[j];
-                }
                 // exact line search: the root of phi' (the rule of the oracle's
                 // line search): Newton steps while no upper end is known, then
                 // Newton steps inside the bracket that at least halve the step
@@ -442,8 +443,7 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                     al = nx;
                 }
                 lsfail |= fl;
-                step_inf = 0.0;
-                for (int j = 0; j < n; ++j) step_inf = fmax(step_inf, fabs(best * p[j]));
+                step_inf = wave_max(tid < n ? fabs(best * p[tid]) : 0.0);
                 __syncthreads();
                 for (int j = tid; j < n; j += EL_NT) a[j] += best * p[j];
                 __syncthreads();

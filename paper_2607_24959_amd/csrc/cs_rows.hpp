@@ -243,6 +243,7 @@ __global__ __launch_bounds__(RW_NT) void k_forward_rows(BatchView bv, int count,
                 const int cq = rw_list(X, X.list, [](uint8_t z) { return z == 1; });
                 const int cf = rw_list(X, X.list2, [](uint8_t z) { return z != 0; });
                 __syncthreads();
+                double fj = 0.0, aj = 0.0;
                 {
                     const int j = tid & 31;
                     const double s = rw_jt(X, X.list2, cf, X.w, j);
@@ -250,15 +251,15 @@ __global__ __launch_bounds__(RW_NT) void k_forward_rows(BatchView bv, int count,
                         double d = 0.0;
                         for (int l = 0; l < n; ++l) d += X.Ms[j * n + l] * (a[l] - a0[l]);
                         md[j] = d;
-                        F[j] = d + s;
+                        fj = d + s;
+                        F[j] = fj;
+                        aj = fabs(a[j]);
                     }
                 }
+                // ||F||^2 and ||a||_inf by wave reductions of the lanes' entries
+                const double g2 = wave_sum(fj * fj);
+                const double anorm = wave_max(aj);
                 __syncthreads();
-                double g2 = 0.0, anorm = 0.0;
-                for (int j = 0; j < n; ++j) {
-                    g2 += F[j] * F[j];
-                    anorm = fmax(anorm, fabs(a[j]));
-                }
                 if (!same) {   // H depends on the zone-1 rows only
                     rw_assemble(X, cq);
                     if (!team_cholesky<RW_NT>(X.H, X.dh, n, n, X.wk)) { st = ST_NOTSPD; break; }
@@ -277,17 +278,17 @@ __global__ __launch_bounds__(RW_NT) void k_forward_rows(BatchView bv, int count,
                     for (int j = 0; j < n; ++j) s += double(X.Js[i * ldj + j]) * p[j];
                     X.q[i] = s;
                 }
-                for (int j = tid; j < n; j += RW_NT) {
+                // c0 = p^T M p, b0 = p^T M (a - a0) by wave reductions
+                double pm = 0.0, pu = 0.0;
+                if (tid < n) {
                     double s = 0.0;
-                    for (int l = 0; l < n; ++l) s += X.Ms[j * n + l] * p[l];
-                    Mp[j] = s;
+                    for (int l = 0; l < n; ++l) s += X.Ms[tid * n + l] * p[l];
+                    Mp[tid] = s;
+                    pm = p[tid] * s;
+                    pu = p[tid] * md[tid];
                 }
+                const double c0 = wave_sum(pm), b0 = wave_sum(pu);
                 __syncthreads();
-                double c0 = 0.0, b0 = 0.0;
-                for (int j = 0; j < n; ++j) {
-                    c0 += p[j] * Mp[j];
-                    b0 += p[j] * md[j];
-                }
                 // exact line search (eq. 10): phi' = c t + b on the piece of
                 // trial t; a Newton point -b/c is accepted when its own piece
                 // sums come out the same (equal zone sets give bitwise equal
@@ -335,8 +336,7 @@ __global__ __launch_bounds__(RW_NT) void k_forward_rows(BatchView bv, int count,
                     if (newton && same_piece) { fl = 0; break; }
                 }
                 lsfail |= fl;
-                step_inf = 0.0;
-                for (int j = 0; j < n; ++j) step_inf = fmax(step_inf, fabs(t * p[j]));
+                step_inf = wave_max(tid < n ? fabs(t * p[tid]) : 0.0);
                 __syncthreads();
                 for (int j = tid; j < n; j += RW_NT) a[j] += t * p[j];
                 __syncthreads();
