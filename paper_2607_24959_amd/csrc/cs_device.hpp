@@ -726,13 +726,13 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve_regs(const
 // Dispatch on n (<= 16, <= 32).  Every pointer points into the dynamic LDS;
 // rebuilt from its offset so that the accesses are LDS ones.
 template <typename T>
-__device__ inline bool wave_cholesky(T *H, T *diag, int n, int ld) {
+__device__ __attribute__((always_inline)) inline bool wave_cholesky(T *H, T *diag, int n, int ld) {
     H = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(H)));
     diag = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(diag)));
     return n <= 16 ? wave_cholesky_regs<16, T>(H, diag, n, ld) : wave_cholesky_regs<32, T>(H, diag, n, ld);
 }
 template <typename T>
-__device__ inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T *x, int n, int ld) {
+__device__ __attribute__((always_inline)) inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T *x, int n, int ld) {
     L_ = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(L_)));
     diag = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(diag)));
     b = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(b)));
@@ -747,7 +747,7 @@ __device__ inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T
 // faster alone but not inside the larger kernels, whose hot code it pushes
 // past the instruction cache).
 template <int NT, typename T>
-__device__ inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
+__device__ __attribute__((always_inline)) inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
     if constexpr (NT == 64) {
         (void)work;
         return wave_cholesky(H, diag, n, ld);
@@ -756,12 +756,12 @@ __device__ inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
     }
 }
 template <int NT, typename T>
-__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
+__device__ __attribute__((always_inline)) inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n, int ld) {
     if constexpr (NT == 64) wave_chol_solve(L, diag, b, x, n, ld);
     else team_chol_solve_lds<NT, T>(lds_off(L), lds_off(diag), lds_off(b), lds_off(x), n, ld);
 }
 template <int NT, typename T>
-__device__ inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
+__device__ __attribute__((always_inline)) inline void team_chol_solve(const T *L, const T *diag, T *b, T *x, int n) {
     team_chol_solve<NT>(L, diag, b, x, n, n);
 }
 
