@@ -743,9 +743,8 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve(const T *L
 
 // Pointer forms for the callers (all arguments point into the dynamic LDS).
 // A one-wave team (NT = 64, n <= 32) factors and solves in registers; larger
-// teams take the blocked forms (a one-wave register solve for them measured
-// faster alone but not inside the larger kernels, whose hot code it pushes
-// past the instruction cache).
+// teams take the blocked forms (a one-wave register solve for them, two rows
+// per lane, was faster alone for n <= 64 but not inside the chunked forward).
 template <int NT, typename T>
 __device__ __attribute__((always_inline)) inline bool team_cholesky(T *H, T *diag, int n, int ld, T *work) {
     if constexpr (NT == 64) {
