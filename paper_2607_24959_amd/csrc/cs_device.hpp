@@ -723,13 +723,15 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve_regs(const
     __syncthreads();
 }
 
-// Dispatch on n (<= 16, <= 32).  Every pointer points into the dynamic LDS;
+// Dispatch on n (<= 16, <= 24, <= 32).  Every pointer points into the dynamic LDS;
 // rebuilt from its offset so that the accesses are LDS ones.
 template <typename T>
 __device__ __attribute__((always_inline)) inline bool wave_cholesky(T *H, T *diag, int n, int ld) {
     H = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(H)));
     diag = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(diag)));
-    return n <= 16 ? wave_cholesky_regs<16, T>(H, diag, n, ld) : wave_cholesky_regs<32, T>(H, diag, n, ld);
+    if (n <= 16) return wave_cholesky_regs<16, T>(H, diag, n, ld);
+    if (n <= 24) return wave_cholesky_regs<24, T>(H, diag, n, ld);
+    return wave_cholesky_regs<32, T>(H, diag, n, ld);
 }
 template <typename T>
 __device__ __attribute__((always_inline)) inline void wave_chol_solve(const T *L_, const T *diag, const T *b, T *x, int n, int ld) {
@@ -738,6 +740,7 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve(const T *L
     b = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(b)));
     x = lds_at<T>(__builtin_amdgcn_readfirstlane(lds_off(x)));
     if (n <= 16) wave_chol_solve_regs<16, T>(L_, diag, b, x, n, ld);
+    else if (n <= 24) wave_chol_solve_regs<24, T>(L_, diag, b, x, n, ld);
     else wave_chol_solve_regs<32, T>(L_, diag, b, x, n, ld);
 }
 
