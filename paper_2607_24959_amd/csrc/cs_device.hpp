@@ -780,10 +780,83 @@ __device__ __attribute__((always_inline)) inline void team_chol_solve(const T *L
 // threads as i = tid + NT * jj (jj < 32, so m <= 32 NT).
 // Returns alpha; bits_out gets this thread's rows of the accepted piece,
 // c_out that piece's slope.  fail is set when the safeguard cap was hit.
+// The same search for a one-wave team with m <= 256 rows: each lane's (up to)
+// four rows are read once and kept in registers with D q^2 and D q r
+// precomputed, each trial's piece sums are two wave reductions, and the
+// unchanged-piece test is a ballot.  Every lane adds its rows in the same
+// order as the general form, so the sums, and the result, are bitwise the
+// same.
+template <typename T>
+__device__ inline T wave_line_search(int m, const T *r, const T *q, const T *D, T c0, T b0,
+                                     uint32_t &bits_out, T &c_out, int &fail) {
+    constexpr int RPL = 4;
+    const int tid = threadIdx.x & 63;
+    T rr[RPL], qq[RPL], dqq[RPL], dqr[RPL];
+#pragma unroll
+    for (int jj = 0; jj < RPL; ++jj) {
+        const int i = tid + 64 * jj, ic = min(i, m - 1);
+        const bool in = i < m;
+        // rows past m: q = 0 and r = 1 keep them off every piece
+        const T qi = in ? q[ic] : T(0), ri = in ? r[ic] : T(1), dq = in ? D[ic] * qi : T(0);
+        rr[jj] = ri;
+        qq[jj] = qi;
+        dqq[jj] = dq * qi;
+        dqr[jj] = dq * ri;
+    }
+    auto piece = [&](T t, uint32_t &bb, T &sc, T &sb) {
+        sc = T(0);
+        sb = T(0);
+        bb = 0;
+#pragma unroll
+        for (int jj = 0; jj < RPL; ++jj) {
+            const bool pa = rr[jj] + t * qq[jj] < T(0);
+            sc += pa ? dqq[jj] : T(0);
+            sb += pa ? dqr[jj] : T(0);
+            bb |= (pa ? 1u : 0u) << jj;
+        }
+        sc = wave_sum(sc);
+        sb = wave_sum(sb);
+    };
+    T t = T(1), c, b;
+    uint32_t bits;
+    piece(t, bits, c, b);
+    c += c0;
+    b += b0;
+    T lo = T(0), hi = inf_val<T>();
+    T alpha = t;
+    fail = 1;
+    const T eps = T(sizeof(T) == 4 ? 1.1920929e-7 : 2.220446049250313e-16);
+    for (int it = 0; it < 96; ++it) {
+        const T g = c * t + b;
+        if (g == T(0)) { alpha = t; fail = 0; break; }
+        if (g < T(0)) lo = t; else hi = t;
+        if (hi < inf_val<T>() && hi - lo <= T(32) * eps * hi) { alpha = t; fail = 0; break; }
+        T cand = -b / c;
+        const bool newton = (cand > lo) && (cand < hi);
+        if (!newton) cand = (hi < inf_val<T>()) ? T(0.5) * (lo + hi) : T(2) * lo + T(1);
+        uint32_t nb;
+        T sc, sb;
+        piece(cand, nb, sc, sb);
+        const bool same = __builtin_amdgcn_ballot_w64(nb != bits) == 0;
+        bits = nb;
+        c = c0 + sc;
+        b = b0 + sb;
+        t = cand;
+        alpha = cand;
+        if (newton && same) { fail = 0; break; }
+    }
+    bits_out = bits;
+    c_out = c;
+    return alpha;
+}
+
 template <int NT, typename T>
 __device__ inline T team_line_search(int m, const T *r, const T *q, const T *D, T c0, T b0,
                                      T *sred, uint32_t &bits_out, T &c_out, int &fail) {
     const int tid = threadIdx.x;
+    if constexpr (NT == 64) {
+        if (m <= 256) return wave_line_search(m, r, q, D, c0, b0, bits_out, c_out, fail);
+    }
     T t = T(1);
     uint32_t bits = 0;
     T c, b;
