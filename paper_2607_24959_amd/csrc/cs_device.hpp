@@ -794,10 +794,14 @@ __device__ inline T wave_line_search(int m, const T *r, const T *q, const T *D, 
     T rr[RPL], qq[RPL], dqq[RPL], dqr[RPL];
 #pragma unroll
     for (int jj = 0; jj < RPL; ++jj) {
-        const int i = tid + 64 * jj, ic = min(i, m - 1);
-        const bool in = i < m;
-        // rows past m: q = 0 and r = 1 keep them off every piece
-        const T qi = in ? q[ic] : T(0), ri = in ? r[ic] : T(1), dq = in ? D[ic] * qi : T(0);
+        const int i = tid + 64 * jj;
+        // rows past m (m may be 0): q = 0 and r = 1 keep them off every piece
+        T qi = T(0), ri = T(1), dq = T(0);
+        if (i < m) {
+            qi = q[i];
+            ri = r[i];
+            dq = D[i] * qi;
+        }
         rr[jj] = ri;
         qq[jj] = qi;
         dqq[jj] = dq * qi;
