@@ -260,15 +260,22 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                 for (int j = tid; j < n; j += NT) a[j] = a0[j];
                 __syncthreads();
                 int st = 0, k, lsfail = 0;
-                T step_inf = T(-1);
+                T step_inf = T(-1), alpha_prev = T(0);
                 for (k = 0;; ++k) {
-                    // residual and active set (eq. 6)
+                    // residual and active set (eq. 6); after the first step
+                    // r = J a - aref is carried, r <- r + alpha J p, with the
+                    // previous step's q = J p
                     bool changed = false;
                     for (int i = tid; i < m; i += NT) {
-                        T s = T(0);
+                        T ri;
+                        if (k == 0) {
+                            T s = T(0);
 #pragma unroll 8
-                        for (int j = 0; j < n; ++j) s += Js[i * ldj + j] * a[j];
-                        const T ri = s - ar[i];
+                            for (int j = 0; j < n; ++j) s += Js[i * ldj + j] * a[j];
+                            ri = s - ar[i];
+                        } else {
+                            ri = r[i] + alpha_prev * q[i];
+                        }
                         r[i] = ri;
                         q[i] = Dv[i] * ri;   // w before the line search needs q
                         const uint8_t an = ri < T(0);
@@ -285,8 +292,13 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                         const int j = tid & 31;
                         const T s = jt_rows(cnt, q, j);
                         if (tid < 32 && j < n) {
-                            T md = T(0);
-                            for (int l = 0; l < n; ++l) md += Ms[j * n + l] * (a[l] - a0[l]);
+                            // u = M (a - a0): formed at the first step, then
+                            // carried, u <- u + alpha M p
+                            T md = u[j];
+                            if (k == 0) {
+                                md = T(0);
+                                for (int l = 0; l < n; ++l) md += Ms[j * n + l] * (a[l] - a0[l]);
+                            }
                             u[j] = md;
                             fj = md + s;
                             F[j] = fj;
@@ -334,7 +346,11 @@ __global__ __launch_bounds__(RO_NT) void k_rollout(BatchView bv, int count, int 
                     lsfail |= fl;
                     step_inf = wave_max(tid < n ? fabs(alpha * p[tid]) : T(0));
                     __syncthreads();
-                    for (int j = tid; j < n; j += NT) a[j] += alpha * p[j];
+                    for (int j = tid; j < n; j += NT) {
+                        a[j] += alpha * p[j];
+                        u[j] += alpha * Mp[j];
+                    }
+                    alpha_prev = alpha;
                     __syncthreads();
                 }
                 if (lsfail) st |= ST_LSFAIL;
