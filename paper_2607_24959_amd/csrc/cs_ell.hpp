@@ -295,14 +295,20 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
         if (st == 0) {
             double trM = 0.0;
             for (int j = 0; j < n; ++j) trM += X.Ms[j * n + j];
-            double step_inf = -1.0;
+            double step_inf = -1.0, step_prev = 0.0;
             int lsfail = 0;
             for (k = 0;; ++k) {
-                // u = J a - aref; per contact: zone, w, G
+                // u = J a - aref (formed at the first step, then carried,
+                // u <- u + t J p with the previous step's q = J p); per
+                // contact: zone, w, G
                 for (int i = tid; i < m; i += EL_NT) {
-                    double s = 0.0;
-                    for (int j = 0; j < n; ++j) s += double(X.Js[i * ldj + j]) * a[j];
-                    u[i] = s - ar[i];
+                    if (k == 0) {
+                        double s = 0.0;
+                        for (int j = 0; j < n; ++j) s += double(X.Js[i * ldj + j]) * a[j];
+                        u[i] = s - ar[i];
+                    } else {
+                        u[i] += step_prev * q[i];
+                    }
                 }
                 __syncthreads();
                 bool changed = false;
@@ -334,8 +340,12 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                         }
                     s += __shfl_xor(s, 32, 64);
                     if (tid < 32 && j < n) {
-                        double d = 0.0;
-                        for (int l = 0; l < n; ++l) d += X.Ms[j * n + l] * (a[l] - a0[l]);
+                        // M (a - a0): formed at the first step, then carried
+                        double d = md[j];
+                        if (k == 0) {
+                            d = 0.0;
+                            for (int l = 0; l < n; ++l) d += X.Ms[j * n + l] * (a[l] - a0[l]);
+                        }
                         md[j] = d;
                         fj = d + s;
                         F[j] = fj;
@@ -445,7 +455,11 @@ __global__ __launch_bounds__(EL_NT) void k_forward_ell(BatchView bv, int count, 
                 lsfail |= fl;
                 step_inf = wave_max(tid < n ? fabs(best * p[tid]) : 0.0);
                 __syncthreads();
-                for (int j = tid; j < n; j += EL_NT) a[j] += best * p[j];
+                for (int j = tid; j < n; j += EL_NT) {
+                    a[j] += best * p[j];
+                    md[j] += best * Mp[j];
+                }
+                step_prev = best;
                 __syncthreads();
             }
             if (lsfail) st |= ST_LSFAIL;
