@@ -540,6 +540,7 @@ def rollout_line(B_=1024, n=18, nc=32, horizon=50, reps=5):
             "rollouts_per_s": B_ / (t_store / 1e3),
             "newton_steps_per_solve": float(o["iters"].double().mean().item()) / horizon,
             "converged_frac": float(((o["status"] & 1) != 0).double().mean().item()),
+            "lsfail_count": int(((o["status"] & 16) != 0).sum().item()),
             "max_rel_diff_vs_layered": e}
 
 
