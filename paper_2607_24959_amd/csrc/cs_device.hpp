@@ -313,68 +313,6 @@ __device__ inline void chol_trailing(double *H, int n, int ld, int c0, int c1) {
     }
 }
 
-// Panel of the blocked Cholesky: rows i in [c1, n) of the block columns
-// [c0, c0 + 16) become L_ij = sum_k H_ik X_jk with X = L_D^{-1} of the
-// factored diagonal block, given transposed in B (B[k * 17 + j] = X_jk).
-// FP32 on the matrix cores (16-row tiles over the waves; a wave reads its
-// tile before it writes it); FP64 on the VALU in rounds of MAXP entries per
-// thread, computed before any is written.  Ends with a team barrier.
-template <int NT>
-__device__ inline void chol_panel(float *H, int n, int ld, int c0, int c1, const float *B) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int nt = (n - c1 + 15) / 16;
-    for (int t = wave; t < nt; t += NT / 64) {
-        const int ra = c1 + 16 * t + li;
-        float a[4], b[4];   // all loads in flight together (see chol_trailing)
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lk;
-            a[ks] = H[min(ra, n - 1) * ld + c0 + k];
-            b[ks] = B[k * 17 + li];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(a[q]), "+v"(b[q]));
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ra < n ? a[ks] : 0.f, b[ks], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = c1 + 16 * t + 4 * lk + r;
-            if (row < n) H[row * ld + c0 + li] = acc[r];
-        }
-    }
-    __syncthreads();
-}
-
-template <int NT>
-__device__ inline void chol_panel(double *H, int n, int ld, int c0, int c1, const double *B) {
-    constexpr int MAXP = 8;
-    const int cnt = (n - c1) * 16;
-    for (int base = 0; base < cnt; base += NT * MAXP) {
-        double out[MAXP];
-#pragma unroll
-        for (int q = 0; q < MAXP; ++q) {
-            const int e = base + (int)threadIdx.x + q * NT;
-            double v = 0.0;
-            if (e < cnt) {
-                const int row = c1 + (e >> 4), j = e & 15;
-                const double *h = H + row * ld + c0;
-                for (int k = 0; k <= j; ++k) v += h[k] * B[k * 17 + j];
-            }
-            out[q] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < MAXP; ++q) {
-            const int e = base + (int)threadIdx.x + q * NT;
-            if (e < cnt) H[(c1 + (e >> 4)) * ld + c0 + (e & 15)] = out[q];
-        }
-        __syncthreads();
-    }
-}
-
 // The team routines below work on the launching kernel's dynamic LDS (every
 // caller carves its LDS from that one region) and are inlined into every
 // caller: no call boundary, so no callee addresses the kernel's dynamic LDS
@@ -390,9 +328,19 @@ template <typename T> __device__ inline int lds_off(const T *p) {
     return (int)(p - reinterpret_cast<const T *>(smem));
 }
 
-template <typename T> __device__ inline T chol_rsq(T x);
-template <> __device__ inline float chol_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ inline double chol_rsq<double>(double x) { return 1.0 / sqrt(x); }
+// 1 / sqrt(x) for a positive, normal pivot: the hardware estimate refined by
+// two Newton steps r <- r + r (1 - x r^2) / 2 in FP64 (quadratic convergence
+// from the estimate's ~2^-22 to rounding level); FP32 takes the estimate.
+__device__ inline double wave_rsq(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+__device__ inline float wave_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 template <typename T> __device__ inline T chol_rcp(T x);
 template <> __device__ inline float chol_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ inline double chol_rcp<double>(double x) { return 1.0 / x; }
@@ -410,12 +358,13 @@ __device__ inline int opaque_lane(int l) {
 // stride ld): the lower triangle is read, L is written strictly below the
 // diagonal and L_jj goes to diag[j].  Right-looking over 16-column blocks:
 // every wave factors the diagonal block in registers (one row per lane,
-// DPP row broadcasts) and forms its inverse X = L_D^{-1} (one column per
-// lane); wave 0 stores L_D and X^T (to work, 16 x 17 values).  The panel
-// below is H_panel X^T and the trailing lower triangle takes the block's
-// rank-16 update.  n <= 32 for NT = 64, n <= 128 for NT = 256.  The caller
-// has synchronised the team after writing H.  Returns false (team-uniform)
-// when a pivot is not positive.
+// DPP row broadcasts); wave 0 stores L_D and the 16 reciprocals 1 / L_jj (to
+// work).  Each panel row below the block is then a triangular solve
+// l_i L_D^T = h_i done by one thread in registers (L_D read from LDS as a
+// broadcast), and the trailing lower triangle takes the block's rank-16
+// update.  Odd row strides keep the panel rows of a wave in distinct LDS
+// banks.  n <= 128 for NT = 256.  The caller has synchronised the team after
+// writing H.  Returns false (team-uniform) when a pivot is not positive.
 template <int NT, typename T>
 __device__ __attribute__((always_inline)) inline bool team_cholesky_lds(int ho, int dgo, int n, int ld, int wko) {
     // sizes are team-uniform: keep them (and every branch on them) scalar
@@ -453,7 +402,7 @@ __device__ __attribute__((always_inline)) inline bool team_cholesky_lds(int ho, 
             static_for<0, 16>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
                 const T pv = row_bcast16<j>(d[j]);
-                d[j] *= chol_rsq((j < bs) ? pv : T(1));
+                d[j] *= wave_rsq((j < bs) ? pv : T(1));
                 static_for<j + 1, 16>([&](auto kc) {
                     constexpr int k = decltype(kc)::value;
                     d[k] -= d[j] * row_bcast16<k>(d[j]);
@@ -466,23 +415,6 @@ __device__ __attribute__((always_inline)) inline bool team_cholesky_lds(int ho, 
             // every wave holds the whole block: positive definiteness from a
             // ballot of the block's diagonal (NaN fails), no LDS round trip
             ok = ok && __builtin_amdgcn_ballot_w64(l < bs && !(dl > T(0))) == 0;
-            // column l of X = L_D^{-1}: x_c = (delta_cl - sum_{k<c} L_ck x_k) / L_cc,
-            // right-looking (each x_k feeds the sums of the later rows at
-            // once); entries above the diagonal come out zero by themselves.
-            // Only the last block has bs < 16, and it has no panel, so X's
-            // columns past bs are never used.
-            T x[16], acc[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) acc[c] = T(0);
-            static_for<0, 16>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                const T rk = chol_rcp(row_bcast16<k>(d[k]));
-                x[k] = ((k == lo ? T(1) : T(0)) - acc[k]) * rk;
-                static_for<k + 1, 16>([&](auto cc) {
-                    constexpr int c = decltype(cc)::value;
-                    acc[c] += row_bcast16<c>(d[k]) * x[k];
-                });
-            });
             // whole rows of the block (a team-uniform bound, no lane masks):
             // the block's upper triangle in H is free storage (readers take L
             // strictly below the diagonal and L_jj from diag)
@@ -492,15 +424,31 @@ __device__ __attribute__((always_inline)) inline bool team_cholesky_lds(int ho, 
                     if (k < bs) H[(c0 + l) * ld + c0 + k] = d[k];
                 diag[c0 + l] = dl;
             }
-            if (w0 && l < 16) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c) work[l * 17 + c] = x[c];
-            }
+            if (w0 && l < bs) work[l] = chol_rcp(dl);
         }
         __syncthreads();
         const int c1 = c0 + bs;
         if (c1 < n) {
-            chol_panel<NT>(H, n, ld, c0, c1, work);
+            // panel: row i solves l_i L_D^T = h_i, right-looking (each l_ik
+            // feeds the later entries of the row at once).  Only the last
+            // block has bs < 16, and it has no panel.
+            for (int i = c1 + (int)threadIdx.x; i < n; i += NT) {
+                T h[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) h[k] = H[i * ld + c0 + k];
+                static_for<0, 16>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    const T lk = h[k] * work[k];
+                    h[k] = lk;
+                    static_for<k + 1, 16>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        h[j] -= lk * H[(c0 + j) * ld + c0 + k];
+                    });
+                });
+#pragma unroll
+                for (int k = 0; k < 16; ++k) H[i * ld + c0 + k] = h[k];
+            }
+            __syncthreads();
             chol_trailing<NT>(H, n, ld, c0, c1);
             __syncthreads();
         }
@@ -593,19 +541,6 @@ __device__ __attribute__((always_inline)) inline void team_chol_solve_lds(int lo
         }
     }
 }
-// 1 / sqrt(x) for a positive, normal pivot: the hardware estimate refined by
-// two Newton steps r <- r + r (1 - x r^2) / 2 in FP64 (quadratic convergence
-// from the estimate's ~2^-22 to rounding level); FP32 takes the estimate.
-__device__ inline double wave_rsq(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-x * r, r, 1.0);
-        r = fma(0.5 * r, e, r);
-    }
-    return r;
-}
-__device__ inline float wave_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Cholesky H = L L^T for a one-wave team (n <= NB <= 64; NB a compile-time
 // bound): lane i holds row i of the lower triangle in registers (rows past n

@@ -20,8 +20,12 @@ struct GenLds {
     uint8_t *A, *Ap;
 };
 
+// Row stride of H in LDS: odd, so that rows handled by consecutive threads
+// sit in distinct LDS banks.
+__host__ __device__ inline int gen_ld(int n) { return n | 1; }
+
 __host__ __device__ inline size_t gen_lds_bytes(int nmax, int mmax, int NT, size_t s) {
-    size_t nT = (size_t)nmax * nmax + 11 * (size_t)nmax + 16 * (size_t)(NT / 64) + 16 * 17 +
+    size_t nT = (size_t)nmax * (nmax + 1) + 11 * (size_t)nmax + 16 * (size_t)(NT / 64) + 16 * 17 +
                 5 * (size_t)mmax;
     return nT * s + 2 * (size_t)mmax + 64;
 }
@@ -30,7 +34,7 @@ template <typename T>
 __device__ inline GenLds<T> gen_carve(unsigned char *smem, int nmax, int mmax, int NT) {
     GenLds<T> L;
     T *p = reinterpret_cast<T *>(smem);
-    L.H = p; p += (size_t)nmax * nmax;
+    L.H = p; p += (size_t)nmax * (nmax + 1);   // row stride gen_ld(n) <= nmax + 1
     L.diag = p; p += nmax;
     L.a = p; p += nmax;
     L.a0 = p; p += nmax;
@@ -102,7 +106,7 @@ __device__ inline void gen_hessian(int n, int m, const T *__restrict__ M, const 
         T h = M[(size_t)j * n + l];
         for (int i = 0; i < m; ++i)
             if (L.A[i]) h += L.Dv[i] * J[(size_t)i * n + j] * J[(size_t)i * n + l];
-        L.H[j * n + l] = h;
+        L.H[j * gen_ld(n) + l] = h;
     }
 }
 
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
             mark_bad(I, gstatus, giters, tid == 0);
             continue;
         }
-        const int n = I.n, m = I.m;
+        const int n = I.n, m = I.m, ldh = gen_ld(n);
         const T *M = gM + I.onn, *J = gJ + I.omn, *a0 = ga0 + I.on, *aref = garef + I.om,
                 *D = gD + I.om;
         bool bad = false;
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
         }
         for (int e = tid; e < n * n; e += NT) {
             const T x = M[e];
-            L.H[e] = x;
+            L.H[(e / n) * ldh + e % n] = x;
             bad |= !finite_val(x);
         }
         for (int e = tid; e < m * n; e += NT) bad |= !finite_val(J[e]);
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
         int st = 0, k = 0;
         if (anybad) {
             st = ST_NONFINITE;
-        } else if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) {
+        } else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.wk)) {
             st = ST_NOTSPD;
         }
         if (st == 0) {
@@ -176,8 +180,8 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
                 gen_hessian<NT>(n, m, M, J, L);
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) { st = ST_NOTSPD; break; }
-                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n);
+                if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.wk)) { st = ST_NOTSPD; break; }
+                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
                 // q = J p; M p and M (a - a0) for the line search coefficients
                 for (int i = tid; i < m; i += NT) {
                     const T *Ji = J + (size_t)i * n;
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
                 // factor of H at the returned iterate (A from its residual)
                 gen_hessian<NT>(n, m, M, J, L);
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) st = ST_NOTSPD;
+                if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.wk)) st = ST_NOTSPD;
             }
         }
         const bool ok = !(st & (ST_NONFINITE | ST_NOTSPD));
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_forward_generic(
         T *fac = gfac + fac_offset(I);
         for (int e = tid; e < n * n; e += NT) {
             const int j = e / n, l = e - (e / n) * n;
-            if (l < j) fac[j * (j + 1) / 2 + l] = ok ? L.H[e] : nanv;
+            if (l < j) fac[j * (j + 1) / 2 + l] = ok ? L.H[j * ldh + l] : nanv;
             else if (l == j) fac[j * (j + 1) / 2 + l] = ok ? L.diag[j] : nanv;
         }
         for (int i = tid; i < m; i += NT) gmask[I.om + i] = ok ? L.A[i] : 0;
@@ -255,12 +259,12 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
     for (int w = blockIdx.x; w < bv.B; w += gridDim.x) {
         const Inst I = inst_at(bv, w);
         if (!I.ok) continue;   // team-uniform: outputs untouched
-        const int n = I.n, m = I.m;
+        const int n = I.n, m = I.m, ldh = gen_ld(n);
         const T *M = gM + I.onn, *J = gJ + I.omn, *aref = garef + I.om, *D = gD + I.om;
         const T *fac = gfac + fac_offset(I);
         for (int e = tid; e < n * n; e += NT) {
             const int j = e / n, l = e - (e / n) * n;
-            if (l < j) L.H[e] = fac[j * (j + 1) / 2 + l];
+            if (l < j) L.H[j * ldh + l] = fac[j * (j + 1) / 2 + l];
             else if (l == j) L.diag[j] = fac[j * (j + 1) / 2 + l];
         }
         for (int j = tid; j < n; j += NT) {
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
         __syncthreads();
         // lambda = H^{-1} abar (H symmetric, so H^T lambda = abar is the same system),
         // then one step of iterative refinement with H v = M v + J^T (D o A* o J v)
-        team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n);
+        team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n, ldh);
         for (int i = tid; i < m; i += NT) {
             const T *Ji = J + (size_t)i * n;
             T s = T(0);
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_ift_vjp_generic(
             L.y[j] = s;
         }
         __syncthreads();
-        team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n);
+        team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
         for (int j = tid; j < n; j += NT) L.u[j] += L.p[j];
         __syncthreads();
         for (int i = tid; i < m; i += NT) {
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             if (mode != ST_REP) mark_bad(I, gstatus, giters, tid == 0);
             continue;
         }
-        const int n = I.n, m = I.m;
+        const int n = I.n, m = I.m, ldh = gen_ld(n);
         const T *M = gM + I.onn, *J = gJ + I.omn, *a0 = ga0 + I.on, *aref = garef + I.om,
                 *D = gD + I.om;
         T *a0bar = ga0bar + I.on, *arefbar = garefbar + I.om, *Jbar = gJbar + I.omn,
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
         }
         for (int e = tid; e < n * n; e += NT) {
             const T x = M[e];
-            L.H[e] = x;
+            L.H[(e / n) * ldh + e % n] = x;
             bad |= !finite_val(x);
         }
         for (int e = tid; e < m * n; e += NT) bad |= !finite_val(J[e]);
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             steps = giters[I.b];
         } else if (anybad) {
             st = ST_NONFINITE;
-        } else if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) {
+        } else if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.wk)) {
             st = ST_NOTSPD;
         }
 
@@ -424,8 +428,8 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 gen_hessian<NT>(n, m, M, J, L);
                 for (int j = tid; j < n; j += NT) L.y[j] = -L.F[j];
                 __syncthreads();
-                if (!team_cholesky<NT>(L.H, L.diag, n, n, L.wk)) { st = ST_NOTSPD; break; }
-                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n);
+                if (!team_cholesky<NT>(L.H, L.diag, n, ldh, L.wk)) { st = ST_NOTSPD; break; }
+                team_chol_solve<NT>(L.H, L.diag, L.y, L.p, n, ldh);
                 for (int i = tid; i < m; i += NT) {
                     const T *Ji = J + (size_t)i * n;
                     T s = T(0);
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
                 }
                 for (int e = tid; e < n * n; e += NT) {
                     const int j = e / n, l = e - (e / n) * n;
-                    if (l < j) rec[2 * n + j * (j + 1) / 2 + l] = L.H[e];
+                    if (l < j) rec[2 * n + j * (j + 1) / 2 + l] = L.H[j * ldh + l];
                     else if (l == j) rec[2 * n + j * (j + 1) / 2 + l] = L.diag[j];
                 }
                 for (int i = tid, jj = 0; i < m; i += NT, ++jj) {
@@ -525,7 +529,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             }
             for (int e = tid; e < n * n; e += NT) {
                 const int j = e / n, l = e - (e / n) * n;
-                if (l < j) L.H[e] = rec[2 * n + j * (j + 1) / 2 + l];
+                if (l < j) L.H[j * ldh + l] = rec[2 * n + j * (j + 1) / 2 + l];
                 else if (l == j) L.diag[j] = rec[2 * n + j * (j + 1) / 2 + l];
             }
             for (int i = tid; i < m; i += NT) {
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(NT) void k_unrolled_generic(
             }
             __syncthreads();
             // u = H^{-1} pbar ; gbar = -u
-            team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n);
+            team_chol_solve<NT>(L.H, L.diag, L.y, L.u, n, ldh);
             // rows: Ju; D-bar, r-bar updates; J-bar row coefficients
             for (int i = tid; i < m; i += NT) {
                 const T *Ji = J + (size_t)i * n;
