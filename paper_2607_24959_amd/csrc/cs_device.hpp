@@ -477,19 +477,16 @@ __device__ __attribute__((always_inline)) inline void team_chol_solve_lds(int lo
             const int l = threadIdx.x;
             const int lr = c0 + min(l, bs - 1);       // clamped row: loads stay in bounds
             T y = b[lr];
-            // the lane's row of the block and the diagonal reciprocals up
-            // front (clamped columns), then 16 unrolled steps; lanes past the
-            // block never store and only feed broadcasts read by such lanes
-            T lrow[16], rd[16];
+            // the lane's row of the block up front (clamped columns) and the
+            // reciprocal of its own pivot, then 16 unrolled steps; lanes past
+            // the block never store and only feed broadcasts read by such lanes
+            T lrow[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int cc = c0 + min(c, bs - 1);
-                lrow[c] = L[lr * ld + cc];
-                rd[c] = chol_rcp(diag[cc]);
-            }
+            for (int c = 0; c < 16; ++c) lrow[c] = L[lr * ld + c0 + min(c, bs - 1)];
+            const T rdl = chol_rcp(diag[lr]);
             static_for<0, 16>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
-                const T yc = row_bcast16<c>(y) * rd[c];   // y_c = (lane c's value) / L_cc
+                const T yc = row_bcast16<c>(y * rdl);   // y_c = (lane c's value) / L_cc
                 y = (l == c) ? yc : ((l > c) ? y - lrow[c] * yc : y);
             });
             if (l < bs) x[c0 + l] = y;
@@ -514,18 +511,15 @@ __device__ __attribute__((always_inline)) inline void team_chol_solve_lds(int lo
             const int l = threadIdx.x;
             const int lc = c0 + min(l, bs - 1);       // clamped column: loads stay in bounds
             T v = x[lc];
-            T lcol[16], rd[16];
+            T lcol[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int cc = c0 + min(c, bs - 1);
-                lcol[c] = L[cc * ld + lc];
-                rd[c] = chol_rcp(diag[cc]);
-            }
+            for (int c = 0; c < 16; ++c) lcol[c] = L[(c0 + min(c, bs - 1)) * ld + lc];
+            const T rdl = chol_rcp(diag[lc]);
             // columns past the block update nobody (c < bs), so the lanes of
             // the block see exactly the bs steps
             static_for<0, 16>([&](auto ic) {
                 constexpr int c = 15 - decltype(ic)::value;
-                const T xc = row_bcast16<c>(v) * rd[c];
+                const T xc = row_bcast16<c>(v * rdl);
                 v = (l == c) ? xc : ((l < c && c < bs) ? v - lcol[c] * xc : v);
             });
             if (l < bs) x[c0 + l] = v;
