@@ -635,7 +635,9 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve_regs(const
         constexpr int j = decltype(jc)::value;
         int nj = n;
         asm volatile("" : "+s"(nj));
-        if (__builtin_expect(j < nj, 1)) v -= l[j] * (lane_read(v, j) * lane_read(rd, j));
+        // y_j = v_j / L_jj, formed in lane j and read once (the same product as
+        // two lane reads multiplied)
+        if (__builtin_expect(j < nj, 1)) v -= l[j] * lane_read(v * rd, j);
     });
     v *= rd;
     // backward L^T x = y: v_i <- v_i - L_ji x_j, x_j = v_j / L_jj
@@ -645,7 +647,7 @@ __device__ __attribute__((always_inline)) inline void wave_chol_solve_regs(const
         constexpr int j = NB - 1 - decltype(jc)::value;
         int nj = n;
         asm volatile("" : "+s"(nj));
-        if (j < nj) v -= l[j] * (lane_read(v, j) * lane_read(rd, j));
+        if (j < nj) v -= l[j] * lane_read(v * rd, j);
     });
     v *= rd;
     if (il < n) x[il] = v;
